@@ -1,0 +1,178 @@
+#!/usr/bin/env python3
+"""Benchmark of the local block-sparse FP64 multiply on one MI355X.
+
+Workload (one step = one full bsmm_multiply, inputs resident in HBM):
+dense square product N = 8192 stored as a 256 x 256 grid of 32 x 32 blocks,
+every block present, values U[-1, 1], C = 1.0 * A * B + 0.0 * C.  The
+library densifies (merge into panels, one FP64 MFMA GEMM with the split back
+into blocks fused into its epilogue).  The same workload is also timed on
+the blocked path (stacks of 32^3 block products), the paper's
+T_blocked / T_densified comparison.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "FP64-equiv GFLOP/s of local C+=A·B, tuned/emulated vs plain, rel err≤1e-12"
+N, BS = 8192, 32
+PEAK_FP64_MFMA_TFLOPS = 78.6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def traffic_from_profile():
+    """HBM bytes per GEMM launch from the committed counter summary, valid
+    only while the GEMM source is unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", "dgemm_dense_square_8192_traffic.json")
+    src = os.path.join(ROOT, "paper_1910_04796_amd", "csrc", "dense.hip")
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if t.get("source_sha256") != sha:
+            return None
+        return t.get("bytes_per_launch")
+    except (OSError, ValueError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-blocked", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this benchmark runs on exactly one GPU (the local multiply of one rank); "
+              "--gpus N > 1 is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_04796_amd import bsmm
+    from synth import dense_square
+
+    torch.cuda.set_device(0)
+    bsmm.use_torch_allocator(0)
+    stream = torch.cuda.current_stream()
+    log("generating inputs")
+    A, B = dense_square(seed=0, n=N, bs=BS)
+    MA = bsmm.Matrix.from_blocks(A)
+    MB = bsmm.Matrix.from_blocks(B)
+    MC = bsmm.Matrix.empty(A.rbs, B.cbs)
+    F = 2.0 * N ** 3
+
+    bsmm.bsmm_set_option("path", "auto")
+    for _ in range(args.warmup):
+        bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream)
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+
+    bsmm.bsmm_set_option("time_kernels", "1")
+    bsmm.bsmm_kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gemm_ms, gemm_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
+    bsmm.bsmm_set_option("time_kernels", "0")
+    stats = bsmm.bsmm_last_stats()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = F / (ms_per_step * 1e-3) / 1e9
+    log(f"dense path: {ms_per_step:.3f} ms/step, {value:.1f} GFLOP/s, path={stats['path']}")
+
+    gemm_avg_ms = gemm_ms / max(gemm_n, 1)
+    achieved = F / (gemm_avg_ms * 1e-3) / 1e12
+    roofline = {"bound": "mfma", "kernel": "k_dgemm_mfma", "achieved": round(achieved, 3),
+                "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
+                "kernel_ms": round(gemm_avg_ms, 4), "launches": gemm_n,
+                "traffic": traffic_from_profile()}
+
+    blocked = None
+    if not args.no_blocked:
+        bsmm.bsmm_set_option("path", "stack")
+        MC2 = bsmm.Matrix.empty(A.rbs, B.cbs)
+        bsmm.multiply(1.0, MA, MB, 0.0, MC2, 0.0, stream)
+        torch.cuda.synchronize()
+        reps = 3
+        tb0 = time.perf_counter()
+        for _ in range(reps):
+            bsmm.multiply(1.0, MA, MB, 0.0, MC2, 0.0, stream)
+        torch.cuda.synchronize()
+        tb1 = time.perf_counter()
+        bsmm.bsmm_set_option("path", "auto")
+        bms = (tb1 - tb0) * 1e3 / reps
+        blocked = {"path": "stack (plain small-block kernels)", "ms_per_step": round(bms, 3),
+                   "gflops": round(F / (bms * 1e-3) / 1e9, 1),
+                   "t_blocked_over_t_densified": round(bms / ms_per_step, 3)}
+        log(f"blocked path: {bms:.3f} ms/step")
+        MC2.close()
+
+    cpu = None
+    rel_err = None
+    if not args.no_cpu_baseline:
+        # CPU baseline leg: the reference on a bounded sample of block rows,
+        # also used to check the GPU result on those rows.
+        from oracle import oracle as orc
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        X = MC.to_host()
+        sizes = orc.block_sizes(X.rbs, X.cbs, X.row_ptr, X.col_ind)
+        elem_start = np.concatenate([[0], np.cumsum(sizes)])
+        row_flops = 2.0 * BS * N * N  # one block row of C: 32 x 8192 x 8192
+        orc.multiply(1.0, A, B, 0.0, rows=(0, 1), nthreads=threads)  # warm-up
+        c0 = time.perf_counter()
+        orc.multiply(1.0, A, B, 0.0, rows=(1, 2), nthreads=threads)
+        t_row = time.perf_counter() - c0
+        nrows = int(max(1, min(N // BS - 17, 15.0 / max(t_row, 1e-3))))
+        r0 = 17
+        c0 = time.perf_counter()
+        R = orc.multiply(1.0, A, B, 0.0, rows=(r0, r0 + nrows), nthreads=threads)
+        t_cpu = time.perf_counter() - c0
+        e0 = int(elem_start[int(X.row_ptr[r0])])
+        e1 = int(elem_start[int(X.row_ptr[r0 + nrows])])
+        assert np.array_equal(X.col_ind[int(X.row_ptr[r0]):int(X.row_ptr[r0 + nrows])], R.col_ind)
+        rel_err = orc.rel_err(X.data[e0:e1], R.data)
+        cpu = {"value": round(row_flops * nrows / t_cpu / 1e9, 3), "unit": "GFLOP/s",
+               "cores": threads, "kind": "oracle",
+               "sample": f"block rows {r0}..{r0 + nrows - 1} of 256 ({nrows * 32} of {N} rows of C), "
+                         f"{t_cpu:.1f} s"}
+        log(f"cpu baseline: {cpu['value']} GFLOP/s on {threads} threads; rel_err {rel_err:.2e}")
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "dense_square_n8192_b32", "N": N, "block": BS, "occupancy": 1.0,
+                   "alpha": 1.0, "beta": 0.0, "path": "dense: merged panels + FP64 MFMA GEMM",
+                   "flops_per_step": F},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "rel_err": rel_err,
+        "blocked": blocked,
+    }
+    print(json.dumps(out), flush=True)
+    for M in (MA, MB, MC):
+        M.close()
+    bsmm.bsmm_set_allocator()
+
+
+if __name__ == "__main__":
+    main()

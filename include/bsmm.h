@@ -1,0 +1,206 @@
+/*
+ * bsmm.h -- block-sparse FP64 matrix multiply on one AMD MI355X (gfx950).
+ *
+ * One rank's local step of a distributed block-CSR multiplication:
+ *
+ *     C <- filter_eps( beta * C + alpha * A * B )
+ *
+ * Matrices are kept in blocked compressed-sparse-row form (paper, Sec. II:
+ * block-CSR storage; the local multiplication is a set of pairwise products
+ * of small dense blocks, an A block m x k times a B block k x n).  The
+ * library turns the block indices into stacks of block products grouped by
+ * block shape and runs them as batched small-block GEMMs on the GPU
+ * (Sec. II, Traversal / Generation / Scheduler phases); when both inputs are
+ * fully occupied it instead merges the blocks into contiguous panels and
+ * runs one large FP64 GEMM, then splits the result back into the original
+ * blocks (Sec. III, densification and undensification, Eqs. (1)-(2) with a
+ * single rank and a single panel).
+ *
+ * Conventions shared by every entry point
+ *  - Block sizes are >= 1.  A matrix has nbr block rows (sizes
+ *    row_blk_sizes[0..nbr)) and nbc block columns (col_blk_sizes[0..nbc)).
+ *  - blk_row_ptr is int64[nbr+1] with blk_row_ptr[0] = 0 and
+ *    blk_row_ptr[nbr] = nnzb, non-decreasing; blk_col_ind is int32[nnzb]
+ *    with column indices in [0, nbc), strictly ascending inside each row.
+ *  - Block data are FP64, packed in CSR order; every block is column-major
+ *    with leading dimension equal to its number of rows.
+ *  - "stream" is a hipStream_t (NULL = the legacy default stream).  All
+ *    device work is ordered on that stream.
+ *  - Every function returns a status code (below) and never throws across
+ *    the ABI.  Validation failures leave every argument untouched.  The
+ *    message of the last failure on the calling thread is returned by
+ *    bsmm_last_error().
+ *  - Handles are not thread-safe: a handle must not be used by two threads
+ *    at once.
+ */
+#ifndef BSMM_H
+#define BSMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bsmm_matrix_s *bsmm_matrix; /* opaque; owns its device memory */
+
+enum bsmm_status {
+    BSMM_OK = 0,
+    BSMM_EINVAL = -1,  /* null pointer, block size < 1, bad scalar, aliasing   */
+    BSMM_ESHAPE = -2,  /* block sizes of A, B, C do not conform                 */
+    BSMM_EINDEX = -3,  /* malformed row pointer or column indices               */
+    BSMM_ENOMEM = -4,  /* the device allocator returned NULL                    */
+    BSMM_EDEVICE = -5, /* a HIP runtime error; C's contents are unspecified     */
+    BSMM_ERANGE = -6,  /* a size exceeds what the library can index             */
+    BSMM_ENOTSUP = -7  /* a supported-but-not-implemented combination           */
+};
+
+/*
+ * Creates a matrix from block-CSR arrays (paper, Sec. II: blocked CSR).
+ *   nbr, row_blk_sizes   block-row count and sizes (host int32[nbr]).
+ *   nbc, col_blk_sizes   block-column count and sizes (host int32[nbc]).
+ *   nnzb, blk_row_ptr, blk_col_ind   the block pattern (host arrays).
+ *   data                 FP64 block values, CSR order, column-major blocks;
+ *                        host or device memory as data_on_device says, or
+ *                        NULL for all-zero blocks.  Its length is the sum
+ *                        of rows(I)*cols(J) over the stored blocks.
+ *   stream               stream for the upload.
+ *   out                  receives the handle.
+ * Every array is copied: the caller may free its inputs on return.  Index
+ * and data live in device memory obtained from the registered allocator.
+ * Errors: EINVAL (null pointers, sizes < 1, nbr or nbc < 0), EINDEX
+ * (malformed index), ERANGE (more than 2^47 elements or 2^31 - 1 blocks),
+ * ENOMEM, EDEVICE.
+ */
+int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes,
+                       int32_t nbc, const int32_t *col_blk_sizes,
+                       int64_t nnzb, const int64_t *blk_row_ptr,
+                       const int32_t *blk_col_ind, const double *data,
+                       int data_on_device, void *stream, bsmm_matrix *out);
+
+/*
+ * C <- filter_eps(beta*C + alpha*A*B) (paper, Sec. II local multiplication;
+ * Sec. III densification for fully occupied inputs).
+ *   A: nbr x nbk blocks, B: nbk x nbc blocks, C: nbr x nbc blocks; the
+ *   block sizes must agree elementwise (A's column sizes = B's row sizes,
+ *   C's row sizes = A's, C's column sizes = B's).
+ *   beta == 0 overwrites C (NaN/Inf in the old C is ignored); alpha == 0
+ *   skips the products (NaN/Inf in A and B is ignored).
+ *   The new pattern of C is the old pattern united with every (I,J) for
+ *   which some K has A(I,K) and B(K,J) stored.  Then, if filter_eps > 0,
+ *   every C block whose squared Frobenius norm is strictly below
+ *   filter_eps^2 is removed (a NaN norm keeps the block).
+ *   A == B is allowed; C must differ from both.
+ * The call blocks the host once to read the size of the new C pattern and
+ * once more when the filter removes blocks; the rest is stream-ordered.
+ * Errors: EINVAL (nulls, C aliasing A or B, filter_eps < 0 or NaN), ESHAPE,
+ * ERANGE, ENOMEM, ENOTSUP, EDEVICE.  On EINVAL/ESHAPE nothing is modified.
+ */
+int bsmm_multiply(double alpha, bsmm_matrix A, bsmm_matrix B, double beta,
+                  bsmm_matrix C, double filter_eps, void *stream);
+
+/* Frees a matrix and its device memory (after synchronising the stream it
+ * was last used on).  NULL is accepted and ignored. */
+int bsmm_destroy_matrix(bsmm_matrix m);
+
+/* Sizes of a matrix: block rows/columns, stored blocks, stored FP64
+ * elements.  Any output pointer may be NULL. */
+int bsmm_matrix_info(bsmm_matrix m, int32_t *nbr, int32_t *nbc, int64_t *nnzb,
+                     int64_t *nelems);
+
+/*
+ * Copies a matrix out: blk_row_ptr (host int64[nbr+1]), blk_col_ind (host
+ * int32[nnzb]) and data (FP64[nelems], host or device as data_on_device
+ * says).  Any output pointer may be NULL to skip that part.  Synchronous
+ * with respect to the host for host outputs.
+ */
+int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
+                  double *data, int data_on_device, void *stream);
+
+/*
+ * Device memory provider.  alloc(bytes, stream, ctx) returns device memory
+ * usable on that stream or NULL; dealloc(ptr, bytes, stream, ctx) returns
+ * it.  Passing alloc == NULL restores the built-in hipMalloc/hipFree
+ * provider.  Memory cached by the library is released (after a device
+ * synchronisation) before the provider changes; matrices created under one
+ * provider are freed through that same provider.
+ */
+typedef void *(*bsmm_alloc_fn)(size_t bytes, void *stream, void *ctx);
+typedef void (*bsmm_dealloc_fn)(void *ptr, size_t bytes, void *stream, void *ctx);
+int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
+
+/*
+ * Library options (process-wide).  Keys and values:
+ *   "path"        "auto" (default) | "stack" | "dense"
+ *                 auto takes the dense path iff A and B have every block
+ *                 stored (paper, Sec. III: densify when the inputs are
+ *                 dense); "dense" forces it (missing blocks read as zero).
+ *   "stack_kernel" "plain" (default) | "tuned"
+ *   "stack_chunk" maximum products per stack launch, "0" = unlimited
+ *                 (paper, Sec. II: batches of at most 30000 products)
+ *   "tune_db"     path of a tuning database file ("" = none)
+ *   "time_kernels" "1" brackets every dense-GEMM and stack-kernel launch
+ *                 with HIP events on the launch stream (see
+ *                 bsmm_kernel_times); "0" (default) records nothing
+ * Errors: EINVAL for an unknown key or value.
+ */
+int bsmm_set_option(const char *key, const char *value);
+
+/* Reads an option into buf (NUL-terminated, truncated to len). */
+int bsmm_get_option(const char *key, char *buf, size_t len);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char *bsmm_last_error(void);
+
+/*
+ * Facts about the last bsmm_multiply on the calling thread, for tests and
+ * benchmarks: which path ran, how many block products and C-block runs the
+ * stacks held, how many shape classes, the algorithmic FP64 flop count
+ * (sum of 2*m*n*k over the block products), and the C block count before
+ * and after the filter.
+ */
+typedef struct bsmm_multiply_stats {
+    int32_t path;          /* 1 = stack, 2 = dense (merged panels)          */
+    int32_t n_classes;     /* shape classes (m, n) holding at least one run */
+    int64_t n_products;    /* block products (a, b, c) in the stacks        */
+    int64_t n_runs;        /* C blocks receiving at least one product       */
+    int64_t c_nnzb_before; /* C blocks before the filter                    */
+    int64_t c_nnzb_after;  /* C blocks after the filter                     */
+    double flops;          /* sum of 2*m*n*k over the block products        */
+} bsmm_multiply_stats;
+int bsmm_last_stats(bsmm_multiply_stats *out);
+
+/*
+ * Builds the product stacks of C = A*B (C's pattern must already contain
+ * the product pattern, e.g. the output of an earlier multiply) and copies
+ * them to the host, for inspection.  Runs are ordered by shape class, then
+ * by C block index; the products of one run are ordered by ascending K.
+ *   n_runs, n_products: in = capacity of the arrays, out = counts.
+ *   run_cblk[r]   C block index of run r (CSR position in C)
+ *   run_class[r]  class id of run r (index into the sorted distinct (m, n))
+ *   run_ptr[r]    first product of run r; run_ptr[n_runs] = n_products
+ *   prod_ablk[p], prod_bblk[p]  A and B block indices (CSR positions)
+ * Arrays may be NULL to query the counts only.  Errors: as bsmm_multiply,
+ * plus ERANGE when a capacity is too small, EINDEX when C's pattern misses
+ * a product block.
+ */
+int bsmm_inspect_stacks(bsmm_matrix A, bsmm_matrix B, bsmm_matrix C,
+                        int64_t *n_runs, int64_t *n_products,
+                        int64_t *run_cblk, int32_t *run_class, int64_t *run_ptr,
+                        int64_t *prod_ablk, int64_t *prod_bblk, void *stream);
+
+/*
+ * Device time of the recorded kernel launches (option "time_kernels"):
+ * total milliseconds and launch counts of the dense GEMM and of the
+ * small-block stack kernels.  Waits for the recorded events.  reset != 0
+ * forgets the recorded launches afterwards.  Output pointers may be NULL.
+ */
+int bsmm_kernel_times(double *gemm_ms, int64_t *gemm_launches, double *stack_ms,
+                      int64_t *stack_launches, int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BSMM_H */

@@ -1,0 +1,315 @@
+"""ctypes binding of libbsmm (include/bsmm.h): argument marshalling only.
+
+Every function keeps the C name and raises ``BsmmError`` on a non-zero
+status.  All computation happens in the HIP library; PyTorch is used only
+for device memory (the caching allocator, registered through
+``use_torch_allocator``) and streams.  Importing this module fails loudly
+when the library has not been built.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbsmm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libbsmm.so not found at {LIB_PATH}; build it with "
+                      "`python -c 'import __graft_entry__ as g; g.build()'`")
+
+# One HIP runtime per process: PyTorch ships its own HIP runtime, and a
+# second runtime initialised in the same process sees no device.  Loading
+# torch first makes the dynamic loader bind libbsmm's libamdhip64.so.7
+# dependency to the copy torch already holds (same SONAME), so device
+# memory and streams from torch are valid in the library.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:  # plain C-ABI use without PyTorch: the system runtime
+    _torch = None
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+BSMM_OK, BSMM_EINVAL, BSMM_ESHAPE, BSMM_EINDEX = 0, -1, -2, -3
+BSMM_ENOMEM, BSMM_EDEVICE, BSMM_ERANGE, BSMM_ENOTSUP = -4, -5, -6, -7
+STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EINDEX", -4: "ENOMEM",
+                -5: "EDEVICE", -6: "ERANGE", -7: "ENOTSUP"}
+
+_vp = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_i64 = ctypes.c_int64
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_i64p = ctypes.POINTER(ctypes.c_int64)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+DEALLOC_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class bsmm_multiply_stats(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("n_classes", ctypes.c_int32),
+                ("n_products", ctypes.c_int64), ("n_runs", ctypes.c_int64),
+                ("c_nnzb_before", ctypes.c_int64), ("c_nnzb_after", ctypes.c_int64),
+                ("flops", ctypes.c_double)]
+
+
+_lib.bsmm_create_matrix.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _vp, ctypes.c_int,
+                                    _vp, ctypes.POINTER(_vp)]
+_lib.bsmm_multiply.argtypes = [ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp]
+_lib.bsmm_destroy_matrix.argtypes = [_vp]
+_lib.bsmm_matrix_info.argtypes = [_vp, _i32p, _i32p, _i64p, _i64p]
+_lib.bsmm_copy_out.argtypes = [_vp, _i64p, _i32p, _vp, ctypes.c_int, _vp]
+_lib.bsmm_set_allocator.argtypes = [ALLOC_FN, DEALLOC_FN, _vp]
+_lib.bsmm_set_option.argtypes = [ctypes.c_char_p, ctypes.c_char_p]
+_lib.bsmm_get_option.argtypes = [ctypes.c_char_p, ctypes.c_char_p, ctypes.c_size_t]
+_lib.bsmm_last_error.restype = ctypes.c_char_p
+_lib.bsmm_last_error.argtypes = []
+_lib.bsmm_last_stats.argtypes = [ctypes.POINTER(bsmm_multiply_stats)]
+_lib.bsmm_inspect_stacks.argtypes = [_vp, _vp, _vp, _i64p, _i64p, _i64p, _i32p, _i64p, _i64p, _i64p, _vp]
+_lib.bsmm_kernel_times.argtypes = [_f64p, _i64p, _f64p, _i64p, ctypes.c_int]
+for _f in ("bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
+           "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
+           "bsmm_last_stats", "bsmm_inspect_stacks"):
+    getattr(_lib, _f).restype = ctypes.c_int
+
+EXPORTED = ("bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
+            "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
+            "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times")
+
+
+class BsmmError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+def _check(st):
+    if st != BSMM_OK:
+        raise BsmmError(st, bsmm_last_error())
+
+
+def _stream(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if hasattr(stream, "cuda_stream"):
+        return ctypes.c_void_p(stream.cuda_stream)
+    return ctypes.c_void_p(int(stream))
+
+
+def _arr(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _ptr(a, t):
+    return a.ctypes.data_as(t) if a is not None and a.size > 0 else ctypes.cast(None, t)
+
+
+def bsmm_last_error():
+    return _lib.bsmm_last_error().decode()
+
+
+def bsmm_create_matrix(nbr, row_blk_sizes, nbc, col_blk_sizes, nnzb, blk_row_ptr, blk_col_ind,
+                       data=None, data_on_device=None, stream=None):
+    """Returns an opaque handle (int).  ``data`` is a numpy array (host), a
+    torch CUDA tensor (device), or None for zeros."""
+    rbs = _arr(row_blk_sizes, np.int32)
+    cbs = _arr(col_blk_sizes, np.int32)
+    rp = _arr(blk_row_ptr, np.int64)
+    ci = _arr(blk_col_ind, np.int32)
+    keep = None
+    if data is None:
+        dptr, on_dev = None, 0
+    elif hasattr(data, "data_ptr"):
+        keep = data.contiguous()
+        dptr, on_dev = keep.data_ptr(), 1 if keep.is_cuda else 0
+        if not on_dev:
+            keep = keep.numpy().astype(np.float64, copy=False)
+            dptr = keep.ctypes.data
+    else:
+        keep = _arr(data, np.float64)
+        dptr, on_dev = (keep.ctypes.data if keep.size else None), 0
+    if data_on_device is not None:
+        on_dev = int(bool(data_on_device))
+    h = ctypes.c_void_p()
+    st = _lib.bsmm_create_matrix(int(nbr), _ptr(rbs, _i32p), int(nbc), _ptr(cbs, _i32p), int(nnzb),
+                                 rp.ctypes.data_as(_i64p), _ptr(ci, _i32p), dptr, on_dev,
+                                 _stream(stream), ctypes.byref(h))
+    _check(st)
+    return h.value
+
+
+def bsmm_multiply(alpha, A, B, beta, C, filter_eps=0.0, stream=None):
+    _check(_lib.bsmm_multiply(float(alpha), A, B, float(beta), C, float(filter_eps), _stream(stream)))
+
+
+def bsmm_destroy_matrix(m):
+    _check(_lib.bsmm_destroy_matrix(m))
+
+
+def bsmm_matrix_info(m):
+    nbr, nbc, nnzb, ne = _i32(), _i32(), _i64(), _i64()
+    _check(_lib.bsmm_matrix_info(m, ctypes.byref(nbr), ctypes.byref(nbc), ctypes.byref(nnzb),
+                                 ctypes.byref(ne)))
+    return nbr.value, nbc.value, nnzb.value, ne.value
+
+
+def bsmm_copy_out(m, stream=None, device_out=None):
+    """Returns (row_ptr, col_ind, data) as numpy arrays; with ``device_out``
+    (a float64 CUDA tensor of nelems) the data go there instead."""
+    nbr, nbc, nnzb, ne = bsmm_matrix_info(m)
+    rp = np.zeros(nbr + 1, dtype=np.int64)
+    ci = np.zeros(max(nnzb, 1), dtype=np.int32)
+    if device_out is not None:
+        _check(_lib.bsmm_copy_out(m, rp.ctypes.data_as(_i64p), ci.ctypes.data_as(_i32p),
+                                  ctypes.c_void_p(device_out.data_ptr()), 1, _stream(stream)))
+        return rp, ci[:nnzb], device_out
+    data = np.zeros(max(ne, 1), dtype=np.float64)
+    _check(_lib.bsmm_copy_out(m, rp.ctypes.data_as(_i64p), ci.ctypes.data_as(_i32p),
+                              ctypes.c_void_p(data.ctypes.data), 0, _stream(stream)))
+    return rp, ci[:nnzb], data[:ne]
+
+
+_alloc_keepalive = []
+
+
+def bsmm_set_allocator(alloc=None, dealloc=None, ctx=None):
+    """Registers Python callables alloc(nbytes, stream) -> int pointer and
+    dealloc(ptr, nbytes, stream); no arguments restores hipMalloc/hipFree."""
+    if alloc is None:
+        _check(_lib.bsmm_set_allocator(ALLOC_FN(), DEALLOC_FN(), None))
+        _alloc_keepalive.clear()
+        return
+
+    def _a(nbytes, stream, _ctx):
+        try:
+            return int(alloc(int(nbytes), stream or 0)) or None
+        except Exception:  # the C side turns NULL into ENOMEM
+            return None
+
+    def _d(ptr, nbytes, stream, _ctx):
+        try:
+            dealloc(ptr, int(nbytes), stream or 0)
+        except Exception:
+            pass
+
+    fa, fd = ALLOC_FN(_a), DEALLOC_FN(_d)
+    _check(_lib.bsmm_set_allocator(fa, fd, None))
+    _alloc_keepalive[:] = [fa, fd]
+
+
+def use_torch_allocator(device=None):
+    """Device memory of the library comes from PyTorch's caching allocator."""
+    import torch
+    dev = torch.cuda.current_device() if device is None else device
+
+    def alloc(nbytes, stream):
+        return torch.cuda.caching_allocator_alloc(nbytes, dev, stream if stream else None)
+
+    def dealloc(ptr, nbytes, stream):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    bsmm_set_allocator(alloc, dealloc)
+
+
+def bsmm_set_option(key, value):
+    _check(_lib.bsmm_set_option(str(key).encode(), str(value).encode()))
+
+
+def bsmm_get_option(key):
+    buf = ctypes.create_string_buffer(4096)
+    _check(_lib.bsmm_get_option(str(key).encode(), buf, 4096))
+    return buf.value.decode()
+
+
+def bsmm_last_stats():
+    s = bsmm_multiply_stats()
+    _check(_lib.bsmm_last_stats(ctypes.byref(s)))
+    return {f: getattr(s, f) for f, _ in bsmm_multiply_stats._fields_}
+
+
+def bsmm_inspect_stacks(A, B, C, stream=None):
+    nr, npr = _i64(0), _i64(0)
+    _check(_lib.bsmm_inspect_stacks(A, B, C, ctypes.byref(nr), ctypes.byref(npr), None, None, None,
+                                    None, None, _stream(stream)))
+    run_cblk = np.zeros(max(nr.value, 1), np.int64)
+    run_class = np.zeros(max(nr.value, 1), np.int32)
+    run_ptr = np.zeros(nr.value + 1, np.int64)
+    pa = np.zeros(max(npr.value, 1), np.int64)
+    pb = np.zeros(max(npr.value, 1), np.int64)
+    _check(_lib.bsmm_inspect_stacks(A, B, C, ctypes.byref(nr), ctypes.byref(npr),
+                                    run_cblk.ctypes.data_as(_i64p), run_class.ctypes.data_as(_i32p),
+                                    run_ptr.ctypes.data_as(_i64p), pa.ctypes.data_as(_i64p),
+                                    pb.ctypes.data_as(_i64p), _stream(stream)))
+    n, p = nr.value, npr.value
+    return {"run_cblk": run_cblk[:n], "run_class": run_class[:n], "run_ptr": run_ptr,
+            "prod_ablk": pa[:p], "prod_bblk": pb[:p]}
+
+
+def bsmm_kernel_times(reset=True):
+    """(gemm_ms, gemm_launches, stack_ms, stack_launches) of the launches
+    recorded while the option time_kernels is 1."""
+    gm, gn, sm, sn = ctypes.c_double(), _i64(), ctypes.c_double(), _i64()
+    _check(_lib.bsmm_kernel_times(ctypes.byref(gm), ctypes.byref(gn), ctypes.byref(sm),
+                                  ctypes.byref(sn), 1 if reset else 0))
+    return gm.value, gn.value, sm.value, sn.value
+
+
+class HostBlockCSR:
+    """Host copy of a matrix (numpy arrays)."""
+
+    def __init__(self, rbs, cbs, row_ptr, col_ind, data):
+        self.rbs, self.cbs, self.row_ptr, self.col_ind, self.data = rbs, cbs, row_ptr, col_ind, data
+
+
+class Matrix:
+    """Owning wrapper of a bsmm handle."""
+
+    def __init__(self, handle, rbs, cbs):
+        self.handle = handle
+        self.rbs = np.asarray(rbs, dtype=np.int32)
+        self.cbs = np.asarray(cbs, dtype=np.int32)
+
+    @classmethod
+    def from_blocks(cls, M, stream=None, data=None):
+        """From any object with rbs, cbs, row_ptr, col_ind, data attributes."""
+        d = M.data if data is None else data
+        h = bsmm_create_matrix(len(M.rbs), M.rbs, len(M.cbs), M.cbs, int(np.asarray(M.row_ptr)[-1]),
+                               M.row_ptr, M.col_ind, d, stream=stream)
+        return cls(h, M.rbs, M.cbs)
+
+    @classmethod
+    def empty(cls, rbs, cbs, stream=None):
+        """A matrix with no stored blocks."""
+        rp = np.zeros(len(rbs) + 1, dtype=np.int64)
+        h = bsmm_create_matrix(len(rbs), rbs, len(cbs), cbs, 0, rp, np.zeros(0, np.int32), None,
+                               stream=stream)
+        return cls(h, rbs, cbs)
+
+    def info(self):
+        return bsmm_matrix_info(self.handle)
+
+    def to_host(self, stream=None):
+        rp, ci, data = bsmm_copy_out(self.handle, stream)
+        return HostBlockCSR(self.rbs, self.cbs, rp, ci, data)
+
+    def close(self):
+        if self.handle:
+            bsmm_destroy_matrix(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def multiply(alpha, A, B, beta, C, filter_eps=0.0, stream=None):
+    """C <- filter_eps(beta*C + alpha*A*B) on Matrix objects."""
+    bsmm_multiply(alpha, A.handle, B.handle, beta, C.handle, filter_eps, stream)

@@ -1,0 +1,488 @@
+// api.hip -- the C-ABI: handles, validation, options, device memory pool.
+//
+// Validation of every argument happens on the host before any HIP call, so
+// malformed input is rejected even on a machine without a GPU.
+#include <algorithm>
+#include <cstdarg>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <unordered_map>
+
+#include "internal.h"
+
+namespace bsmm {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string t_msg;
+static thread_local int t_code = BSMM_OK;
+
+void set_error(int code, const char *fmt, ...) {
+    char buf[1024];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_msg = buf;
+    t_code = code;
+}
+void clear_error() {
+    t_msg.clear();
+    t_code = BSMM_OK;
+}
+int last_code() { return t_code; }
+
+int launch_check(const char *what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(BSMM_EDEVICE, "kernel launch '%s' failed: %s", what, hipGetErrorString(e));
+        return BSMM_EDEVICE;
+    }
+    return BSMM_OK;
+}
+
+Options &options() {
+    static Options o;
+    return o;
+}
+
+// ------------------------------------------------------------------- pool
+namespace {
+struct Provider {
+    bsmm_alloc_fn alloc = nullptr;
+    bsmm_dealloc_fn dealloc = nullptr;
+    void *ctx = nullptr;
+};
+struct Block {
+    void *p;
+    size_t bytes;
+    hipStream_t s;
+    Provider prov;
+};
+std::mutex g_mu;
+std::multimap<size_t, Block> g_free;
+std::unordered_map<void *, Block> g_used;
+Provider g_prov;
+
+void *raw_alloc(size_t bytes, hipStream_t s) {
+    if (g_prov.alloc) return g_prov.alloc(bytes, (void *)s, g_prov.ctx);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return p;
+}
+void raw_free(const Block &b) {
+    if (b.prov.alloc) {
+        if (b.prov.dealloc) b.prov.dealloc(b.p, b.bytes, (void *)b.s, b.prov.ctx);
+    } else {
+        (void)hipFree(b.p);
+    }
+}
+size_t round_size(size_t n) {
+    if (n <= 4096) return (n + 255) & ~size_t(255);
+    size_t p = size_t(1) << (63 - __builtin_clzll(n));  // highest power of two <= n
+    size_t step = std::max<size_t>(p / 8, 4096);
+    return (n + step - 1) / step * step;
+}
+void release_free_locked() {
+    if (g_free.empty()) return;
+    (void)hipDeviceSynchronize();
+    for (auto &kv : g_free) raw_free(kv.second);
+    g_free.clear();
+}
+}  // namespace
+
+void *dev_alloc(size_t bytes, hipStream_t s) {
+    size_t want = round_size(bytes ? bytes : 1);
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_free.lower_bound(want);
+    if (it != g_free.end() && it->first <= want + want / 2 + 4096) {
+        Block b = it->second;
+        g_free.erase(it);
+        if (b.s != s) (void)hipStreamSynchronize(b.s);
+        b.s = s;
+        g_used[b.p] = b;
+        return b.p;
+    }
+    void *p = raw_alloc(want, s);
+    if (!p) {
+        release_free_locked();
+        p = raw_alloc(want, s);
+    }
+    if (!p) return nullptr;
+    g_used[p] = Block{p, want, s, g_prov};
+    return p;
+}
+
+void dev_free(void *p, hipStream_t s) {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_used.find(p);
+    if (it == g_used.end()) return;
+    Block b = it->second;
+    g_used.erase(it);
+    b.s = s;
+    g_free.emplace(b.bytes, b);
+}
+
+int pool_release_all() {
+    std::lock_guard<std::mutex> lk(g_mu);
+    release_free_locked();
+    return BSMM_OK;
+}
+
+static int set_provider(bsmm_alloc_fn a, bsmm_dealloc_fn d, void *ctx) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    release_free_locked();
+    g_prov.alloc = a;
+    g_prov.dealloc = a ? d : nullptr;
+    g_prov.ctx = a ? ctx : nullptr;
+    return BSMM_OK;
+}
+
+// ------------------------------------------------------------- validation
+// Pure host checks of a block-CSR description; no HIP call.
+static int validate_sizes(const char *what, int32_t nb, const int32_t *sizes) {
+    if (nb < 0) {
+        set_error(BSMM_EINVAL, "%s: negative block count %d", what, nb);
+        return BSMM_EINVAL;
+    }
+    if (nb > 0 && !sizes) {
+        set_error(BSMM_EINVAL, "%s: block sizes pointer is NULL", what);
+        return BSMM_EINVAL;
+    }
+    for (int32_t i = 0; i < nb; ++i)
+        if (sizes[i] < 1) {
+            set_error(BSMM_EINVAL, "%s: block size %d at index %d is < 1", what, sizes[i], i);
+            return BSMM_EINVAL;
+        }
+    return BSMM_OK;
+}
+
+static int validate_pattern(int32_t nbr, int32_t nbc, int64_t nnzb, const int64_t *rp,
+                            const int32_t *ci) {
+    if (nnzb < 0) {
+        set_error(BSMM_EINVAL, "negative block count nnzb=%lld", (long long)nnzb);
+        return BSMM_EINVAL;
+    }
+    if (!rp) {
+        set_error(BSMM_EINVAL, "blk_row_ptr is NULL");
+        return BSMM_EINVAL;
+    }
+    if (nnzb > 0 && !ci) {
+        set_error(BSMM_EINVAL, "blk_col_ind is NULL");
+        return BSMM_EINVAL;
+    }
+    if (nnzb > (int64_t)INT32_MAX) {
+        set_error(BSMM_ERANGE, "too many blocks (%lld)", (long long)nnzb);
+        return BSMM_ERANGE;
+    }
+    if (rp[0] != 0 || rp[nbr] != nnzb) {
+        set_error(BSMM_EINDEX, "blk_row_ptr must start at 0 and end at nnzb");
+        return BSMM_EINDEX;
+    }
+    for (int32_t i = 0; i < nbr; ++i) {
+        if (rp[i + 1] < rp[i]) {
+            set_error(BSMM_EINDEX, "blk_row_ptr decreases at row %d", i);
+            return BSMM_EINDEX;
+        }
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (ci[p] < 0 || ci[p] >= nbc) {
+                set_error(BSMM_EINDEX, "column index %d out of range at row %d", ci[p], i);
+                return BSMM_EINDEX;
+            }
+            if (p > rp[i] && ci[p] <= ci[p - 1]) {
+                set_error(BSMM_EINDEX, "columns not strictly ascending at row %d", i);
+                return BSMM_EINDEX;
+            }
+        }
+    }
+    return BSMM_OK;
+}
+
+static thread_local bsmm_multiply_stats t_stats;
+bsmm_multiply_stats &stats() { return t_stats; }
+
+}  // namespace bsmm
+
+using namespace bsmm;
+
+// ------------------------------------------------------------------- C-ABI
+extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int32_t nbc,
+                                  const int32_t *col_blk_sizes, int64_t nnzb,
+                                  const int64_t *blk_row_ptr, const int32_t *blk_col_ind,
+                                  const double *data, int data_on_device, void *stream,
+                                  bsmm_matrix *out) {
+    clear_error();
+    if (!out) {
+        set_error(BSMM_EINVAL, "out is NULL");
+        return BSMM_EINVAL;
+    }
+    BSMM_TRY(validate_sizes("row_blk_sizes", nbr, row_blk_sizes));
+    BSMM_TRY(validate_sizes("col_blk_sizes", nbc, col_blk_sizes));
+    BSMM_TRY(validate_pattern(nbr, nbc, nnzb, blk_row_ptr, blk_col_ind));
+
+    // Host-side offsets.
+    std::vector<int64_t> row_off(nbr + 1, 0), col_off(nbc + 1, 0), blk_off(nnzb + 1, 0);
+    for (int32_t i = 0; i < nbr; ++i) row_off[i + 1] = row_off[i] + row_blk_sizes[i];
+    for (int32_t j = 0; j < nbc; ++j) col_off[j + 1] = col_off[j] + col_blk_sizes[j];
+    int64_t acc = 0;
+    for (int32_t i = 0; i < nbr; ++i)
+        for (int64_t p = blk_row_ptr[i]; p < blk_row_ptr[i + 1]; ++p) {
+            blk_off[p] = acc;
+            acc += (int64_t)row_blk_sizes[i] * col_blk_sizes[blk_col_ind[p]];
+            if (acc >= (int64_t(1) << 47)) {
+                set_error(BSMM_ERANGE, "matrix holds 2^47 or more elements");
+                return BSMM_ERANGE;
+            }
+        }
+    blk_off[nnzb] = acc;
+    if (row_off[nbr] > INT32_MAX || col_off[nbc] > INT32_MAX) {
+        set_error(BSMM_ERANGE, "matrix dimension exceeds 2^31-1 rows or columns");
+        return BSMM_ERANGE;
+    }
+
+    hipStream_t s = (hipStream_t)stream;
+    auto *M = new (std::nothrow) bsmm_matrix_s();
+    if (!M) {
+        set_error(BSMM_ENOMEM, "host allocation failed");
+        return BSMM_ENOMEM;
+    }
+    M->nbr = nbr;
+    M->nbc = nbc;
+    M->rbs.assign(row_blk_sizes, row_blk_sizes + nbr);
+    M->cbs.assign(col_blk_sizes, col_blk_sizes + nbc);
+    M->row_off = row_off;
+    M->col_off = col_off;
+    M->nnzb = nnzb;
+    M->nelems = acc;
+    M->max_rbs = nbr ? *std::max_element(M->rbs.begin(), M->rbs.end()) : 0;
+    M->max_cbs = nbc ? *std::max_element(M->cbs.begin(), M->cbs.end()) : 0;
+    M->last_stream = s;
+    {
+        int ndev = 0;
+        hipError_t e1 = hipGetDeviceCount(&ndev);
+        hipError_t e2 = e1 == hipSuccess && ndev > 0 ? hipGetDevice(&M->device) : e1;
+        if (e1 != hipSuccess || ndev <= 0 || e2 != hipSuccess) {
+            (void)hipGetLastError();
+            delete M;
+            set_error(BSMM_EDEVICE, "no HIP device available (%s, %d devices, %s)",
+                      hipGetErrorString(e1), ndev, hipGetErrorString(e2));
+            return BSMM_EDEVICE;
+        }
+    }
+
+    std::vector<int2> rmap(row_off[nbr]), cmap(col_off[nbc]);
+    for (int32_t i = 0; i < nbr; ++i)
+        for (int32_t r = 0; r < row_blk_sizes[i]; ++r) rmap[row_off[i] + r] = make_int2(i, r);
+    for (int32_t j = 0; j < nbc; ++j)
+        for (int32_t c = 0; c < col_blk_sizes[j]; ++c) cmap[col_off[j] + c] = make_int2(j, c);
+
+    auto fail = [&](int code) {
+        delete M;
+        return code;
+    };
+    int st = BSMM_OK;
+    if ((st = M->b_rbs.reserve(sizeof(int32_t) * (nbr + 1), s)) ||
+        (st = M->b_cbs.reserve(sizeof(int32_t) * (nbc + 1), s)) ||
+        (st = M->b_row_off.reserve(sizeof(int64_t) * (nbr + 1), s)) ||
+        (st = M->b_col_off.reserve(sizeof(int64_t) * (nbc + 1), s)) ||
+        (st = M->b_row_map.reserve(sizeof(int2) * (rmap.size() + 1), s)) ||
+        (st = M->b_col_map.reserve(sizeof(int2) * (cmap.size() + 1), s)) ||
+        (st = M->b_row_ptr.reserve(sizeof(int64_t) * (nbr + 1), s)) ||
+        (st = M->b_col_ind.reserve(sizeof(int32_t) * (nnzb + 1), s)) ||
+        (st = M->b_blk_off.reserve(sizeof(int64_t) * (nnzb + 1), s)) ||
+        (st = M->b_data.reserve(sizeof(double) * (acc + 1), s)))
+        return fail(st);
+
+#define CP(dst, src, bytes)                                                                  \
+    do {                                                                                     \
+        if ((bytes) > 0) {                                                                   \
+            hipError_t e_ = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s);       \
+            if (e_ != hipSuccess) {                                                          \
+                set_error(BSMM_EDEVICE, "upload failed: %s", hipGetErrorString(e_));         \
+                return fail(BSMM_EDEVICE);                                                   \
+            }                                                                                \
+        }                                                                                    \
+    } while (0)
+    CP(M->d_rbs(), row_blk_sizes, sizeof(int32_t) * nbr);
+    CP(M->d_cbs(), col_blk_sizes, sizeof(int32_t) * nbc);
+    CP(M->d_row_off(), row_off.data(), sizeof(int64_t) * (nbr + 1));
+    CP(M->d_col_off(), col_off.data(), sizeof(int64_t) * (nbc + 1));
+    CP(M->d_row_map(), rmap.data(), sizeof(int2) * rmap.size());
+    CP(M->d_col_map(), cmap.data(), sizeof(int2) * cmap.size());
+    CP(M->d_row_ptr(), blk_row_ptr, sizeof(int64_t) * (nbr + 1));
+    CP(M->d_col_ind(), blk_col_ind, sizeof(int32_t) * nnzb);
+    CP(M->d_blk_off(), blk_off.data(), sizeof(int64_t) * (nnzb + 1));
+#undef CP
+    if (acc > 0) {
+        hipError_t e;
+        if (data)
+            e = hipMemcpyAsync(M->d_data(), data, sizeof(double) * acc,
+                               data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
+        else
+            e = (hipError_t)(fill_zero(M->d_data(), acc, s) == BSMM_OK ? hipSuccess : hipErrorUnknown);
+        if (e != hipSuccess) {
+            set_error(BSMM_EDEVICE, "data upload failed: %s", hipGetErrorString(e));
+            return fail(BSMM_EDEVICE);
+        }
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        set_error(BSMM_EDEVICE, "stream synchronisation failed");
+        return fail(BSMM_EDEVICE);
+    }
+    *out = M;
+    return BSMM_OK;
+}
+
+extern "C" int bsmm_destroy_matrix(bsmm_matrix m) {
+    clear_error();
+    if (!m) return BSMM_OK;
+    (void)hipStreamSynchronize(m->last_stream);
+    delete m;
+    return BSMM_OK;
+}
+
+extern "C" int bsmm_matrix_info(bsmm_matrix m, int32_t *nbr, int32_t *nbc, int64_t *nnzb,
+                                int64_t *nelems) {
+    clear_error();
+    if (!m) {
+        set_error(BSMM_EINVAL, "matrix is NULL");
+        return BSMM_EINVAL;
+    }
+    if (nbr) *nbr = m->nbr;
+    if (nbc) *nbc = m->nbc;
+    if (nnzb) *nnzb = m->nnzb;
+    if (nelems) *nelems = m->nelems;
+    return BSMM_OK;
+}
+
+extern "C" int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
+                             double *data, int data_on_device, void *stream) {
+    clear_error();
+    if (!m) {
+        set_error(BSMM_EINVAL, "matrix is NULL");
+        return BSMM_EINVAL;
+    }
+    hipStream_t s = (hipStream_t)stream;
+    if (blk_row_ptr)
+        BSMM_HIP(hipMemcpyAsync(blk_row_ptr, m->d_row_ptr(), sizeof(int64_t) * (m->nbr + 1),
+                                hipMemcpyDeviceToHost, s));
+    if (blk_col_ind && m->nnzb > 0)
+        BSMM_HIP(hipMemcpyAsync(blk_col_ind, m->d_col_ind(), sizeof(int32_t) * m->nnzb,
+                                hipMemcpyDeviceToHost, s));
+    if (data && m->nelems > 0)
+        BSMM_HIP(hipMemcpyAsync(data, m->d_data(), sizeof(double) * m->nelems,
+                                data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    m->last_stream = s;
+    return BSMM_OK;
+}
+
+extern "C" int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx) {
+    clear_error();
+    if (alloc && !dealloc) {
+        set_error(BSMM_EINVAL, "an allocator needs a matching deallocator");
+        return BSMM_EINVAL;
+    }
+    return set_provider(alloc, dealloc, ctx);
+}
+
+extern "C" int bsmm_set_option(const char *key, const char *value) {
+    clear_error();
+    if (!key || !value) {
+        set_error(BSMM_EINVAL, "key or value is NULL");
+        return BSMM_EINVAL;
+    }
+    Options &o = options();
+    std::string k(key), v(value);
+    if (k == "path") {
+        if (v == "auto") o.path = 0;
+        else if (v == "stack") o.path = 1;
+        else if (v == "dense") o.path = 2;
+        else goto bad;
+    } else if (k == "stack_kernel") {
+        if (v == "plain") o.stack_kernel = 0;
+        else if (v == "tuned") o.stack_kernel = 1;
+        else goto bad;
+    } else if (k == "stack_chunk") {
+        char *end = nullptr;
+        long long x = strtoll(value, &end, 10);
+        if (!end || *end || x < 0) goto bad;
+        o.stack_chunk = x;
+    } else if (k == "tune_db") {
+        o.tune_db = v;
+    } else if (k == "time_kernels") {
+        if (v == "0") o.time_kernels = 0;
+        else if (v == "1") o.time_kernels = 1;
+        else goto bad;
+    } else {
+        set_error(BSMM_EINVAL, "unknown option '%s'", key);
+        return BSMM_EINVAL;
+    }
+    return BSMM_OK;
+bad:
+    set_error(BSMM_EINVAL, "bad value '%s' for option '%s'", value, key);
+    return BSMM_EINVAL;
+}
+
+extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
+    clear_error();
+    if (!key || !buf || len == 0) {
+        set_error(BSMM_EINVAL, "bad arguments");
+        return BSMM_EINVAL;
+    }
+    Options &o = options();
+    std::string k(key), v;
+    if (k == "path") v = o.path == 0 ? "auto" : o.path == 1 ? "stack" : "dense";
+    else if (k == "stack_kernel") v = o.stack_kernel ? "tuned" : "plain";
+    else if (k == "stack_chunk") v = std::to_string(o.stack_chunk);
+    else if (k == "tune_db") v = o.tune_db;
+    else if (k == "time_kernels") v = std::to_string(o.time_kernels);
+    else {
+        set_error(BSMM_EINVAL, "unknown option '%s'", key);
+        return BSMM_EINVAL;
+    }
+    snprintf(buf, len, "%s", v.c_str());
+    return BSMM_OK;
+}
+
+extern "C" const char *bsmm_last_error(void) { return bsmm::t_msg.c_str(); }
+
+extern "C" int bsmm_last_stats(bsmm_multiply_stats *out) {
+    if (!out) {
+        set_error(BSMM_EINVAL, "out is NULL");
+        return BSMM_EINVAL;
+    }
+    *out = bsmm::t_stats;
+    return BSMM_OK;
+}
+
+// Shared by multiply.hip: argument checks of a multiply (host only).
+namespace bsmm {
+int validate_multiply(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, double eps) {
+    if (!A || !B || !C) {
+        set_error(BSMM_EINVAL, "a matrix handle is NULL");
+        return BSMM_EINVAL;
+    }
+    if (C == A || C == B) {
+        set_error(BSMM_EINVAL, "C must not alias A or B");
+        return BSMM_EINVAL;
+    }
+    if (!(eps >= 0.0)) {
+        set_error(BSMM_EINVAL, "filter_eps must be >= 0 and not NaN");
+        return BSMM_EINVAL;
+    }
+    if (A->cbs != B->rbs) {
+        set_error(BSMM_ESHAPE, "A block-column sizes differ from B block-row sizes");
+        return BSMM_ESHAPE;
+    }
+    if (C->rbs != A->rbs || C->cbs != B->cbs) {
+        set_error(BSMM_ESHAPE, "C block sizes differ from (A rows, B columns)");
+        return BSMM_ESHAPE;
+    }
+    return BSMM_OK;
+}
+}  // namespace bsmm

@@ -1,0 +1,284 @@
+// dense.hip -- densification path: merge blocks into panels, one FP64 MFMA
+// GEMM, split the result back into the blocks of C.
+//
+// Paper, Sec. III: when the inputs are dense, all blocks handled by a worker
+// are coalesced into one large block by copying them into new buffers, the
+// product becomes a single GEMM, and C is undensified at the end.  With one
+// rank and one panel (Eqs. (1)-(2) with P~ = 1, t = 1) the panels are the
+// whole matrices: A -> Ap (M x K), B -> Bp (K x N), both column-major and
+// zero-padded to the GEMM tile.  The undensify step is fused into the GEMM
+// epilogue, which writes C = beta*C + alpha*(Ap Bp) straight into C's
+// blocks through per-row and per-column (block, offset) maps.
+//
+// GEMM: 128 x 128 output tile per 256-thread workgroup, k step 16, LDS double
+// buffered; each wave owns a 64 x 64 sub-tile as 4 x 4 MFMA tiles of
+// v_mfma_f64_16x16x4 (FP64 in, FP64 accumulate).  Workgroup ids are remapped
+// so that the tiles dispatched to one XCD form a contiguous band of
+// 8 tile-rows (shared A panels stay in that XCD's L2).
+#include <algorithm>
+
+#include "dev_util.h"
+#include "internal.h"
+
+namespace bsmm {
+
+namespace {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+typedef double double2_t __attribute__((ext_vector_type(2)));
+
+constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int kGroupM = 8;
+
+// Merge: one workgroup per block row; each wave copies whole blocks into the
+// column-major panel (ld = panel rows).
+__global__ __launch_bounds__(256) void k_merge(const int32_t *rbs, const int32_t *cbs,
+                                               const int64_t *row_off, const int64_t *col_off,
+                                               const int64_t *rp, const int32_t *ci,
+                                               const int64_t *blk_off, const double *data,
+                                               double *panel, int64_t ld) {
+    const int32_t row = blockIdx.x;
+    const int nw = blockDim.x / kWave;
+    const int m = rbs[row];
+    const int64_t r0 = row_off[row];
+    for (int64_t p = rp[row] + wave_id(); p < rp[row + 1]; p += nw) {
+        const int32_t j = ci[p];
+        const int n = cbs[j];
+        const int64_t c0 = col_off[j];
+        const double *src = data + blk_off[p];
+        const int64_t len = (int64_t)m * n;
+        if (len < (1 << 20) && m < 4096) {
+            const float rcp = 1.0f / (float)m;
+            for (int e = lane_id(); e < len; e += kWave) {
+                int ii;
+                const int jj = divmod_small(e, m, rcp, &ii);
+                panel[(c0 + jj) * ld + r0 + ii] = src[e];
+            }
+        } else {
+            for (int64_t e = lane_id(); e < len; e += kWave)
+                panel[(c0 + e / m) * ld + r0 + e % m] = src[e];
+        }
+    }
+}
+
+struct GemmArgs {
+    const double *Ap;   // M_pad x K_pad, column-major, ld = lda
+    const double *Bp;   // K_pad x N_pad, column-major, ld = ldb
+    int64_t lda, ldb;
+    int tiles_m, tiles_n, ktiles;
+    int64_t M, N;       // true sizes (rows/cols of C)
+    double alpha, beta;
+    double *C;          // C block data
+    const int64_t *c_blk_off;
+    const int32_t *c_map;   // nbr*nbc block index map, or null when C is full
+    int32_t c_nbc;
+    const int32_t *c_rbs;
+    const int2 *rmap, *cmap;
+};
+
+// Global -> register loads of one k step: A tile (128 rows x 16 k) as 1024
+// double2 along the rows, B tile (16 k x 128 cols) as 1024 double2 along k.
+__device__ __forceinline__ void gemm_gload(double2_t (&ra)[4], double2_t (&rb)[4], const double *Ablk,
+                                           const double *Bblk, int64_t lda, int64_t ldb, int kt,
+                                           int tid) {
+    const int64_t k0 = (int64_t)kt * BK;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + 256 * i;
+        const int kk = e >> 6, r2 = e & 63;
+        ra[i] = *reinterpret_cast<const double2_t *>(Ablk + (k0 + kk) * lda + 2 * r2);
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + 256 * i;
+        const int col = e >> 3, k2 = e & 7;
+        rb[i] = *reinterpret_cast<const double2_t *>(Bblk + (int64_t)col * ldb + k0 + 2 * k2);
+    }
+}
+
+// Register -> LDS stores: As[k][m]; Bs[n][k ^ (n & 15)] (XOR swizzle keeps
+// the 16 lanes that read one k of 16 consecutive columns on distinct banks).
+__device__ __forceinline__ void gemm_lstore(const double2_t (&ra)[4], const double2_t (&rb)[4],
+                                            double *As, double *Bs, int tid) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + 256 * i;
+        const int kk = e >> 6, r2 = e & 63;
+        *reinterpret_cast<double2_t *>(&As[kk * BM + 2 * r2]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int e = tid + 256 * i;
+        const int col = e >> 3, k2 = e & 7;
+        const int sw = col & 15;
+        const int base = (2 * k2) ^ (sw & ~1);
+        const double2_t v = (sw & 1) ? rb[i].yx : rb[i];
+        *reinterpret_cast<double2_t *>(&Bs[col * BK + base]) = v;
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_dgemm_mfma(GemmArgs g) {
+    __shared__ double As[2][BK * BM];  // [k][m]
+    __shared__ double Bs[2][BN * BK];  // [n][k ^ swizzle(n)]
+
+    // XCD-aware remap, then grouped row-major order inside the XCD's band.
+    const int nwg = gridDim.x;
+    int logical = blockIdx.x;
+    if ((nwg & 7) == 0) logical = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+    const int per_group = kGroupM * g.tiles_n;
+    const int group = logical / per_group;
+    const int first_m = group * kGroupM;
+    const int gsz = min(g.tiles_m - first_m, kGroupM);
+    const int in_group = logical - group * per_group;
+    const int tm = first_m + in_group % gsz;
+    const int tn = in_group / gsz;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int l16 = lane & 15, lk = lane >> 4;
+
+    const double *Ablk = g.Ap + (int64_t)tm * BM;
+    const double *Bblk = g.Bp + (int64_t)tn * BN * g.ldb;
+
+    double2_t ra[4], rb[4];
+    double4_t acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+    gemm_gload(ra, rb, Ablk, Bblk, g.lda, g.ldb, 0, tid);
+    gemm_lstore(ra, rb, As[0], Bs[0], tid);
+    __syncthreads();
+    for (int kt = 0; kt < g.ktiles; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < g.ktiles) gemm_gload(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
+#pragma unroll
+        for (int ks = 0; ks < BK / 4; ++ks) {
+            const int k = ks * 4 + lk;
+            double a[4], b[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) a[t] = As[cur][k * BM + wm * 64 + t * 16 + l16];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const int col = wn * 64 + t * 16 + l16;
+                b[t] = Bs[cur][col * BK + (k ^ (col & 15))];
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+        }
+        if (kt + 1 < g.ktiles) gemm_lstore(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
+        __syncthreads();
+    }
+
+    // Epilogue: D(row, col) of a 16x16 FP64 tile sits in lane
+    // (col + 16 * (row % 4)), element row / 4.
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + l16;
+            if (col >= g.N) continue;
+            const int2 cm = g.cmap[col];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + e * 4 + lk;
+                if (row >= g.M) continue;
+                const int2 rm = g.rmap[row];
+                const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
+                const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
+                if (blk < 0) continue;
+                double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
+                const double prod = g.alpha * acc[i][j][e];
+                *dst = (g.beta == 0.0) ? prod : fma(g.beta, *dst, prod);
+            }
+        }
+    }
+}
+
+// c_map[I*nbc + J] = CSR position of block (I,J) in C, or -1.
+__global__ __launch_bounds__(256) void k_block_map(int32_t nbr, int32_t nbc, const int64_t *rp,
+                                                   const int32_t *ci, int32_t *map) {
+    const int32_t row = blockIdx.x;
+    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[(int64_t)row * nbc + j] = -1;
+    __syncthreads();
+    for (int64_t p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x)
+        map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
+}
+
+}  // namespace
+
+int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
+                   double alpha, double beta, hipStream_t s) {
+    const int64_t M = A->rows(), K = A->cols(), N = B->cols();
+    if (M == 0 || N == 0 || C->nnzb == 0) return BSMM_OK;
+    if (alpha == 0.0 || K == 0) return scale_blocks(C, nullptr, beta, s);
+    const int64_t Mp = ceil_div(M, BM) * BM, Np = ceil_div(N, BN) * BN, Kp = ceil_div(K, BK) * BK;
+    const int64_t tiles = (Mp / BM) * (Np / BN);
+    if (tiles > INT32_MAX || Mp * Kp > (int64_t(1) << 47) || Kp * Np > (int64_t(1) << 47)) {
+        set_error(BSMM_ERANGE, "dense panels too large");
+        return BSMM_ERANGE;
+    }
+    DevBuf ap, bp, cmap;
+    BSMM_TRY(ap.reserve(sizeof(double) * Mp * Kp, s));
+    BSMM_TRY(bp.reserve(sizeof(double) * Kp * Np, s));
+    // Panels need zeros where blocks are absent and in the padding.
+    if (!A->full() || Mp != M || Kp != K) BSMM_TRY(fill_zero(ap.as<double>(), Mp * Kp, s));
+    if (!B->full() || Kp != K || Np != N) BSMM_TRY(fill_zero(bp.as<double>(), Kp * Np, s));
+    if (A->nnzb > 0) {
+        hipLaunchKernelGGL(k_merge, dim3(A->nbr), dim3(256), 0, s, A->d_rbs(), A->d_cbs(),
+                           A->d_row_off(), A->d_col_off(), A->d_row_ptr(), A->d_col_ind(),
+                           A->d_blk_off(), A->d_data(), ap.as<double>(), Mp);
+        BSMM_TRY(launch_check("merge_A"));
+    }
+    if (B->nnzb > 0) {
+        hipLaunchKernelGGL(k_merge, dim3(B->nbr), dim3(256), 0, s, B->d_rbs(), B->d_cbs(),
+                           B->d_row_off(), B->d_col_off(), B->d_row_ptr(), B->d_col_ind(),
+                           B->d_blk_off(), B->d_data(), bp.as<double>(), Kp);
+        BSMM_TRY(launch_check("merge_B"));
+    }
+    const int32_t *d_cmap = nullptr;
+    if (!C->full()) {
+        const int64_t cells = (int64_t)C->nbr * C->nbc;
+        if (cells > (int64_t(1) << 30)) {
+            set_error(BSMM_ENOTSUP, "dense path on a sparse C with more than 2^30 block cells");
+            return BSMM_ENOTSUP;
+        }
+        BSMM_TRY(cmap.reserve(sizeof(int32_t) * cells, s));
+        hipLaunchKernelGGL(k_block_map, dim3(C->nbr), dim3(256), 0, s, C->nbr, C->nbc,
+                           C->d_row_ptr(), C->d_col_ind(), cmap.as<int32_t>());
+        BSMM_TRY(launch_check("block_map"));
+        d_cmap = cmap.as<int32_t>();
+    }
+    GemmArgs g{};
+    g.Ap = ap.as<double>();
+    g.Bp = bp.as<double>();
+    g.lda = Mp;
+    g.ldb = Kp;
+    g.tiles_m = (int)(Mp / BM);
+    g.tiles_n = (int)(Np / BN);
+    g.ktiles = (int)(Kp / BK);
+    g.M = M;
+    g.N = N;
+    g.alpha = alpha;
+    g.beta = beta;
+    g.C = C->d_data();
+    g.c_blk_off = C->d_blk_off();
+    g.c_map = d_cmap;
+    g.c_nbc = C->nbc;
+    g.c_rbs = C->d_rbs();
+    g.rmap = C->d_row_map();
+    g.cmap = C->d_col_map();
+    {
+        KernelTimer kt(0, s);
+        hipLaunchKernelGGL(k_dgemm_mfma, dim3((unsigned)tiles), dim3(256), 0, s, g);
+    }
+    return launch_check("dgemm_mfma");
+}
+
+}  // namespace bsmm

@@ -1,0 +1,106 @@
+// filter.hip -- post-multiply block filter: drop every C block whose squared
+// Frobenius norm is strictly below eps^2 (a NaN norm keeps the block), then
+// compact C's index and data.
+#include "dev_util.h"
+#include "internal.h"
+
+namespace bsmm {
+
+namespace {
+
+// One wave per block: keep flag and kept element count.
+__global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *blk_off,
+                                                   const double *data, double eps2,
+                                                   int64_t *keep, int64_t *keep_elems) {
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (b >= nnzb) return;
+    const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
+    double s = 0.0;
+    for (int64_t e = lane_id(); e < len; e += kWave) {
+        const double x = data[o + e];
+        s = fma(x, x, s);
+    }
+    s = wave_sum(s);
+    if (lane_id() == 0) {
+        const int64_t k = (s < eps2) ? 0 : 1;
+        keep[b] = k;
+        keep_elems[b] = k ? len : 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_new_row_ptr(int32_t nbr, int64_t nnzb, const int64_t *rp,
+                                                     const int64_t *kpos, int64_t *new_rp,
+                                                     int64_t *new_off, int64_t total_elems) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i <= nbr) new_rp[i] = kpos[rp[i]];
+    if (i == 0) new_off[kpos[nnzb]] = total_elems;
+}
+
+// One wave per old block: kept blocks move to their new place.
+__global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci,
+                                                 const int64_t *blk_off, const double *data,
+                                                 const int64_t *kpos, const int64_t *epos,
+                                                 int32_t *new_ci, int64_t *new_off,
+                                                 double *new_data) {
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (b >= nnzb) return;
+    if (kpos[b + 1] == kpos[b]) return;  // dropped
+    const int64_t nb = kpos[b];
+    const int64_t o = blk_off[b], len = blk_off[b + 1] - o, no = epos[b];
+    if (lane_id() == 0) {
+        new_ci[nb] = ci[b];
+        new_off[nb] = no;
+    }
+    for (int64_t e = lane_id(); e < len; e += kWave) new_data[no + e] = data[o + e];
+}
+
+}  // namespace
+
+int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s) {
+    *nnzb_after = C->nnzb;
+    if (!(eps > 0.0) || C->nnzb == 0) return BSMM_OK;
+    const int64_t nnzb = C->nnzb;
+    DevBuf keep, kel, kpos, epos;
+    BSMM_TRY(keep.reserve(sizeof(int64_t) * (nnzb + 1), s));
+    BSMM_TRY(kel.reserve(sizeof(int64_t) * (nnzb + 1), s));
+    BSMM_TRY(kpos.reserve(sizeof(int64_t) * (nnzb + 1), s));
+    BSMM_TRY(epos.reserve(sizeof(int64_t) * (nnzb + 1), s));
+    hipLaunchKernelGGL(k_norm_keep, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb, C->d_blk_off(),
+                       C->d_data(), eps * eps, keep.as<int64_t>(), kel.as<int64_t>());
+    BSMM_TRY(launch_check("norm_keep"));
+    BSMM_TRY(scan_exclusive_i64(keep.as<int64_t>(), kpos.as<int64_t>(), nnzb, s));
+    BSMM_TRY(scan_exclusive_i64(kel.as<int64_t>(), epos.as<int64_t>(), nnzb, s));
+    int64_t tot[2];
+    BSMM_HIP(hipMemcpyAsync(&tot[0], kpos.as<int64_t>() + nnzb, sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(&tot[1], epos.as<int64_t>() + nnzb, sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    const int64_t new_nnzb = tot[0], new_elems = tot[1];
+    *nnzb_after = new_nnzb;
+    if (new_nnzb == nnzb) return BSMM_OK;
+
+    DevBuf n_rp, n_ci, n_off, n_data;
+    BSMM_TRY(n_rp.reserve(sizeof(int64_t) * (C->nbr + 1), s));
+    BSMM_TRY(n_ci.reserve(sizeof(int32_t) * (new_nnzb + 1), s));
+    BSMM_TRY(n_off.reserve(sizeof(int64_t) * (new_nnzb + 1), s));
+    BSMM_TRY(n_data.reserve(sizeof(double) * (new_elems + 1), s));
+    hipLaunchKernelGGL(k_new_row_ptr, dim3(grid_of(C->nbr + 1, 256)), dim3(256), 0, s, C->nbr,
+                       nnzb, C->d_row_ptr(), (const int64_t *)kpos.as<int64_t>(), n_rp.as<int64_t>(),
+                       n_off.as<int64_t>(), new_elems);
+    BSMM_TRY(launch_check("new_row_ptr"));
+    hipLaunchKernelGGL(k_compact, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb, C->d_col_ind(),
+                       C->d_blk_off(), C->d_data(), (const int64_t *)kpos.as<int64_t>(),
+                       (const int64_t *)epos.as<int64_t>(), n_ci.as<int32_t>(), n_off.as<int64_t>(),
+                       n_data.as<double>());
+    BSMM_TRY(launch_check("compact"));
+    C->b_row_ptr = std::move(n_rp);
+    C->b_col_ind = std::move(n_ci);
+    C->b_blk_off = std::move(n_off);
+    C->b_data = std::move(n_data);
+    C->nnzb = new_nnzb;
+    C->nelems = new_elems;
+    return BSMM_OK;
+}
+
+}  // namespace bsmm

@@ -1,0 +1,314 @@
+// index.hip -- block offsets, the symbolic C pattern, relayout and scaling.
+//
+// Symbolic phase (paper, Sec. II, start of the Generation phase): the new C
+// pattern is the old one united with {(I,J) : some K has A(I,K) and B(K,J)}.
+// One workgroup owns one block row I of C (the paper's race-free row
+// ownership) and builds the row's column set as a bitmap in LDS.
+#include "dev_util.h"
+#include "internal.h"
+
+namespace bsmm {
+
+namespace {
+
+constexpr int kRowThreads = 256;
+constexpr int kMaxBitmapWords = 16384;  // 64 KB of LDS: up to 524288 block columns
+
+// ------------------------------------------------------------ offsets
+// One wave per block row: blk_off[p] = row_base[I] + m_I * (sum of the
+// column sizes of the earlier blocks of the row).
+__global__ __launch_bounds__(256) void k_block_offsets(const int32_t *rbs, const int32_t *cbs,
+                                                       int32_t nbr, const int64_t *rp,
+                                                       const int32_t *ci, const int64_t *row_base,
+                                                       int64_t *blk_off) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (row >= nbr) return;
+    const int64_t m = rbs[row];
+    int64_t base = row_base[row];
+    const int64_t p0 = rp[row], p1 = rp[row + 1];
+    for (int64_t c = p0; c < p1; c += kWave) {
+        const int64_t p = c + lane_id();
+        const int64_t v = p < p1 ? m * cbs[ci[p]] : 0;
+        const int64_t inc = wave_inclusive_scan(v);
+        if (p < p1) blk_off[p] = base + inc - v;
+        base += __shfl(inc, kWave - 1, kWave);
+    }
+    if (row == nbr - 1 && lane_id() == 0) blk_off[p1] = row_base[nbr];
+}
+
+__global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
+
+// --------------------------------------------------------- row totals
+__global__ __launch_bounds__(256) void k_row_elems(const int32_t *rbs, const int32_t *cbs,
+                                                   int32_t nbr, const int64_t *rp,
+                                                   const int32_t *ci, int64_t *row_elems) {
+    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (row >= nbr) return;
+    int64_t s = 0;
+    for (int64_t p = rp[row] + lane_id(); p < rp[row + 1]; p += kWave) s += cbs[ci[p]];
+    s = wave_sum(s);
+    if (lane_id() == 0) row_elems[row] = s * rbs[row];
+}
+
+// --------------------------------------------------------- symbolic
+// Marks the old-C columns and every column J reached through A(I,K) B(K,J)
+// in the LDS bitmap of row I.  Returns (through the accumulators) the
+// number of block products and their algorithmic flop count / (2 m_I).
+__device__ void mark_row(uint32_t *bm, int nwords, int32_t row, const int64_t *a_rp,
+                         const int32_t *a_ci, const int64_t *b_rp, const int32_t *b_ci,
+                         const int64_t *c_rp, const int32_t *c_ci, const int32_t *kbs,
+                         const int32_t *cbs, int64_t *nprod, double *kn_sum) {
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) bm[w] = 0u;
+    __syncthreads();
+    if (c_rp)
+        for (int64_t p = c_rp[row] + threadIdx.x; p < c_rp[row + 1]; p += blockDim.x) {
+            const int32_t j = c_ci[p];
+            atomicOr(&bm[j >> 5], 1u << (j & 31));
+        }
+    const int nw = blockDim.x / kWave;
+    int64_t np = 0;
+    double kn = 0.0;
+    for (int64_t pa = a_rp[row] + wave_id(); pa < a_rp[row + 1]; pa += nw) {
+        const int32_t kb = a_ci[pa];
+        const int64_t q0 = b_rp[kb], q1 = b_rp[kb + 1];
+        const double k = (double)kbs[kb];
+        for (int64_t q = q0 + lane_id(); q < q1; q += kWave) {
+            const int32_t j = b_ci[q];
+            atomicOr(&bm[j >> 5], 1u << (j & 31));
+            np += 1;
+            kn += k * (double)cbs[j];
+        }
+    }
+    *nprod = np;
+    *kn_sum = kn;
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_symbolic_count(
+    int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
+    const int32_t *b_ci, const int64_t *c_rp, const int32_t *c_ci, const int32_t *rbs,
+    const int32_t *kbs, const int32_t *cbs, int64_t *row_nnz, int64_t *row_elems,
+    int64_t *row_prod, double *row_flops) {
+    extern __shared__ uint32_t bm[];
+    __shared__ int64_t red_i[16];
+    __shared__ double red_d[16];
+    const int32_t row = blockIdx.x;
+    const int nwords = (nbc + 31) >> 5;
+    int64_t np;
+    double kn;
+    mark_row(bm, nwords, row, a_rp, a_ci, b_rp, b_ci, c_rp, c_ci, kbs, cbs, &np, &kn);
+    int64_t cnt = 0, cols = 0;
+    for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
+        uint32_t bits = bm[w];
+        cnt += __popc(bits);
+        while (bits) {
+            const int b = __ffs(bits) - 1;
+            bits &= bits - 1;
+            cols += cbs[(w << 5) + b];
+        }
+    }
+    cnt = block_sum(cnt, red_i);
+    cols = block_sum(cols, red_i);
+    np = block_sum(np, red_i);
+    kn = block_sum(kn, red_d);
+    if (threadIdx.x == 0) {
+        const int64_t m = rbs[row];
+        row_nnz[row] = cnt;
+        row_elems[row] = m * cols;
+        row_prod[row] = np;
+        row_flops[row] = 2.0 * (double)m * kn;
+    }
+}
+
+__global__ __launch_bounds__(kRowThreads) void k_symbolic_fill(
+    int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
+    const int32_t *b_ci, const int64_t *c_rp, const int32_t *c_ci, const int32_t *kbs,
+    const int32_t *cbs, const int64_t *new_rp, int32_t *new_ci) {
+    extern __shared__ uint32_t bm[];
+    __shared__ int64_t red[16];
+    const int32_t row = blockIdx.x;
+    const int nwords = (nbc + 31) >> 5;
+    int64_t np;
+    double kn;
+    mark_row(bm, nwords, row, a_rp, a_ci, b_rp, b_ci, c_rp, c_ci, kbs, cbs, &np, &kn);
+    int64_t out = new_rp[row];
+    for (int w0 = 0; w0 < nwords; w0 += blockDim.x) {
+        const int w = w0 + threadIdx.x;
+        const uint32_t bits = w < nwords ? bm[w] : 0u;
+        int64_t total;
+        const int64_t pos = out + block_exclusive_scan((int64_t)__popc(bits), red, &total);
+        uint32_t b = bits;
+        int64_t k = 0;
+        while (b) {
+            const int bit = __ffs(b) - 1;
+            b &= b - 1;
+            new_ci[pos + k] = (w << 5) + bit;
+            ++k;
+        }
+        out += total;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_full_pattern(int32_t nbr, int32_t nbc, int64_t *rp,
+                                                      int32_t *ci, int64_t *row_elems,
+                                                      const int32_t *rbs, int64_t ncols) {
+    const int64_t total = (int64_t)nbr * nbc;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x)
+        ci[e] = (int32_t)(e % nbc);
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nbr;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        rp[i] = i * nbc;
+        if (i < nbr) row_elems[i] = (int64_t)rbs[i] * ncols;
+    }
+}
+
+// ---------------------------------------------------------- relayout
+// One workgroup per new block row; each wave copies whole blocks: the old
+// block (found by binary search in the old row) or zeros.
+__global__ __launch_bounds__(256) void k_relayout(const int32_t *rbs, const int32_t *cbs,
+                                                  const int64_t *o_rp, const int32_t *o_ci,
+                                                  const int64_t *o_off, const double *o_data,
+                                                  const int64_t *n_rp, const int32_t *n_ci,
+                                                  const int64_t *n_off, double *n_data) {
+    const int32_t row = blockIdx.x;
+    const int nw = blockDim.x / kWave;
+    const int64_t m = rbs[row];
+    for (int64_t p = n_rp[row] + wave_id(); p < n_rp[row + 1]; p += nw) {
+        const int32_t j = n_ci[p];
+        int64_t lo = o_rp[row], hi = o_rp[row + 1], found = -1;
+        while (lo < hi) {
+            const int64_t mid = lo + (hi - lo) / 2;
+            const int32_t c = o_ci[mid];
+            if (c < j) lo = mid + 1;
+            else if (c > j) hi = mid;
+            else { found = mid; break; }
+        }
+        const int64_t len = m * cbs[j];
+        double *dst = n_data + n_off[p];
+        if (found >= 0) {
+            const double *src = o_data + o_off[found];
+            for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = src[e];
+        } else {
+            for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = 0.0;
+        }
+    }
+}
+
+// One wave per block: data *= beta, or zeros when beta == 0, for the blocks
+// whose flag is zero.
+__global__ __launch_bounds__(256) void k_scale_blocks(int64_t nnzb, const int64_t *blk_off,
+                                                      const int64_t *flags, double beta,
+                                                      double *data) {
+    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (b >= nnzb) return;
+    if (flags && flags[b] != 0) return;
+    double *d = data + blk_off[b];
+    const int64_t len = blk_off[b + 1] - blk_off[b];
+    if (beta == 0.0)
+        for (int64_t e = lane_id(); e < len; e += kWave) d[e] = 0.0;
+    else
+        for (int64_t e = lane_id(); e < len; e += kWave) d[e] *= beta;
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero(double *p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0.0;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- host side
+int build_block_offsets(const int32_t *d_rbs, const int32_t *d_cbs, int32_t nbr,
+                        const int64_t *d_row_ptr, const int32_t *d_col_ind, int64_t nnzb,
+                        int64_t *d_blk_off, const int64_t *d_row_elems, hipStream_t s) {
+    (void)nnzb;
+    if (nbr == 0) {
+        hipLaunchKernelGGL(k_set_i64, dim3(1), dim3(1), 0, s, d_blk_off, (int64_t)0);
+        return launch_check("set_i64");
+    }
+    DevBuf row_elems, row_base;
+    BSMM_TRY(row_base.reserve(sizeof(int64_t) * (nbr + 1), s));
+    if (!d_row_elems) {
+        BSMM_TRY(row_elems.reserve(sizeof(int64_t) * (nbr + 1), s));
+        hipLaunchKernelGGL(k_row_elems, dim3(grid_of(nbr, 4)), dim3(256), 0, s, d_rbs, d_cbs, nbr,
+                           d_row_ptr, d_col_ind, row_elems.as<int64_t>());
+        BSMM_TRY(launch_check("row_elems"));
+        d_row_elems = row_elems.as<int64_t>();
+    }
+    BSMM_TRY(scan_exclusive_i64(d_row_elems, row_base.as<int64_t>(), nbr, s));
+    hipLaunchKernelGGL(k_block_offsets, dim3(grid_of(nbr, 4)), dim3(256), 0, s, d_rbs, d_cbs, nbr,
+                       d_row_ptr, d_col_ind, (const int64_t *)row_base.as<int64_t>(), d_blk_off);
+    return launch_check("block_offsets");
+}
+
+static int bitmap_lds_bytes(int32_t nbc, size_t *bytes) {
+    const int64_t nwords = (nbc + 31) / 32;
+    if (nwords > kMaxBitmapWords) {
+        set_error(BSMM_ENOTSUP, "more than %d block columns in C", kMaxBitmapWords * 32);
+        return BSMM_ENOTSUP;
+    }
+    *bytes = (size_t)(nwords > 0 ? nwords : 1) * sizeof(uint32_t);
+    return BSMM_OK;
+}
+
+int symbolic_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                   int64_t *d_row_nnz, int64_t *d_row_elems, int64_t *d_row_prod,
+                   double *d_row_flops, hipStream_t s) {
+    if (A->nbr == 0) return BSMM_OK;
+    size_t lds;
+    BSMM_TRY(bitmap_lds_bytes(B->nbc, &lds));
+    const bool has_c = C && C->nnzb > 0;
+    hipLaunchKernelGGL(k_symbolic_count, dim3(A->nbr), dim3(kRowThreads), lds, s, B->nbc,
+                       A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
+                       has_c ? C->d_row_ptr() : nullptr, has_c ? C->d_col_ind() : nullptr,
+                       A->d_rbs(), B->d_rbs(), B->d_cbs(), d_row_nnz, d_row_elems, d_row_prod,
+                       d_row_flops);
+    return launch_check("symbolic_count");
+}
+
+int symbolic_fill(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                  const int64_t *d_new_row_ptr, int32_t *d_new_col_ind, hipStream_t s) {
+    if (A->nbr == 0) return BSMM_OK;
+    size_t lds;
+    BSMM_TRY(bitmap_lds_bytes(B->nbc, &lds));
+    const bool has_c = C && C->nnzb > 0;
+    hipLaunchKernelGGL(k_symbolic_fill, dim3(A->nbr), dim3(kRowThreads), lds, s, B->nbc,
+                       A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
+                       has_c ? C->d_row_ptr() : nullptr, has_c ? C->d_col_ind() : nullptr,
+                       B->d_rbs(), B->d_cbs(), d_new_row_ptr, d_new_col_ind);
+    return launch_check("symbolic_fill");
+}
+
+int full_pattern(int32_t nbr, int32_t nbc, int64_t ncols, int64_t *d_row_ptr,
+                 int32_t *d_col_ind, int64_t *d_row_elems, const int32_t *d_rbs, hipStream_t s) {
+    const int64_t total = (int64_t)nbr * nbc;
+    hipLaunchKernelGGL(k_full_pattern, dim3(grid_of(std::max<int64_t>(total, nbr + 1), 256, 8192)),
+                       dim3(256), 0, s, nbr, nbc, d_row_ptr, d_col_ind, d_row_elems, d_rbs, ncols);
+    return launch_check("full_pattern");
+}
+
+int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *d_new_ci,
+             const int64_t *d_new_off, double *d_new_data, hipStream_t s) {
+    if (Cold->nbr == 0) return BSMM_OK;
+    hipLaunchKernelGGL(k_relayout, dim3(Cold->nbr), dim3(256), 0, s, Cold->d_rbs(), Cold->d_cbs(),
+                       Cold->d_row_ptr(), Cold->d_col_ind(), Cold->d_blk_off(), Cold->d_data(),
+                       d_new_rp, d_new_ci, d_new_off, d_new_data);
+    return launch_check("relayout");
+}
+
+int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hipStream_t s) {
+    if (C->nnzb == 0) return BSMM_OK;
+    hipLaunchKernelGGL(k_scale_blocks, dim3(grid_of(C->nnzb, 4)), dim3(256), 0, s, C->nnzb,
+                       C->d_blk_off(), d_flags, beta, C->d_data());
+    return launch_check("scale_blocks");
+}
+
+int fill_zero(double *p, int64_t n, hipStream_t s) {
+    if (n <= 0) return BSMM_OK;
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_of(n, 256, 16384)), dim3(256), 0, s, p, n);
+    return launch_check("fill_zero");
+}
+
+}  // namespace bsmm

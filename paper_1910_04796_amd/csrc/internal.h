@@ -1,0 +1,225 @@
+// internal.h -- shared declarations of the bsmm library (not installed).
+//
+// Layout of a matrix in device memory (one handle, all owned by the handle):
+//   d_rbs/d_cbs        int32 block sizes
+//   d_row_off/d_col_off int64 element offset of every block row / column
+//   d_row_map/d_col_map int2 per element row / column: (block, index inside)
+//   d_row_ptr/d_col_ind int64[nbr+1] / int32[nnzb] block-CSR pattern
+//   d_blk_off          int64[nnzb+1] element offset of every block
+//   d_data             FP64 blocks, CSR order, column-major inside a block
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/bsmm.h"
+
+namespace bsmm {
+
+// ------------------------------------------------------------------ errors
+void set_error(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+int last_code();
+
+#define BSMM_HIP(call)                                                                   \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess) {                                                          \
+            ::bsmm::set_error(BSMM_EDEVICE, "%s failed: %s (%s:%d)", #call,              \
+                              hipGetErrorString(e_), __FILE__, __LINE__);                \
+            return BSMM_EDEVICE;                                                         \
+        }                                                                                \
+    } while (0)
+
+#define BSMM_TRY(expr)                  \
+    do {                                \
+        int s_ = (expr);                \
+        if (s_ != BSMM_OK) return s_;   \
+    } while (0)
+
+// Checks the last kernel launch.
+int launch_check(const char *what);
+
+// --------------------------------------------------------------- options
+struct Options {
+    int path = 0;          // 0 auto, 1 stack, 2 dense
+    int stack_kernel = 0;  // 0 plain, 1 tuned
+    int64_t stack_chunk = 0;
+    int time_kernels = 0;
+    std::string tune_db;
+};
+Options &options();
+
+// Brackets one kernel launch with HIP events when "time_kernels" is on.
+// kind 0: dense GEMM, kind 1: small-block stack kernel.
+class KernelTimer {
+  public:
+    KernelTimer(int kind, hipStream_t s);
+    ~KernelTimer();
+
+  private:
+    int kind_;
+    hipStream_t s_;
+    void *a_ = nullptr, *b_ = nullptr;
+};
+
+// ------------------------------------------------------------ device pool
+// Device memory comes from the registered provider (default hipMalloc) and
+// is cached by the library; blocks are stream-ordered on the stream they
+// were last used on.
+void *dev_alloc(size_t bytes, hipStream_t s);
+void dev_free(void *p, hipStream_t s);
+int pool_release_all();
+
+// A device buffer owned by RAII (freed back to the pool).
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+    hipStream_t s = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    DevBuf(DevBuf &&o) noexcept { *this = std::move(o); }
+    DevBuf &operator=(DevBuf &&o) noexcept {
+        if (this != &o) {
+            reset();
+            p = o.p; bytes = o.bytes; s = o.s;
+            o.p = nullptr; o.bytes = 0;
+        }
+        return *this;
+    }
+    ~DevBuf() { reset(); }
+    void reset() {
+        if (p) dev_free(p, s);
+        p = nullptr;
+        bytes = 0;
+    }
+    // Ensures capacity >= n bytes (contents are not preserved).
+    int reserve(size_t n, hipStream_t st) {
+        s = st;
+        if (n <= bytes && p) return BSMM_OK;
+        reset();
+        size_t want = n ? n : 1;
+        p = dev_alloc(want, st);
+        if (!p) {
+            set_error(BSMM_ENOMEM, "device allocation of %zu bytes failed", want);
+            return BSMM_ENOMEM;
+        }
+        bytes = want;
+        return BSMM_OK;
+    }
+    template <class T> T *as() const { return static_cast<T *>(p); }
+};
+
+}  // namespace bsmm
+
+// ------------------------------------------------------------------ matrix
+struct bsmm_matrix_s {
+    int32_t nbr = 0, nbc = 0;
+    std::vector<int32_t> rbs, cbs;          // host copies of the block sizes
+    std::vector<int64_t> row_off, col_off;  // host element offsets (nbr+1, nbc+1)
+    int64_t nnzb = 0, nelems = 0;
+    int32_t max_rbs = 0, max_cbs = 0;
+    int device = 0;
+    hipStream_t last_stream = nullptr;
+
+    bsmm::DevBuf b_rbs, b_cbs, b_row_off, b_col_off, b_row_map, b_col_map;
+    bsmm::DevBuf b_row_ptr, b_col_ind, b_blk_off, b_data;
+
+    int32_t *d_rbs() const { return b_rbs.as<int32_t>(); }
+    int32_t *d_cbs() const { return b_cbs.as<int32_t>(); }
+    int64_t *d_row_off() const { return b_row_off.as<int64_t>(); }
+    int64_t *d_col_off() const { return b_col_off.as<int64_t>(); }
+    int2 *d_row_map() const { return b_row_map.as<int2>(); }
+    int2 *d_col_map() const { return b_col_map.as<int2>(); }
+    int64_t *d_row_ptr() const { return b_row_ptr.as<int64_t>(); }
+    int32_t *d_col_ind() const { return b_col_ind.as<int32_t>(); }
+    int64_t *d_blk_off() const { return b_blk_off.as<int64_t>(); }
+    double *d_data() const { return b_data.as<double>(); }
+    int64_t rows() const { return row_off.empty() ? 0 : row_off.back(); }
+    int64_t cols() const { return col_off.empty() ? 0 : col_off.back(); }
+    bool full() const { return nnzb == (int64_t)nbr * (int64_t)nbc; }
+};
+
+namespace bsmm {
+
+// ------------------------------------------------------- device utilities
+// Exclusive prefix sum of n int64 values: out[0..n] with out[n] = total.
+// in and out may alias.  Temporary storage comes from the pool.
+int scan_exclusive_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- index
+// Builds d_blk_off (int64[nnzb+1]) of a pattern from per-row element totals
+// (computed here when d_row_elems is null): scan, then per-row offsets.
+int build_block_offsets(const int32_t *d_rbs, const int32_t *d_cbs, int32_t nbr,
+                        const int64_t *d_row_ptr, const int32_t *d_col_ind, int64_t nnzb,
+                        int64_t *d_blk_off, const int64_t *d_row_elems, hipStream_t s);
+
+// Symbolic phase: per block row of C, the size of old-C united with the
+// product pattern.  Outputs per row: block count, element count, product
+// count and algorithmic flops.
+struct SymbolicTotals {
+    int64_t nnzb = 0, nelems = 0, nprod = 0;
+    double flops = 0.0;
+};
+int symbolic_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                   int64_t *d_row_nnz, int64_t *d_row_elems, int64_t *d_row_prod,
+                   double *d_row_flops, hipStream_t s);
+int symbolic_fill(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                  const int64_t *d_new_row_ptr, int32_t *d_new_col_ind, hipStream_t s);
+// Every block present: row_ptr[i] = i*nbc, col_ind = 0..nbc-1 per row,
+// row_elems[i] = rbs[i] * ncols.
+int full_pattern(int32_t nbr, int32_t nbc, int64_t ncols, int64_t *d_row_ptr,
+                 int32_t *d_col_ind, int64_t *d_row_elems, const int32_t *d_rbs, hipStream_t s);
+// Copies old C blocks into the new layout (zeros for new blocks).
+int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *d_new_ci,
+             const int64_t *d_new_off, double *d_new_data, hipStream_t s);
+// data *= beta (beta == 0 writes zeros) over the blocks whose flag is zero
+// (flags == nullptr: every block).
+int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hipStream_t s);
+int fill_zero(double *p, int64_t n, hipStream_t s);
+
+// ---------------------------------------------------------------- stacks
+// Product stacks of C += A*B, grouped by shape class (m, n).
+struct Stacks {
+    int64_t n_runs = 0, n_prod = 0;
+    int32_t n_classes = 0;            // distinct (m, n) classes (all, including empty)
+    int32_t nrs = 0, ncs = 0;         // distinct row sizes / column sizes of C
+    std::vector<int32_t> row_sizes;   // sorted distinct C block-row sizes
+    std::vector<int32_t> col_sizes;   // sorted distinct C block-column sizes
+    std::vector<int64_t> class_begin; // run range of class cl: [cb[cl], cb[cl+1])
+    DevBuf run_cblk;   // int64[n_runs]   C block index
+    DevBuf run_coff;   // int64[n_runs]   C element offset
+    DevBuf run_ptr;    // int64[n_runs+1] first product
+    DevBuf run_class;  // int32[n_runs]
+    DevBuf prods;      // ulonglong2[n_prod]: {a_off | k << 48, b_off}
+    DevBuf c_count;    // int64[C.nnzb]   products per C block
+};
+int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                 Stacks &st, hipStream_t s);
+
+// --------------------------------------------------------- small blocks
+int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
+               const Stacks &st, double alpha, double beta, hipStream_t s);
+
+// ----------------------------------------------------------------- dense
+int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
+                   double alpha, double beta, hipStream_t s);
+
+// ---------------------------------------------------------------- filter
+int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s);
+
+// --------------------------------------------------------------- helpers
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline unsigned grid_of(int64_t n, int64_t per, int64_t cap = 1 << 30) {
+    int64_t g = ceil_div(n, per);
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+}  // namespace bsmm

@@ -1,0 +1,263 @@
+// multiply.hip -- orchestration of C <- filter_eps(beta*C + alpha*A*B).
+//
+// Order of the phases (paper, Sec. II: Traversal, Generation, Scheduler;
+// Sec. III: densification):
+//   1. symbolic: new C pattern = old pattern U product pattern; one host
+//      read of the totals; new C storage with the old blocks moved in;
+//   2. numeric: dense inputs -> merged panels + one FP64 MFMA GEMM with the
+//      undensify step fused into its epilogue; otherwise stacks of block
+//      products grouped by shape -> batched small-block kernels;
+//   3. filter.
+#include <algorithm>
+
+#include "dev_util.h"
+#include "internal.h"
+
+namespace bsmm {
+int validate_multiply(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, double eps);
+bsmm_multiply_stats &stats();
+
+namespace {
+
+// Sums of the per-row symbolic counts: out_i[0..2] (nnz, elems, products),
+// out_d[0] (flops).
+__global__ __launch_bounds__(256) void k_row_totals(int32_t nbr, const int64_t *nnz,
+                                                    const int64_t *elems, const int64_t *prod,
+                                                    const double *flops, int64_t *out_i,
+                                                    double *out_d) {
+    __shared__ int64_t ri[16];
+    __shared__ double rd[16];
+    int64_t a = 0, b = 0, c = 0;
+    double d = 0.0;
+    for (int64_t i = threadIdx.x; i < nbr; i += blockDim.x) {
+        a += nnz[i];
+        b += elems[i];
+        c += prod[i];
+        d += flops[i];
+    }
+    a = block_sum(a, ri);
+    b = block_sum(b, ri);
+    c = block_sum(c, ri);
+    d = block_sum(d, rd);
+    if (threadIdx.x == 0) {
+        out_i[0] = a;
+        out_i[1] = b;
+        out_i[2] = c;
+        out_d[0] = d;
+    }
+}
+
+struct NewPattern {
+    DevBuf rp, ci, off, data;
+};
+
+// Symbolic phase.  On return *tot holds the new C sizes, the product count
+// and the algorithmic flops; if the pattern grows, np holds the new index
+// (and row element totals in row_elems).
+int symbolic(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, SymbolicTotals *tot,
+             bool *changed, NewPattern &np, DevBuf &row_elems, hipStream_t s) {
+    const int32_t nbr = A->nbr, nbk = A->nbc, nbc = B->nbc;
+    *changed = false;
+    if (nbr == 0 || nbc == 0) return BSMM_OK;
+    const bool closed_form = A->full() && B->full() && nbk > 0;
+    BSMM_TRY(row_elems.reserve(sizeof(int64_t) * (nbr + 1), s));
+    if (closed_form) {
+        // Every (I,K,J) is a product: the new pattern is every block.
+        const double M = (double)A->rows(), K = (double)A->cols(), N = (double)B->cols();
+        tot->nnzb = (int64_t)nbr * nbc;
+        tot->nelems = A->rows() * B->cols();
+        tot->nprod = (int64_t)nbr * nbk * nbc;
+        tot->flops = 2.0 * M * N * K;
+        if (tot->nnzb == C->nnzb) return BSMM_OK;
+        *changed = true;
+        BSMM_TRY(np.rp.reserve(sizeof(int64_t) * (nbr + 1), s));
+        BSMM_TRY(np.ci.reserve(sizeof(int32_t) * (tot->nnzb + 1), s));
+        BSMM_TRY(full_pattern(nbr, nbc, B->cols(), np.rp.as<int64_t>(), np.ci.as<int32_t>(),
+                              row_elems.as<int64_t>(), C->d_rbs(), s));
+        return BSMM_OK;
+    }
+    DevBuf rnnz, rprod, rflops, sums_i, sums_d;
+    BSMM_TRY(rnnz.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(rprod.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(rflops.reserve(sizeof(double) * (nbr + 1), s));
+    BSMM_TRY(sums_i.reserve(sizeof(int64_t) * 4, s));
+    BSMM_TRY(sums_d.reserve(sizeof(double) * 2, s));
+    BSMM_TRY(symbolic_count(A, B, C, rnnz.as<int64_t>(), row_elems.as<int64_t>(),
+                            rprod.as<int64_t>(), rflops.as<double>(), s));
+    hipLaunchKernelGGL(k_row_totals, dim3(1), dim3(256), 0, s, nbr,
+                       (const int64_t *)rnnz.as<int64_t>(), (const int64_t *)row_elems.as<int64_t>(),
+                       (const int64_t *)rprod.as<int64_t>(), (const double *)rflops.as<double>(),
+                       sums_i.as<int64_t>(), sums_d.as<double>());
+    BSMM_TRY(launch_check("row_totals"));
+    int64_t hi[3];
+    double hd[1];
+    BSMM_HIP(hipMemcpyAsync(hi, sums_i.p, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(hd, sums_d.p, sizeof(hd), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    tot->nnzb = hi[0];
+    tot->nelems = hi[1];
+    tot->nprod = hi[2];
+    tot->flops = hd[0];
+    if (tot->nnzb > (int64_t)INT32_MAX || tot->nelems >= (int64_t(1) << 47)) {
+        set_error(BSMM_ERANGE, "result too large (%lld blocks, %lld elements)",
+                  (long long)tot->nnzb, (long long)tot->nelems);
+        return BSMM_ERANGE;
+    }
+    // The new pattern contains the old one, so equal counts mean equal sets.
+    if (tot->nnzb == C->nnzb) return BSMM_OK;
+    *changed = true;
+    BSMM_TRY(np.rp.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(np.ci.reserve(sizeof(int32_t) * (tot->nnzb + 1), s));
+    BSMM_TRY(scan_exclusive_i64(rnnz.as<int64_t>(), np.rp.as<int64_t>(), nbr, s));
+    return symbolic_fill(A, B, C, np.rp.as<int64_t>(), np.ci.as<int32_t>(), s);
+}
+
+// Installs a grown pattern into C, moving the old blocks in when beta != 0.
+int install_pattern(bsmm_matrix_s *C, const SymbolicTotals &tot, NewPattern &np,
+                    const DevBuf &row_elems, double beta, hipStream_t s) {
+    BSMM_TRY(np.off.reserve(sizeof(int64_t) * (tot.nnzb + 1), s));
+    BSMM_TRY(np.data.reserve(sizeof(double) * (tot.nelems + 1), s));
+    BSMM_TRY(build_block_offsets(C->d_rbs(), C->d_cbs(), C->nbr, np.rp.as<int64_t>(),
+                                 np.ci.as<int32_t>(), tot.nnzb, np.off.as<int64_t>(),
+                                 row_elems.as<int64_t>(), s));
+    // beta != 0 reads the old values: move the old blocks in (new blocks get
+    // zeros), or zero everything when there were no old blocks.  beta == 0
+    // never reads C, so the new storage is left as is.
+    if (beta != 0.0) {
+        if (C->nnzb > 0)
+            BSMM_TRY(relayout(C, np.rp.as<int64_t>(), np.ci.as<int32_t>(), np.off.as<int64_t>(),
+                              np.data.as<double>(), s));
+        else
+            BSMM_TRY(fill_zero(np.data.as<double>(), tot.nelems, s));
+    }
+    C->b_row_ptr = std::move(np.rp);
+    C->b_col_ind = std::move(np.ci);
+    C->b_blk_off = std::move(np.off);
+    C->b_data = std::move(np.data);
+    C->nnzb = tot.nnzb;
+    C->nelems = tot.nelems;
+    return BSMM_OK;
+}
+
+int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
+                  bsmm_matrix_s *C, double eps, hipStream_t s) {
+    bsmm_multiply_stats &stt = stats();
+    stt = bsmm_multiply_stats{};
+    SymbolicTotals tot;
+    bool changed = false;
+    NewPattern np;
+    DevBuf row_elems;
+    BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s));
+    if (changed) BSMM_TRY(install_pattern(C, tot, np, row_elems, beta, s));
+    stt.c_nnzb_before = C->nnzb;
+    stt.n_products = tot.nprod;
+    stt.flops = tot.flops;
+
+    const Options &o = options();
+    const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
+    if (alpha == 0.0 || tot.nprod == 0) {
+        if (beta != 1.0) BSMM_TRY(scale_blocks(C, nullptr, beta, s));
+        stt.path = 0;
+    } else if (dense) {
+        stt.path = 2;
+        BSMM_TRY(dense_multiply(A, B, C, alpha, beta, s));
+    } else {
+        stt.path = 1;
+        Stacks st;
+        st.n_prod = tot.nprod;
+        BSMM_TRY(build_stacks(A, B, C, st, s));
+        stt.n_runs = st.n_runs;
+        int nc = 0;
+        for (int cl = 0; cl < st.n_classes; ++cl) nc += st.class_begin[cl + 1] > st.class_begin[cl];
+        stt.n_classes = nc;
+        BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s));
+        if (beta != 1.0 && st.n_runs < C->nnzb)
+            BSMM_TRY(scale_blocks(C, st.c_count.as<int64_t>(), beta, s));
+    }
+    int64_t after = C->nnzb;
+    BSMM_TRY(filter_blocks(C, eps, &after, s));
+    stt.c_nnzb_after = after;
+    return BSMM_OK;
+}
+
+}  // namespace
+}  // namespace bsmm
+
+using namespace bsmm;
+
+extern "C" int bsmm_multiply(double alpha, bsmm_matrix A, bsmm_matrix B, double beta,
+                             bsmm_matrix C, double filter_eps, void *stream) {
+    clear_error();
+    BSMM_TRY(validate_multiply(A, B, C, filter_eps));
+    hipStream_t s = (hipStream_t)stream;
+    const int st = multiply_impl(alpha, A, B, beta, C, filter_eps, s);
+    A->last_stream = B->last_stream = C->last_stream = s;
+    return st;
+}
+
+extern "C" int bsmm_inspect_stacks(bsmm_matrix A, bsmm_matrix B, bsmm_matrix C, int64_t *n_runs,
+                                   int64_t *n_products, int64_t *run_cblk, int32_t *run_class,
+                                   int64_t *run_ptr, int64_t *prod_ablk, int64_t *prod_bblk,
+                                   void *stream) {
+    clear_error();
+    if (!n_runs || !n_products) {
+        set_error(BSMM_EINVAL, "count pointers are NULL");
+        return BSMM_EINVAL;
+    }
+    BSMM_TRY(validate_multiply(A, B, C, 0.0));
+    hipStream_t s = (hipStream_t)stream;
+    SymbolicTotals tot;
+    bool changed = false;
+    NewPattern np;
+    DevBuf row_elems;
+    BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s));
+    if (changed) {
+        set_error(BSMM_EINDEX, "C pattern does not contain every product block");
+        return BSMM_EINDEX;
+    }
+    Stacks st;
+    st.n_prod = tot.nprod;
+    BSMM_TRY(build_stacks(A, B, C, st, s));
+    const int64_t cap_r = *n_runs, cap_p = *n_products;
+    *n_runs = st.n_runs;
+    *n_products = st.n_prod;
+    if (!run_cblk && !run_class && !run_ptr && !prod_ablk && !prod_bblk) return BSMM_OK;
+    if (cap_r < st.n_runs || cap_p < st.n_prod) {
+        set_error(BSMM_ERANGE, "output capacity too small");
+        return BSMM_ERANGE;
+    }
+    std::vector<ulonglong2> prods(st.n_prod);
+    std::vector<int64_t> a_off(A->nnzb + 1), b_off(B->nnzb + 1);
+    if (st.n_runs > 0) {
+        if (run_cblk)
+            BSMM_HIP(hipMemcpyAsync(run_cblk, st.run_cblk.p, sizeof(int64_t) * st.n_runs,
+                                    hipMemcpyDeviceToHost, s));
+        if (run_class)
+            BSMM_HIP(hipMemcpyAsync(run_class, st.run_class.p, sizeof(int32_t) * st.n_runs,
+                                    hipMemcpyDeviceToHost, s));
+        if (run_ptr)
+            BSMM_HIP(hipMemcpyAsync(run_ptr, st.run_ptr.p, sizeof(int64_t) * (st.n_runs + 1),
+                                    hipMemcpyDeviceToHost, s));
+    } else if (run_ptr) {
+        run_ptr[0] = 0;
+    }
+    if (st.n_prod > 0)
+        BSMM_HIP(hipMemcpyAsync(prods.data(), st.prods.p, sizeof(ulonglong2) * st.n_prod,
+                                hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(a_off.data(), A->d_blk_off(), sizeof(int64_t) * (A->nnzb + 1),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(b_off.data(), B->d_blk_off(), sizeof(int64_t) * (B->nnzb + 1),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    // Element offsets back to block indices (offsets are strictly increasing
+    // because every block holds at least one element).
+    for (int64_t p = 0; p < st.n_prod; ++p) {
+        const int64_t ao = (int64_t)(prods[p].x & ((1ull << 48) - 1));
+        const int64_t bo = (int64_t)prods[p].y;
+        if (prod_ablk)
+            prod_ablk[p] = std::lower_bound(a_off.begin(), a_off.end() - 1, ao) - a_off.begin();
+        if (prod_bblk)
+            prod_bblk[p] = std::lower_bound(b_off.begin(), b_off.end() - 1, bo) - b_off.begin();
+    }
+    return BSMM_OK;
+}

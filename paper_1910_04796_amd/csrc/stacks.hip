@@ -1,0 +1,290 @@
+// stacks.hip -- the stack builder: block-CSR indices -> stacks of block
+// products grouped by shape.
+//
+// Paper, Sec. II (Traversal and Generation phases): the local multiply walks
+// the A block rows and, for each, the B block columns, and collects the
+// pairwise block products in batches.  Here every product (I,K,J) becomes
+// an entry {A offset, k, B offset} of the "run" of its C block (I,J): all
+// products that update one C block are contiguous, in ascending K, and a
+// run has exactly one owner during execution, so no two workers ever write
+// the same C block (the paper's race-free static ownership, here per block
+// instead of per block row).  Runs are grouped by the shape class (m, n) of
+// their C block and, inside a class, kept in C's CSR order, which is the
+// paper's traversal order (A row blocks outer, B column blocks inner).
+//
+// Phases (all on the GPU, one workgroup per C block row where a row is the
+// unit):
+//   1. count    products per C block, through an LDS map column -> slot;
+//   2. classify counting sort of the C blocks that receive products by
+//               class, stable in CSR order (per-tile histograms, a scan,
+//               wave-level ranking with ballots);
+//   3. offsets  scan of the product counts in run order;
+//   4. fill     products written per row, K ascending.
+#include <algorithm>
+
+#include "dev_util.h"
+#include "internal.h"
+
+namespace bsmm {
+
+namespace {
+
+constexpr int kMapMaxCols = 8192;   // LDS map + counters: 64 KB
+constexpr int kTile = 1024;         // C blocks per classification tile
+constexpr int kMaxClasses = 1024;   // distinct (m, n) shapes
+
+__global__ __launch_bounds__(256) void k_stack_count(int32_t nbc, const int64_t *a_rp,
+                                                     const int32_t *a_ci, const int64_t *b_rp,
+                                                     const int32_t *b_ci, const int64_t *c_rp,
+                                                     const int32_t *c_ci, int64_t *c_count,
+                                                     int32_t *c_row, int32_t *missing) {
+    extern __shared__ int32_t lds[];
+    int32_t *map = lds;          // nbc entries: column -> slot in the C row, or -1
+    int32_t *cnt = lds + nbc;    // row length entries
+    const int32_t row = blockIdx.x;
+    const int64_t p0 = c_rp[row];
+    const int32_t len = (int32_t)(c_rp[row + 1] - p0);
+    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
+    __syncthreads();
+    for (int s = threadIdx.x; s < len; s += blockDim.x) {
+        map[c_ci[p0 + s]] = s;
+        cnt[s] = 0;
+    }
+    __syncthreads();
+    const int nw = blockDim.x / kWave;
+    for (int64_t pa = a_rp[row] + wave_id(); pa < a_rp[row + 1]; pa += nw) {
+        const int32_t kb = a_ci[pa];
+        for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
+            const int32_t s = map[b_ci[q]];
+            if (s >= 0) atomicAdd(&cnt[s], 1);
+            else *missing = 1;
+        }
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < len; s += blockDim.x) {
+        c_count[p0 + s] = cnt[s];
+        c_row[p0 + s] = row;
+    }
+}
+
+__device__ __forceinline__ int class_of(int64_t c, const int32_t *c_row, const int32_t *c_ci,
+                                        const int32_t *rsi, const int32_t *csi, int ncs) {
+    return rsi[c_row[c]] * ncs + csi[c_ci[c]];
+}
+
+// One wave per tile of kTile C blocks: per-class counts of the blocks that
+// receive products, written class-major (hist[cl * ntiles + tile]).
+__global__ __launch_bounds__(256) void k_class_hist(int64_t nnzb, int64_t ntiles,
+                                                    const int64_t *c_count, const int32_t *c_row,
+                                                    const int32_t *c_ci, const int32_t *rsi,
+                                                    const int32_t *csi, int ncs, int ncl,
+                                                    int64_t *hist) {
+    extern __shared__ int32_t lds[];
+    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    int32_t *cnt = lds + wave_id() * ncl;
+    if (tile >= ntiles) return;
+    for (int cl = lane_id(); cl < ncl; cl += kWave) cnt[cl] = 0;
+    wave_lds_sync();
+    const int64_t end = std::min<int64_t>(nnzb, (tile + 1) * kTile);
+    for (int64_t c = tile * kTile + lane_id(); c < end; c += kWave)
+        if (c_count[c] > 0) atomicAdd(&cnt[class_of(c, c_row, c_ci, rsi, csi, ncs)], 1);
+    wave_lds_sync();
+    for (int cl = lane_id(); cl < ncl; cl += kWave) hist[(int64_t)cl * ntiles + tile] = cnt[cl];
+}
+
+// Stable scatter of the runs into class-major order.
+__global__ __launch_bounds__(256) void k_class_scatter(
+    int64_t nnzb, int64_t ntiles, const int64_t *c_count, const int32_t *c_row,
+    const int32_t *c_ci, const int64_t *c_blk_off, const int32_t *rsi, const int32_t *csi,
+    int ncs, int ncl, const int64_t *hoff, int64_t *run_cblk, int32_t *run_class,
+    int64_t *run_coff, int64_t *run_cnt, int64_t *run_of_c) {
+    extern __shared__ int64_t lds64[];
+    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    int64_t *next = lds64 + wave_id() * ncl;
+    if (tile >= ntiles) return;
+    for (int cl = lane_id(); cl < ncl; cl += kWave) next[cl] = hoff[(int64_t)cl * ntiles + tile];
+    wave_lds_sync();
+    const int64_t end = std::min<int64_t>(nnzb, (tile + 1) * kTile);
+    for (int64_t base = tile * kTile; base < end; base += kWave) {
+        const int64_t c = base + lane_id();
+        const bool inb = c < end;
+        const int64_t cnt = inb ? c_count[c] : 0;
+        const bool valid = cnt > 0;
+        const int cl = valid ? class_of(c, c_row, c_ci, rsi, csi, ncs) : -1;
+        if (inb && !valid) run_of_c[c] = -1;
+        uint64_t pending = __ballot(valid);
+        while (pending) {
+            const int leader = __ffsll((unsigned long long)pending) - 1;
+            const int cl_lead = __shfl(cl, leader, kWave);
+            const uint64_t mask = __ballot(valid && cl == cl_lead);
+            if (valid && cl == cl_lead) {
+                const int64_t r = next[cl_lead] + __popcll(mask & lanemask_lt());
+                run_cblk[r] = c;
+                run_class[r] = cl;
+                run_coff[r] = c_blk_off[c];
+                run_cnt[r] = cnt;
+                run_of_c[c] = r;
+            }
+            wave_lds_sync();
+            if (lane_id() == leader) next[cl_lead] += __popcll(mask);
+            wave_lds_sync();
+            pending &= ~mask;
+        }
+    }
+}
+
+__global__ void k_zero_i32(int32_t *p) { *p = 0; }
+
+__global__ void k_gather_class_begin(const int64_t *hoff, int64_t ntiles, int ncl, int64_t *out) {
+    for (int cl = threadIdx.x; cl <= ncl; cl += blockDim.x) out[cl] = hoff[(int64_t)cl * ntiles];
+}
+
+// Products of one C block row, K ascending inside every run.  Within one K
+// every C slot is hit at most once, so the per-slot cursors need no atomics;
+// a barrier separates consecutive K.
+__global__ __launch_bounds__(256) void k_stack_fill(int32_t nbc, const int64_t *a_rp,
+                                                    const int32_t *a_ci, const int64_t *a_off,
+                                                    const int64_t *b_rp, const int32_t *b_ci,
+                                                    const int64_t *b_off, const int32_t *kbs,
+                                                    const int64_t *c_rp, const int32_t *c_ci,
+                                                    const int64_t *run_of_c, const int64_t *run_ptr,
+                                                    ulonglong2 *prods) {
+    extern __shared__ int32_t lds[];
+    int32_t *map = lds;
+    int32_t *cur = lds + nbc;
+    const int32_t row = blockIdx.x;
+    const int64_t p0 = c_rp[row];
+    const int32_t len = (int32_t)(c_rp[row + 1] - p0);
+    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
+    __syncthreads();
+    for (int s = threadIdx.x; s < len; s += blockDim.x) {
+        map[c_ci[p0 + s]] = s;
+        cur[s] = 0;
+    }
+    __syncthreads();
+    for (int64_t pa = a_rp[row]; pa < a_rp[row + 1]; ++pa) {
+        const int32_t kb = a_ci[pa];
+        const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
+        for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
+            const int32_t s = map[b_ci[q]];
+            if (s < 0) continue;
+            const int64_t r = run_of_c[p0 + s];
+            const int64_t pos = run_ptr[r] + cur[s];
+            cur[s] += 1;
+            prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
+        }
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+// Distinct sizes of a size vector and the index of every entry.
+static void size_classes(const std::vector<int32_t> &sizes, std::vector<int32_t> &distinct,
+                         std::vector<int32_t> &index) {
+    distinct = sizes;
+    std::sort(distinct.begin(), distinct.end());
+    distinct.erase(std::unique(distinct.begin(), distinct.end()), distinct.end());
+    index.resize(sizes.size());
+    for (size_t i = 0; i < sizes.size(); ++i)
+        index[i] = (int32_t)(std::lower_bound(distinct.begin(), distinct.end(), sizes[i]) -
+                             distinct.begin());
+}
+
+// st.n_prod must hold the product count of the symbolic phase on entry.
+int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                 Stacks &st, hipStream_t s) {
+    const int32_t nbr = C->nbr, nbc = C->nbc;
+    const int64_t nnzb = C->nnzb;
+    if (nbc > kMapMaxCols) {
+        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns", kMapMaxCols);
+        return BSMM_ENOTSUP;
+    }
+    std::vector<int32_t> rsi, csi;
+    size_classes(C->rbs, st.row_sizes, rsi);
+    size_classes(C->cbs, st.col_sizes, csi);
+    st.nrs = (int32_t)st.row_sizes.size();
+    st.ncs = (int32_t)st.col_sizes.size();
+    const int ncl = st.nrs * st.ncs;
+    st.n_classes = ncl;
+    if (ncl > kMaxClasses) {
+        set_error(BSMM_ENOTSUP, "more than %d distinct block shapes", kMaxClasses);
+        return BSMM_ENOTSUP;
+    }
+    st.class_begin.assign(ncl + 1, 0);
+    st.n_runs = 0;
+    if (nbr == 0 || nnzb == 0) return BSMM_OK;
+
+    DevBuf d_rsi, d_csi, c_row, missing, hist, hoff, run_cnt, run_of_c, cb;
+    const int64_t ntiles = ceil_div(nnzb, kTile);
+    BSMM_TRY(d_rsi.reserve(sizeof(int32_t) * nbr, s));
+    BSMM_TRY(d_csi.reserve(sizeof(int32_t) * nbc, s));
+    BSMM_TRY(c_row.reserve(sizeof(int32_t) * nnzb, s));
+    BSMM_TRY(missing.reserve(sizeof(int32_t), s));
+    BSMM_TRY(hist.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    BSMM_TRY(hoff.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    BSMM_TRY(run_cnt.reserve(sizeof(int64_t) * (nnzb + 1), s));
+    BSMM_TRY(run_of_c.reserve(sizeof(int64_t) * nnzb, s));
+    BSMM_TRY(cb.reserve(sizeof(int64_t) * (ncl + 1), s));
+    BSMM_TRY(st.c_count.reserve(sizeof(int64_t) * nnzb, s));
+    BSMM_TRY(st.run_cblk.reserve(sizeof(int64_t) * nnzb, s));
+    BSMM_TRY(st.run_coff.reserve(sizeof(int64_t) * nnzb, s));
+    BSMM_TRY(st.run_class.reserve(sizeof(int32_t) * nnzb, s));
+    BSMM_TRY(st.run_ptr.reserve(sizeof(int64_t) * (nnzb + 1), s));
+
+    BSMM_HIP(hipMemcpyAsync(d_rsi.p, rsi.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice, s));
+    BSMM_HIP(hipMemcpyAsync(d_csi.p, csi.data(), sizeof(int32_t) * nbc, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, missing.as<int32_t>());
+    BSMM_TRY(launch_check("zero_i32"));
+
+    const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
+    hipLaunchKernelGGL(k_stack_count, dim3(nbr), dim3(256), map_lds, s, nbc, A->d_row_ptr(),
+                       A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(), C->d_row_ptr(),
+                       C->d_col_ind(), st.c_count.as<int64_t>(), c_row.as<int32_t>(),
+                       missing.as<int32_t>());
+    BSMM_TRY(launch_check("stack_count"));
+
+    const unsigned tgrid = grid_of(ntiles, 4);
+    hipLaunchKernelGGL(k_class_hist, dim3(tgrid), dim3(256), sizeof(int32_t) * 4 * ncl, s, nnzb,
+                       ntiles, (const int64_t *)st.c_count.as<int64_t>(),
+                       (const int32_t *)c_row.as<int32_t>(), C->d_col_ind(),
+                       (const int32_t *)d_rsi.as<int32_t>(), (const int32_t *)d_csi.as<int32_t>(),
+                       st.ncs, ncl, hist.as<int64_t>());
+    BSMM_TRY(launch_check("class_hist"));
+    BSMM_TRY(scan_exclusive_i64(hist.as<int64_t>(), hoff.as<int64_t>(), ncl * ntiles, s));
+    hipLaunchKernelGGL(k_class_scatter, dim3(tgrid), dim3(256), sizeof(int64_t) * 4 * ncl, s,
+                       nnzb, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
+                       (const int32_t *)c_row.as<int32_t>(), C->d_col_ind(), C->d_blk_off(),
+                       (const int32_t *)d_rsi.as<int32_t>(), (const int32_t *)d_csi.as<int32_t>(),
+                       st.ncs, ncl, (const int64_t *)hoff.as<int64_t>(), st.run_cblk.as<int64_t>(),
+                       st.run_class.as<int32_t>(), st.run_coff.as<int64_t>(),
+                       run_cnt.as<int64_t>(), run_of_c.as<int64_t>());
+    BSMM_TRY(launch_check("class_scatter"));
+    hipLaunchKernelGGL(k_gather_class_begin, dim3(1), dim3(256), 0, s,
+                       (const int64_t *)hoff.as<int64_t>(), ntiles, ncl, cb.as<int64_t>());
+    BSMM_TRY(launch_check("gather_class_begin"));
+
+    int32_t miss = 0;
+    BSMM_HIP(hipMemcpyAsync(st.class_begin.data(), cb.p, sizeof(int64_t) * (ncl + 1),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(&miss, missing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    if (miss) {
+        set_error(BSMM_EINDEX, "C pattern does not contain every product block");
+        return BSMM_EINDEX;
+    }
+    st.n_runs = st.class_begin[ncl];
+    BSMM_TRY(scan_exclusive_i64(run_cnt.as<int64_t>(), st.run_ptr.as<int64_t>(), st.n_runs, s));
+    if (st.n_prod > 0) {
+        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * st.n_prod, s));
+        hipLaunchKernelGGL(k_stack_fill, dim3(nbr), dim3(256), map_lds, s, nbc, A->d_row_ptr(),
+                           A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(), B->d_col_ind(),
+                           B->d_blk_off(), B->d_rbs(), C->d_row_ptr(), C->d_col_ind(),
+                           (const int64_t *)run_of_c.as<int64_t>(),
+                           (const int64_t *)st.run_ptr.as<int64_t>(), st.prods.as<ulonglong2>());
+        BSMM_TRY(launch_check("stack_fill"));
+    }
+    return BSMM_OK;
+}
+
+}  // namespace bsmm
