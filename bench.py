@@ -53,6 +53,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blocked", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -67,6 +69,15 @@ def main():
     from synth import dense_square
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # A plain copy of known size: 1 GiB read + 1 GiB written per launch.
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)  # elementwise kernel: 1 GiB in, 1 GiB out
+        torch.cuda.synchronize()
+        log("copy calibration: 3 launches of a 1 GiB elementwise copy kernel")
+        return
     bsmm.use_torch_allocator(0)
     stream = torch.cuda.current_stream()
     log("generating inputs")
