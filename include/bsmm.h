@@ -132,14 +132,27 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
 
 /*
  * Library options (process-wide).  Keys and values:
- *   "path"        "auto" (default) | "stack" | "dense"
+ *   "path"        "auto" (default) | "stack" | "dense" | "emul"
  *                 auto takes the dense path iff A and B have every block
  *                 stored (paper, Sec. III: densify when the inputs are
- *                 dense); "dense" forces it (missing blocks read as zero).
+ *                 dense); "dense" forces it (missing blocks read as zero);
+ *                 "emul" runs the densified product as split-precision FP64
+ *                 emulation on INT8 matrix cores (Ozaki scheme: S digit
+ *                 slices of 7 bits per operand with power-of-two row/column
+ *                 scales, exact INT32 sums of every digit pair s + t <= S + 1,
+ *                 FP64 recombination and native FP64 beta*C)
+ *   "emul_slices" S in [1, 8] (default 7)
  *   "stack_kernel" "plain" (default) | "tuned"
+ *                 plain: one fixed parameter rule per shape, one launch per
+ *                 shape class; tuned: parameters from the tuning database,
+ *                 else the learned model, else the plain rule, and all shape
+ *                 classes launched together as nodes of one hipGraph
  *   "stack_chunk" maximum products per stack launch, "0" = unlimited
  *                 (paper, Sec. II: batches of at most 30000 products)
  *   "tune_db"     path of a tuning database file ("" = none)
+ *   "mlp_weights" path of a learned-model weight file ("" = none)
+ *   "stack_params" "TM TN KC WAVES": the tuned path uses this parameter
+ *                 set for every shape class ("" = select per shape)
  *   "time_kernels" "1" brackets every dense-GEMM and stack-kernel launch
  *                 with HIP events on the launch stream (see
  *                 bsmm_kernel_times); "0" (default) records nothing
@@ -198,6 +211,71 @@ int bsmm_inspect_stacks(bsmm_matrix A, bsmm_matrix B, bsmm_matrix C,
  */
 int bsmm_kernel_times(double *gemm_ms, int64_t *gemm_launches, double *stack_ms,
                       int64_t *stack_launches, int reset);
+
+/*
+ * Autotuning (paper, Sec. II: the small-matrix kernels are parametrised by
+ * algorithm, work per thread block, elements per thread and tiling, and an
+ * autotuner times the parameter sets of each (m, n, k)).
+ *
+ * A parameter set is 4 int32: register tile rows TM and columns TN per lane
+ * (each in {1,2,3,4,5,6,8}), k chunk staged per step (0 = as large as LDS
+ * allows), waves per workgroup (1, 2 or 4; 0 = as many as fit).
+ *
+ * bsmm_tune_candidates: the legal candidate sets of shape (m, n, k).
+ *   *n_cands: in = capacity (sets), out = count; cands may be NULL to query.
+ * bsmm_tune_shape: times each candidate on a synthetic stack of n_runs C
+ *   blocks of m x n, each receiving run_len products of k-deep blocks drawn
+ *   from pools of 4096 A and 4096 B blocks; one warm-up launch, then reps
+ *   timed launches (HIP events); out_us[c] = median microseconds, or -1 when
+ *   the set cannot be launched.  1 <= m, n, k <= 256; n_runs * run_len <=
+ *   2^26.  The library's own device memory holds the synthetic data.
+ * bsmm_select_params: the parameters the tuned path uses for (m, n, k):
+ *   database entry, else the learned model's choice, else the plain rule.
+ */
+int bsmm_tune_candidates(int32_t m, int32_t n, int32_t k, int32_t *n_cands, int32_t *cands);
+int bsmm_tune_shape(int32_t m, int32_t n, int32_t k, int64_t n_runs, int32_t run_len,
+                    int32_t n_cands, const int32_t *cands, int32_t reps, double *out_us,
+                    void *stream);
+int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t *params4);
+
+/*
+ * Learned performance model (paper, Sec. II: a model learned from part of the
+ * tuning data predicts performance for the whole shape set).  An FP32 MLP
+ *     y = W3 relu(W2 relu(W1 x + b1) + b2) + b3,  hidden width 64,
+ * maps the normalised features x of (shape, parameter set) to a predicted
+ * (standardised) log kernel time.  Parameters are one float array of
+ * bsmm_mlp_param_count() values: W1 [64 x F] row-major, b1 [64], W2 [64 x 64]
+ * row-major, b2 [64], W3 [64], b3 [1].  Every array argument is host memory;
+ * the work runs on the device (null stream) and the call returns when done.
+ *
+ * bsmm_mlp_features: the F raw features of (m, n, k, params4) (F = 9 here):
+ *   log2 m, log2 n, log2 k, TM, TN, log2 effective k chunk, waves per
+ *   workgroup, log2 lanes holding tiles, fraction of the tiles that covers
+ *   the block.  Training and selection both use this definition.
+ * bsmm_mlp_forward: y[i] for the n rows of x (n x F, row-major).
+ * bsmm_mlp_grad: gradient of the mean squared error over the n samples
+ *   (per-sample gradients summed in sample order) and the loss.
+ * bsmm_mlp_adam_step: one Adam update (step >= 1) of params with moment
+ *   arrays m, v (updated in place).
+ * bsmm_mlp_train: epochs of minibatch Adam (batch size, learning rate; the
+ *   sample order of every epoch is a Fisher-Yates shuffle driven by a 64-bit
+ *   LCG seeded with seed); params are updated in place; final_loss = mean
+ *   squared error over all samples afterwards.
+ * The tuned path loads a model from the file named by option "mlp_weights"
+ * (text: "bsmm-mlp features F mean ... std ... params COUNT ...") and, for a
+ * shape missing from the tuning database, takes the candidate with the
+ * lowest prediction.  Errors: EINVAL on bad arguments, ENOMEM, EDEVICE.
+ */
+int bsmm_mlp_param_count(int32_t n_features, int64_t *count);
+int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, const int32_t *params4, float *features,
+                      int32_t *n_features);
+int bsmm_mlp_forward(int32_t n_features, const float *params, int64_t n, const float *x, float *y);
+int bsmm_mlp_grad(int32_t n_features, const float *params, int64_t n, const float *x,
+                  const float *t, float *grad, float *loss);
+int bsmm_mlp_adam_step(int32_t n_features, float *params, const float *grad, float *m, float *v,
+                       int32_t step, float lr, float beta1, float beta2, float eps);
+int bsmm_mlp_train(int32_t n_features, float *params, int64_t n, const float *x, const float *t,
+                   int32_t epochs, int32_t batch, float lr, uint64_t seed, float *final_loss);
 
 #ifdef __cplusplus
 }

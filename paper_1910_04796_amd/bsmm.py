@@ -67,14 +67,30 @@ _lib.bsmm_last_error.argtypes = []
 _lib.bsmm_last_stats.argtypes = [ctypes.POINTER(bsmm_multiply_stats)]
 _lib.bsmm_inspect_stacks.argtypes = [_vp, _vp, _vp, _i64p, _i64p, _i64p, _i32p, _i64p, _i64p, _i64p, _vp]
 _lib.bsmm_kernel_times.argtypes = [_f64p, _i64p, _f64p, _i64p, ctypes.c_int]
-for _f in ("bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
+_lib.bsmm_tune_candidates.argtypes = [_i32, _i32, _i32, _i32p, _i32p]
+_lib.bsmm_tune_shape.argtypes = [_i32, _i32, _i32, _i64, _i32, _i32, _i32p, _i32, _f64p, _vp]
+_lib.bsmm_select_params.argtypes = [_i32, _i32, _i32, _i32p]
+_f32p = ctypes.POINTER(ctypes.c_float)
+_lib.bsmm_mlp_param_count.argtypes = [_i32, _i64p]
+_lib.bsmm_mlp_features.argtypes = [_i32, _i32, _i32, _i32p, _f32p, _i32p]
+_lib.bsmm_mlp_forward.argtypes = [_i32, _f32p, _i64, _f32p, _f32p]
+_lib.bsmm_mlp_grad.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _f32p, _f32p]
+_lib.bsmm_mlp_adam_step.argtypes = [_i32, _f32p, _f32p, _f32p, _f32p, _i32, ctypes.c_float,
+                                    ctypes.c_float, ctypes.c_float, ctypes.c_float]
+_lib.bsmm_mlp_train.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _i32, _i32, ctypes.c_float,
+                                ctypes.c_uint64, _f32p]
+for _f in ("bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
+           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
            "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
            "bsmm_last_stats", "bsmm_inspect_stacks"):
     getattr(_lib, _f).restype = ctypes.c_int
 
 EXPORTED = ("bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
             "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
-            "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times")
+            "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times",
+            "bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params",
+            "bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
+            "bsmm_mlp_adam_step", "bsmm_mlp_train")
 
 
 class BsmmError(RuntimeError):
@@ -258,6 +274,89 @@ def bsmm_kernel_times(reset=True):
     _check(_lib.bsmm_kernel_times(ctypes.byref(gm), ctypes.byref(gn), ctypes.byref(sm),
                                   ctypes.byref(sn), 1 if reset else 0))
     return gm.value, gn.value, sm.value, sn.value
+
+
+def bsmm_tune_candidates(m, n, k):
+    """Legal parameter sets (tm, tn, kc, waves) of shape (m, n, k), as an
+    int32 array of shape (count, 4)."""
+    cnt = _i32(0)
+    _check(_lib.bsmm_tune_candidates(m, n, k, ctypes.byref(cnt), None))
+    out = np.zeros((max(cnt.value, 1), 4), np.int32)
+    _check(_lib.bsmm_tune_candidates(m, n, k, ctypes.byref(cnt), out.ctypes.data_as(_i32p)))
+    return out[:cnt.value]
+
+
+def bsmm_tune_shape(m, n, k, cands, n_runs=3750, run_len=8, reps=5, stream=None):
+    """Median microseconds of every candidate on a synthetic stack."""
+    c = np.ascontiguousarray(cands, dtype=np.int32).reshape(-1, 4)
+    out = np.zeros(max(len(c), 1), np.float64)
+    _check(_lib.bsmm_tune_shape(m, n, k, n_runs, run_len, len(c), c.ctypes.data_as(_i32p), reps,
+                                out.ctypes.data_as(_f64p), _stream(stream)))
+    return out[:len(c)]
+
+
+def bsmm_select_params(m, n, k):
+    p = np.zeros(4, np.int32)
+    _check(_lib.bsmm_select_params(m, n, k, p.ctypes.data_as(_i32p)))
+    return tuple(int(x) for x in p)
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def bsmm_mlp_param_count(n_features):
+    c = _i64()
+    _check(_lib.bsmm_mlp_param_count(n_features, ctypes.byref(c)))
+    return c.value
+
+
+def bsmm_mlp_features(m, n, k, params4):
+    p = np.ascontiguousarray(params4, dtype=np.int32)
+    out = np.zeros(32, np.float32)
+    nf = _i32()
+    _check(_lib.bsmm_mlp_features(m, n, k, p.ctypes.data_as(_i32p), out.ctypes.data_as(_f32p),
+                                  ctypes.byref(nf)))
+    return out[:nf.value]
+
+
+def bsmm_mlp_forward(params, x):
+    x = _f32(x)
+    P = _f32(params)
+    y = np.zeros(max(len(x), 1), np.float32)
+    _check(_lib.bsmm_mlp_forward(x.shape[1], P.ctypes.data_as(_f32p), len(x), x.ctypes.data_as(_f32p),
+                                 y.ctypes.data_as(_f32p)))
+    return y[:len(x)]
+
+
+def bsmm_mlp_grad(params, x, t):
+    x, t, P = _f32(x), _f32(t), _f32(params)
+    g = np.zeros_like(P)
+    loss = ctypes.c_float()
+    _check(_lib.bsmm_mlp_grad(x.shape[1], P.ctypes.data_as(_f32p), len(x), x.ctypes.data_as(_f32p),
+                              t.ctypes.data_as(_f32p), g.ctypes.data_as(_f32p), ctypes.byref(loss)))
+    return g, loss.value
+
+
+def bsmm_mlp_adam_step(n_features, params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999,
+                       eps=1e-8):
+    """In-place update of params, m, v (float32 arrays)."""
+    g = _f32(grad)
+    for a in (params, m, v):
+        assert a.dtype == np.float32 and a.flags.c_contiguous
+    _check(_lib.bsmm_mlp_adam_step(n_features, params.ctypes.data_as(_f32p), g.ctypes.data_as(_f32p),
+                                   m.ctypes.data_as(_f32p), v.ctypes.data_as(_f32p), step, lr, beta1,
+                                   beta2, eps))
+
+
+def bsmm_mlp_train(params, x, t, epochs=30, batch=256, lr=1e-3, seed=0):
+    """Returns (trained params, final mean squared error)."""
+    x, t = _f32(x), _f32(t)
+    P = _f32(params).copy()
+    loss = ctypes.c_float()
+    _check(_lib.bsmm_mlp_train(x.shape[1], P.ctypes.data_as(_f32p), len(x), x.ctypes.data_as(_f32p),
+                               t.ctypes.data_as(_f32p), epochs, batch, lr, seed, ctypes.byref(loss)))
+    return P, loss.value
 
 
 class HostBlockCSR:

@@ -402,6 +402,7 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         if (v == "auto") o.path = 0;
         else if (v == "stack") o.path = 1;
         else if (v == "dense") o.path = 2;
+        else if (v == "emul") o.path = 3;
         else goto bad;
     } else if (k == "stack_kernel") {
         if (v == "plain") o.stack_kernel = 0;
@@ -414,6 +415,18 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         o.stack_chunk = x;
     } else if (k == "tune_db") {
         o.tune_db = v;
+    } else if (k == "emul_slices") {
+        char *end = nullptr;
+        long x = strtol(value, &end, 10);
+        if (!end || *end || x < 1 || x > 8) goto bad;
+        o.emul_slices = (int)x;
+    } else if (k == "stack_params") {
+        int q[4] = {0, 0, 0, 0};
+        if (!v.empty() && sscanf(value, "%d %d %d %d", &q[0], &q[1], &q[2], &q[3]) != 4) goto bad;
+        if (!v.empty() && (q[0] < 1 || q[1] < 1 || q[2] < 0 || q[3] < 0 || q[3] > 4)) goto bad;
+        for (int i = 0; i < 4; ++i) o.forced[i] = q[i];
+    } else if (k == "mlp_weights") {
+        o.mlp_weights = v;
     } else if (k == "time_kernels") {
         if (v == "0") o.time_kernels = 0;
         else if (v == "1") o.time_kernels = 1;
@@ -436,11 +449,17 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     }
     Options &o = options();
     std::string k(key), v;
-    if (k == "path") v = o.path == 0 ? "auto" : o.path == 1 ? "stack" : "dense";
+    if (k == "path") v = o.path == 0 ? "auto" : o.path == 1 ? "stack" : o.path == 2 ? "dense" : "emul";
+    else if (k == "emul_slices") v = std::to_string(o.emul_slices);
     else if (k == "stack_kernel") v = o.stack_kernel ? "tuned" : "plain";
     else if (k == "stack_chunk") v = std::to_string(o.stack_chunk);
     else if (k == "tune_db") v = o.tune_db;
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
+    else if (k == "mlp_weights") v = o.mlp_weights;
+    else if (k == "stack_params")
+        v = o.forced[0] ? std::to_string(o.forced[0]) + " " + std::to_string(o.forced[1]) + " " +
+                              std::to_string(o.forced[2]) + " " + std::to_string(o.forced[3])
+                        : std::string();
     else {
         set_error(BSMM_EINVAL, "unknown option '%s'", key);
         return BSMM_EINVAL;

@@ -46,11 +46,14 @@ int launch_check(const char *what);
 
 // --------------------------------------------------------------- options
 struct Options {
-    int path = 0;          // 0 auto, 1 stack, 2 dense
+    int path = 0;          // 0 auto, 1 stack, 2 dense, 3 emulated dense
+    int emul_slices = 7;   // digit slices of the emulated path
     int stack_kernel = 0;  // 0 plain, 1 tuned
     int64_t stack_chunk = 0;
     int time_kernels = 0;
     std::string tune_db;
+    std::string mlp_weights;
+    int forced[4] = {0, 0, 0, 0};  // "stack_params": tm tn kc waves for every class
 };
 Options &options();
 
@@ -203,12 +206,66 @@ int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matr
                  Stacks &st, hipStream_t s);
 
 // --------------------------------------------------------- small blocks
+// Parameters of the small-block kernel (the tuning space): register tile
+// TM x TN per lane (TM, TN in {1,2,3,4,5,6,8}), k chunk staged per step
+// (0 = as large as LDS allows), waves per workgroup (0 = as many as fit,
+// at most 4).
+struct SmmParams {
+    int tm = 0, tn = 0, kc = 0, waves = 0;
+};
+// Kernel arguments of one small-block launch.
+struct SmmArgs {
+    const double *A;
+    const double *B;
+    double *C;
+    const int64_t *run_coff;
+    const int64_t *run_ptr;
+    const ulonglong2 *prods;
+    int64_t run_begin, run_end;
+    int m, n;
+    int tiles_m, tiles_n;   // register tiles covering the C block
+    int L;                  // lanes per group (min(tiles, 64))
+    int G;                  // groups per wave
+    int passes;             // ceil(tiles / L)
+    int region;             // doubles of LDS per group
+    int kc_max;             // largest k chunk that fits the region
+    double alpha, beta;
+};
+// A planned launch: kernel, shape-dependent arguments, block size, LDS.
+struct SmmLaunch {
+    void *fn = nullptr;
+    SmmArgs args{};
+    int waves = 1;
+    size_t lds = 0;
+};
+int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out);
+unsigned smm_grid(const SmmLaunch &L, int64_t nruns);
+int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const int64_t *run_coff,
+               const int64_t *run_ptr, const ulonglong2 *prods, int64_t rb, int64_t re,
+               double alpha, double beta, hipStream_t s);
+int run_graph(const std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>> &launches,
+              const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, const Stacks &st,
+              double alpha, double beta, hipStream_t s);
+SmmParams plain_params(int m, int n);
+// Selected parameters for shape (m, n, k): tuning database, then learned
+// model, then the plain rule.
+SmmParams select_params(int m, int n, int k);
+// Legal candidate parameter sets of a shape (the tuning space).
+std::vector<SmmParams> candidate_params(int m, int n, int k);
+// Learned model: ranks the candidates of (m, n, k) by predicted time; false
+// when no model is loaded.
+bool mlp_select(int m, int n, int k, SmmParams *out);
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                const Stacks &st, double alpha, double beta, hipStream_t s);
 
 // ----------------------------------------------------------------- dense
 int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                    double alpha, double beta, hipStream_t s);
+
+// Split-precision FP64 emulation of the dense product on INT8 matrix cores.
+int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
+                  double alpha, double beta, int S, hipStream_t s);
+int64_t emul_chunk(int S);
 
 // ---------------------------------------------------------------- filter
 int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s);

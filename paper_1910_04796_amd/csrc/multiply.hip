@@ -158,6 +158,9 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
     if (alpha == 0.0 || tot.nprod == 0) {
         if (beta != 1.0) BSMM_TRY(scale_blocks(C, nullptr, beta, s));
         stt.path = 0;
+    } else if (o.path == 3) {
+        stt.path = 3;
+        BSMM_TRY(emul_multiply(A, B, C, alpha, beta, o.emul_slices, s));
     } else if (dense) {
         stt.path = 2;
         BSMM_TRY(dense_multiply(A, B, C, alpha, beta, s));

@@ -28,24 +28,6 @@ namespace bsmm {
 
 namespace {
 
-struct SmmArgs {
-    const double *A;
-    const double *B;
-    double *C;
-    const int64_t *run_coff;
-    const int64_t *run_ptr;
-    const ulonglong2 *prods;
-    int64_t run_begin, run_end;
-    int m, n;
-    int tiles_m, tiles_n;   // register tiles covering the C block
-    int L;                  // lanes per group (min(tiles, 64))
-    int G;                  // groups per wave
-    int passes;             // ceil(tiles / L)
-    int region;             // doubles of LDS per group
-    int kc_max;             // largest k chunk that fits the region
-    double alpha, beta;
-};
-
 template <int TM, int TN>
 __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
     extern __shared__ double lds[];
@@ -149,18 +131,30 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
 
 using SmmKernel = void (*)(SmmArgs);
 
-template <int T> SmmKernel pick_square() { return k_smm_valu<T, T>; }
+// Register-tile shapes with a compiled kernel: TM, TN in {1,2,3,4,5,6,8}.
+template <int TM> SmmKernel pick_tn(int tn) {
+    switch (tn) {
+    case 1: return k_smm_valu<TM, 1>;
+    case 2: return k_smm_valu<TM, 2>;
+    case 3: return k_smm_valu<TM, 3>;
+    case 4: return k_smm_valu<TM, 4>;
+    case 5: return k_smm_valu<TM, 5>;
+    case 6: return k_smm_valu<TM, 6>;
+    case 8: return k_smm_valu<TM, 8>;
+    default: return nullptr;
+    }
+}
 
-SmmKernel kernel_for(int tm) {
+SmmKernel kernel_for(int tm, int tn) {
     switch (tm) {
-    case 1: return pick_square<1>();
-    case 2: return pick_square<2>();
-    case 3: return pick_square<3>();
-    case 4: return pick_square<4>();
-    case 5: return pick_square<5>();
-    case 6: return pick_square<6>();
-    case 7: return pick_square<7>();
-    default: return pick_square<8>();
+    case 1: return pick_tn<1>(tn);
+    case 2: return pick_tn<2>(tn);
+    case 3: return pick_tn<3>(tn);
+    case 4: return pick_tn<4>(tn);
+    case 5: return pick_tn<5>(tn);
+    case 6: return pick_tn<6>(tn);
+    case 8: return pick_tn<8>(tn);
+    default: return nullptr;
     }
 }
 
@@ -169,60 +163,107 @@ constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per workgroup
 }  // namespace
 
 // Plain parameter rule: the smallest square register tile T (1..8) for
-// which ceil(m/T) * ceil(n/T) <= 64 lanes; blocks above 64 use T = 8 and
-// passes.
-static int plain_tile(int m, int n) {
-    for (int t = 1; t < 8; ++t)
-        if (ceil_div(m, t) * ceil_div(n, t) <= kWave) return t;
-    return 8;
+// which ceil(m/T) * ceil(n/T) <= 64 lanes (blocks above 64 use T = 8 and
+// passes), the largest k chunk that fits, and as many waves per workgroup
+// (up to 4) as 64 KB of LDS allow.
+SmmParams plain_params(int m, int n) {
+    int t = 8;
+    for (int c = 1; c < 8; ++c)
+        if (c != 7 && ceil_div(m, c) * ceil_div(n, c) <= kWave) {
+            t = c;
+            break;
+        }
+    return SmmParams{t, t, 0, 0};
 }
 
-static int launch_class(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
-                        const Stacks &st, int cl, int64_t rb, int64_t re, int kmax, double alpha,
-                        double beta, hipStream_t s) {
+int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
+    const int TM = prm.tm, TN = prm.tn;
+    SmmKernel fn = kernel_for(TM, TN);
+    if (!fn) {
+        set_error(BSMM_EINVAL, "no small-block kernel for register tile %dx%d", TM, TN);
+        return BSMM_EINVAL;
+    }
     SmmArgs a{};
-    a.A = A->d_data();
-    a.B = B->d_data();
-    a.C = C->d_data();
-    a.run_coff = st.run_coff.as<int64_t>();
-    a.run_ptr = st.run_ptr.as<int64_t>();
-    a.prods = st.prods.as<ulonglong2>();
-    a.run_begin = rb;
-    a.run_end = re;
-    a.m = st.row_sizes[cl / st.ncs];
-    a.n = st.col_sizes[cl % st.ncs];
-    const int T = plain_tile(a.m, a.n);
-    a.tiles_m = (int)ceil_div(a.m, T);
-    a.tiles_n = (int)ceil_div(a.n, T);
+    a.m = m;
+    a.n = n;
+    a.tiles_m = (int)ceil_div(m, TM);
+    a.tiles_n = (int)ceil_div(n, TN);
     const int tiles = a.tiles_m * a.tiles_n;
     a.L = std::min(tiles, kWave);
     a.G = kWave / a.L;
     a.passes = (int)ceil_div(tiles, a.L);
     // LDS region per group: A chunk (m x kc) + B chunk (n_pad x kc) + slack
     // for the tail reads of the last register tile.
-    const int n_pad = a.tiles_n * T;
-    const int max_group_doubles = kLdsBudget / 8 / a.G;
-    int kc = std::min(kmax, (max_group_doubles - T - 3) / (a.m + n_pad));
+    const int n_pad = a.tiles_n * TN;
+    const int waves_req = prm.waves > 0 ? std::min(prm.waves, 4) : 1;
+    const int max_group_doubles = kLdsBudget / 8 / a.G / waves_req;
+    int kc = (max_group_doubles - TM - 3) / (m + n_pad);
+    kc = std::min(kc, std::max(1, kmax));
+    if (prm.kc > 0) kc = std::min(kc, prm.kc);
     if (kc < 1) {
-        set_error(BSMM_ENOTSUP, "block shape %dx%d too large for the small-block kernel", a.m, a.n);
+        set_error(BSMM_ENOTSUP, "block shape %dx%d with tile %dx%d does not fit in LDS", m, n, TM, TN);
         return BSMM_ENOTSUP;
     }
     a.kc_max = kc;
-    a.region = (a.m + n_pad) * kc + T + 2;
+    a.region = (m + n_pad) * kc + TM + 2;
     a.region = (a.region + 1) & ~1;
+    const size_t wave_bytes = sizeof(double) * (size_t)a.G * a.region;
+    int waves = prm.waves > 0 ? waves_req
+                              : (int)std::max<int64_t>(1, std::min<int64_t>(4, kLdsBudget / wave_bytes));
+    if (wave_bytes * waves > (size_t)kLdsBudget) {
+        set_error(BSMM_ENOTSUP, "small-block launch needs more than 64 KB of LDS");
+        return BSMM_ENOTSUP;
+    }
+    out->fn = (void *)fn;
+    out->args = a;
+    out->waves = waves;
+    out->lds = wave_bytes * waves;
+    return BSMM_OK;
+}
+
+unsigned smm_grid(const SmmLaunch &L, int64_t nruns) {
+    const int64_t waves_needed = ceil_div(nruns, L.args.G);
+    const int64_t wg_cap = 256 * 8;  // enough resident work for 256 CUs
+    return grid_of(waves_needed, L.waves, wg_cap);
+}
+
+int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const int64_t *run_coff,
+               const int64_t *run_ptr, const ulonglong2 *prods, int64_t rb, int64_t re,
+               double alpha, double beta, hipStream_t s) {
+    SmmArgs a = L.args;
+    a.A = A;
+    a.B = B;
+    a.C = C;
+    a.run_coff = run_coff;
+    a.run_ptr = run_ptr;
+    a.prods = prods;
+    a.run_begin = rb;
+    a.run_end = re;
     a.alpha = alpha;
     a.beta = beta;
-    const int64_t per_wave = a.G;
-    const int64_t nruns = re - rb;
-    const size_t wave_bytes = sizeof(double) * (size_t)a.G * a.region;
-    int waves_per_wg = (int)std::max<int64_t>(1, std::min<int64_t>(4, kLdsBudget / wave_bytes));
-    const int64_t waves_needed = ceil_div(nruns, per_wave);
-    const int64_t wg_cap = 256 * 8;  // enough resident work for 256 CUs
-    const unsigned grid = grid_of(waves_needed, waves_per_wg, wg_cap);
     KernelTimer kt(1, s);
-    hipLaunchKernelGGL(kernel_for(T), dim3(grid), dim3(64 * waves_per_wg),
-                       wave_bytes * waves_per_wg, s, a);
+    hipLaunchKernelGGL((SmmKernel)L.fn, dim3(smm_grid(L, re - rb)), dim3(64 * L.waves), L.lds, s,
+                       a);
     return launch_check("smm_valu");
+}
+
+// Most frequent k of the products of a class, as seen from A's block-column
+// sizes: the key under which tuned parameters are looked up.
+static int representative_k(const bsmm_matrix_s *A) {
+    std::vector<int32_t> v = A->cbs;
+    if (v.empty()) return 1;
+    std::sort(v.begin(), v.end());
+    int best = v[0], bestc = 0;
+    for (size_t i = 0; i < v.size();) {
+        size_t j = i;
+        while (j < v.size() && v[j] == v[i]) ++j;
+        if ((int)(j - i) > bestc) {
+            bestc = (int)(j - i);
+            best = v[i];
+        }
+        i = j;
+    }
+    return best;
 }
 
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
@@ -230,6 +271,8 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
     if (st.n_runs == 0) return BSMM_OK;
     const int kmax = std::max(1, A->max_cbs);
     const int64_t chunk = options().stack_chunk;
+    const bool tuned = options().stack_kernel == 1;
+    const int krep = representative_k(A);
     std::vector<int64_t> run_ptr_h;
     if (chunk > 0) {
         run_ptr_h.resize(st.n_runs + 1);
@@ -237,11 +280,16 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                                 hipMemcpyDeviceToHost, s));
         BSMM_HIP(hipStreamSynchronize(s));
     }
+    std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>> launches;
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t rb = st.class_begin[cl], re = st.class_begin[cl + 1];
         if (re <= rb) continue;
+        const int m = st.row_sizes[cl / st.ncs], n = st.col_sizes[cl % st.ncs];
+        SmmParams prm = tuned ? select_params(m, n, krep) : plain_params(m, n);
+        SmmLaunch L;
+        BSMM_TRY(plan_smm(prm, m, n, kmax, &L));
         if (chunk <= 0) {
-            BSMM_TRY(launch_class(A, B, C, st, cl, rb, re, kmax, alpha, beta, s));
+            launches.push_back({L, {rb, re}});
             continue;
         }
         // Batches of at most `chunk` products; a run is never split.
@@ -249,11 +297,74 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         while (b0 < re) {
             int64_t b1 = b0 + 1;
             while (b1 < re && run_ptr_h[b1 + 1] - run_ptr_h[b0] <= chunk) ++b1;
-            BSMM_TRY(launch_class(A, B, C, st, cl, b0, b1, kmax, alpha, beta, s));
+            launches.push_back({L, {b0, b1}});
             b0 = b1;
         }
     }
+    if (tuned && chunk <= 0 && launches.size() > 1)
+        return run_graph(launches, A, B, C, st, alpha, beta, s);
+    for (auto &l : launches)
+        BSMM_TRY(launch_smm(l.first, A->d_data(), B->d_data(), C->d_data(),
+                            st.run_coff.as<int64_t>(), st.run_ptr.as<int64_t>(),
+                            st.prods.as<ulonglong2>(), l.second.first, l.second.second, alpha, beta,
+                            s));
     return BSMM_OK;
+}
+
+// Tuned path: all shape classes as independent kernel nodes of one hipGraph,
+// launched once, so classes run concurrently.
+int run_graph(const std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>> &launches,
+              const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, const Stacks &st,
+              double alpha, double beta, hipStream_t s) {
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    BSMM_HIP(hipGraphCreate(&graph, 0));
+    std::vector<SmmArgs> args(launches.size());
+    std::vector<void *> argp(launches.size());
+    int status = BSMM_OK;
+    for (size_t i = 0; i < launches.size() && status == BSMM_OK; ++i) {
+        const SmmLaunch &L = launches[i].first;
+        SmmArgs &a = args[i];
+        a = L.args;
+        a.A = A->d_data();
+        a.B = B->d_data();
+        a.C = C->d_data();
+        a.run_coff = st.run_coff.as<int64_t>();
+        a.run_ptr = st.run_ptr.as<int64_t>();
+        a.prods = st.prods.as<ulonglong2>();
+        a.run_begin = launches[i].second.first;
+        a.run_end = launches[i].second.second;
+        a.alpha = alpha;
+        a.beta = beta;
+        argp[i] = &a;
+        hipKernelNodeParams kp{};
+        kp.func = L.fn;
+        kp.gridDim = dim3(smm_grid(L, a.run_end - a.run_begin));
+        kp.blockDim = dim3(64 * L.waves);
+        kp.sharedMemBytes = (unsigned)L.lds;
+        kp.kernelParams = &argp[i];
+        kp.extra = nullptr;
+        hipGraphNode_t node;
+        if (hipGraphAddKernelNode(&node, graph, nullptr, 0, &kp) != hipSuccess) {
+            set_error(BSMM_EDEVICE, "hipGraphAddKernelNode failed");
+            status = BSMM_EDEVICE;
+        }
+    }
+    if (status == BSMM_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+        set_error(BSMM_EDEVICE, "hipGraphInstantiate failed");
+        status = BSMM_EDEVICE;
+    }
+    if (status == BSMM_OK) {
+        KernelTimer kt(1, s);
+        if (hipGraphLaunch(exec, s) != hipSuccess) {
+            set_error(BSMM_EDEVICE, "hipGraphLaunch failed");
+            status = BSMM_EDEVICE;
+        }
+    }
+    if (exec) (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    (void)hipGetLastError();
+    return status;
 }
 
 }  // namespace bsmm

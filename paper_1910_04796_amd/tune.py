@@ -1,0 +1,95 @@
+"""Exhaustive autotuner of the small-block kernels (paper, Sec. II: every
+requested (m, n, k) kernel is tuned over its parameter space).
+
+For each shape the legal candidate parameter sets (register tile TM x TN,
+k chunk, waves per workgroup) are timed by the library on a synthetic stack
+of 3,750 C blocks with runs of 8 products (30,000 products, the paper's
+batch size).  The best set per shape goes to the database read by the tuned
+path (option ``tune_db``); every timing goes to a CSV that trains the learned
+model.
+
+    python -m paper_1910_04796_amd.tune --sizes 5,13,23,32 --db DB --all ALL
+    python -m paper_1910_04796_amd.tune --random 600 --lo 4 --hi 64 --seed 0 --db DB --all ALL
+"""
+import argparse
+import gzip
+import itertools
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_DB = os.path.join(HERE, "tune_db", "gfx950.txt")
+
+
+def shapes_from_sizes(sizes):
+    return list(itertools.product(sizes, repeat=3))
+
+
+def random_shapes(count, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    allv = np.array(list(itertools.product(range(lo, hi + 1), repeat=3)))
+    idx = rng.choice(len(allv), size=count, replace=False)
+    return [tuple(int(x) for x in allv[i]) for i in idx]
+
+
+def tune(shapes, db_path, all_path, reps=5, n_runs=3750, run_len=8, log=print):
+    from . import bsmm
+    rows = []
+    best = {}
+    t0 = time.time()
+    for i, (m, n, k) in enumerate(shapes):
+        cands = bsmm.bsmm_tune_candidates(m, n, k)
+        plain = np.array([bsmm.bsmm_select_params(m, n, k)], np.int32)
+        us_all = bsmm.bsmm_tune_shape(m, n, k, np.concatenate([cands, plain]), n_runs=n_runs,
+                                      run_len=run_len, reps=reps)
+        us, plain_us = us_all[:-1], float(us_all[-1])
+        ok = us > 0
+        for c, u in zip(cands[ok], us[ok]):
+            rows.append((m, n, k, *[int(x) for x in c], float(u)))
+        j = int(np.argmin(np.where(ok, us, np.inf)))
+        best[(m, n, k)] = (tuple(int(x) for x in cands[j]), float(us[j]), plain_us)
+        log(f"[tune] {i + 1}/{len(shapes)} ({m},{n},{k}): {len(cands)} candidates, best "
+            f"{tuple(int(x) for x in cands[j])} {us[j]:.1f} us ({time.time() - t0:.0f} s)")
+    if db_path:
+        os.makedirs(os.path.dirname(os.path.abspath(db_path)), exist_ok=True)
+        with open(db_path, "w") as f:
+            f.write("# m n k tm tn kc waves best_us plain_us  (gfx950, stack of %d runs x %d products)\n"
+                    % (n_runs, run_len))
+            for (m, n, k), (p, u, pu) in sorted(best.items()):
+                f.write(f"{m} {n} {k} {p[0]} {p[1]} {p[2]} {p[3]} {u:.2f} {pu:.2f}\n")
+    if all_path:
+        op = gzip.open if all_path.endswith(".gz") else open
+        with op(all_path, "wt") as f:
+            f.write("m,n,k,tm,tn,kc,waves,us\n")
+            for r in rows:
+                f.write(",".join(str(x) for x in r[:7]) + f",{r[7]:.3f}\n")
+    return best, rows
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--sizes", default="")
+    ap.add_argument("--random", type=int, default=0)
+    ap.add_argument("--lo", type=int, default=4)
+    ap.add_argument("--hi", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--skip", type=int, default=0, help="skip the first N random shapes")
+    ap.add_argument("--db", default=DEFAULT_DB)
+    ap.add_argument("--all", default="")
+    ap.add_argument("--reps", type=int, default=5)
+    args = ap.parse_args()
+    if args.sizes:
+        shapes = shapes_from_sizes([int(x) for x in args.sizes.split(",")])
+    else:
+        shapes = random_shapes(args.random, args.lo, args.hi, args.seed)[args.skip:]
+    from . import bsmm
+    bsmm.bsmm_set_option("tune_db", "")  # the plain rule is the reference for every shape
+    bsmm.bsmm_set_option("mlp_weights", "")
+    tune(shapes, args.db, args.all, reps=args.reps, log=lambda s: print(s, file=sys.stderr, flush=True))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,100 @@
+"""Tuned stack path: every kernel parameter set computes the reference result,
+the hipGraph launch of all shape classes matches the reference, the tuning
+database round-trips, and the tuner's timings are sane."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from synth import banded_uneven, make_matrix, rng_of
+
+from tests.helpers import check_against_oracle, gpu_multiply, lib
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _tuned(A, B, params=None, beta=0.0, Cin=None, eps=0.0):
+    b = lib()
+    b.bsmm_set_option("stack_params", params or "")
+    try:
+        return gpu_multiply(1.0, A, B, beta, Cin, eps=eps, path="stack", kernel="tuned")
+    finally:
+        b.bsmm_set_option("stack_params", "")
+
+
+@pytest.mark.parametrize("m,n,k", [(5, 5, 5), (13, 23, 32), (32, 32, 32), (23, 5, 13)])
+def test_every_candidate_bit_exact(m, n, k):
+    """Integer inputs: every legal parameter set of the shape gives the exact
+    result (any summation order is exact)."""
+    b = lib()
+    rng = rng_of(m * 10000 + n * 100 + k)
+    A = make_matrix(rng, np.full(6, m, np.int32), np.full(5, k, np.int32), 0.6, values="int")
+    B = make_matrix(rng, np.full(5, k, np.int32), np.full(7, n, np.int32), 0.6, values="int")
+    Cin = make_matrix(rng, np.full(6, m, np.int32), np.full(7, n, np.int32), 0.3, values="int")
+    R = orc.multiply(1.0, A, B, -1.0, Cin)
+    cands = b.bsmm_tune_candidates(m, n, k)
+    assert len(cands) > 0
+    for c in cands[:: max(1, len(cands) // 60)]:
+        X, st = _tuned(A, B, " ".join(str(int(x)) for x in c), beta=-1.0, Cin=Cin)
+        assert st["path"] == 1
+        try:
+            check_against_oracle(X, R, 0.0)
+        except AssertionError as e:
+            raise AssertionError(f"parameters {c.tolist()}: {e}") from None
+
+
+@pytest.mark.parametrize("occ", [0.05, 0.3])
+def test_tuned_graph_uneven(occ):
+    """Several shape classes launched as one hipGraph."""
+    A, B = banded_uneven(seed=21, occupancy=occ, target=1200)
+    for eps in (0.0, 1e-10):
+        R = orc.multiply(1.0, A, B, 0.0, filter_eps=eps)
+        X, st = _tuned(A, B, eps=eps)
+        assert st["n_classes"] > 1
+        check_against_oracle(X, R, TOL)
+
+
+def test_tuned_with_database(tmp_path):
+    b = lib()
+    db = tmp_path / "db.txt"
+    db.write_text("# m n k tm tn kc waves us\n23 23 23 2 8 8 2 1.0\n5 5 5 1 2 4 1 1.0\n")
+    b.bsmm_set_option("tune_db", str(db))
+    try:
+        assert b.bsmm_select_params(23, 23, 23) == (2, 8, 8, 2)
+        assert b.bsmm_select_params(5, 5, 5) == (1, 2, 4, 1)
+        assert b.bsmm_select_params(13, 13, 13) == (2, 2, 0, 0)  # plain rule
+        rng = rng_of(4)
+        s = np.full(9, 23, np.int32)
+        A = make_matrix(rng, s, s, 0.4)
+        B = make_matrix(rng, s, s, 0.4)
+        X, st = _tuned(A, B)
+        check_against_oracle(X, orc.multiply(1.0, A, B, 0.0), TOL)
+    finally:
+        b.bsmm_set_option("tune_db", "")
+
+
+def test_tuner_timings():
+    b = lib()
+    cands = np.array([[1, 1, 0, 0], [2, 2, 8, 2], [7, 7, 0, 0], [4, 4, 0, 4]], np.int32)
+    us = b.bsmm_tune_shape(13, 13, 13, cands, n_runs=500, run_len=8, reps=3)
+    assert us[0] > 0 and us[1] > 0 and us[3] > 0
+    assert us[2] == -1.0  # no kernel for a 7 x 7 tile
+
+
+def test_committed_database_beats_plain():
+    """For every shape of the committed database, the recorded best set is
+    no slower than the plain rule on the tuning stack (re-measured)."""
+    from paper_1910_04796_amd.tune import DEFAULT_DB
+    if not os.path.exists(DEFAULT_DB):
+        pytest.skip("no committed tuning database")
+    b = lib()
+    rows = [l.split() for l in open(DEFAULT_DB) if l.strip() and not l.startswith("#")]
+    for r in rows[:: max(1, len(rows) // 8)]:
+        m, n, k = (int(x) for x in r[:3])
+        best = [int(x) for x in r[3:7]]
+        b.bsmm_set_option("tune_db", "")
+        plain = list(b.bsmm_select_params(m, n, k))
+        us = b.bsmm_tune_shape(m, n, k, np.array([best, plain, best, plain], np.int32), reps=5)
+        assert min(us[0], us[2]) <= 1.10 * min(us[1], us[3]), (m, n, k, best, plain, us.tolist())

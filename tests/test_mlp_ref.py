@@ -1,0 +1,48 @@
+"""Pins of the numpy model reference: back-propagation against central finite
+differences in FP64, Adam's first step against its closed form, and a
+learnable target."""
+import numpy as np
+
+from oracle import mlp_ref as ref
+
+
+def test_backprop_matches_finite_differences():
+    rng = np.random.default_rng(0)
+    F = 9
+    P = ref.init_params(F, seed=1, dtype=np.float64)
+    # push some biases so both ReLU branches are exercised away from the kink
+    X = rng.normal(size=(37, F))
+    T = rng.normal(size=37)
+    G, _ = ref.grad(P, X, T)
+    idx = rng.choice(len(P), size=200, replace=False)
+    h = 1e-6
+    for i in idx:
+        Pp = P.copy(); Pp[i] += h
+        Pm = P.copy(); Pm[i] -= h
+        fd = (ref.loss(Pp, X, T) - ref.loss(Pm, X, T)) / (2 * h)
+        assert abs(fd - G[i]) <= 1e-6 * max(1.0, abs(fd)), (i, fd, G[i])
+
+
+def test_adam_first_step_closed_form():
+    """With zero moments, the first bias-corrected step is lr * g / (|g| + eps)."""
+    g = np.array([3.0, -0.5, 1e-3, 0.0])
+    P = np.zeros(4)
+    P1, M, V = ref.adam_step(P, g, np.zeros(4), np.zeros(4), 1, lr=0.01)
+    assert np.allclose(P1, -0.01 * g / (np.abs(g) + 1e-8), rtol=1e-12, atol=0)
+
+
+def test_training_learns_a_smooth_target():
+    rng = np.random.default_rng(3)
+    F = 3
+    X = rng.uniform(-1, 1, size=(512, F))
+    T = X[:, 0] * 0.7 - X[:, 1] ** 2 + 0.2 * np.abs(X[:, 2])
+    P = ref.init_params(F, seed=2, dtype=np.float64)
+    M = np.zeros_like(P); V = np.zeros_like(P)
+    l0 = ref.loss(P, X, T)
+    step = 0
+    for ep in range(60):
+        for b in range(0, 512, 64):
+            step += 1
+            G, _ = ref.grad(P, X[b:b + 64], T[b:b + 64])
+            P, M, V = ref.adam_step(P, G, M, V, step, lr=3e-3)
+    assert ref.loss(P, X, T) < 0.05 * l0
