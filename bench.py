@@ -1,13 +1,20 @@
 #!/usr/bin/env python3
 """Benchmark of the local block-sparse FP64 multiply on one MI355X.
 
-Workload (one step = one full bsmm_multiply, inputs resident in HBM):
+Headline workload (one step = one full bsmm_multiply, inputs resident in HBM):
 dense square product N = 8192 stored as a 256 x 256 grid of 32 x 32 blocks,
 every block present, values U[-1, 1], C = 1.0 * A * B + 0.0 * C.  The
 library densifies (merge into panels, one FP64 MFMA GEMM with the split back
-into blocks fused into its epilogue).  The same workload is also timed on
-the blocked path (stacks of 32^3 block products), the paper's
-T_blocked / T_densified comparison.
+into blocks fused into its epilogue).  `value` is that path's FP64-equivalent
+GFLOP/s (sum of 2 m n k over the block products per second).
+
+Comparison legs on the same workload (extra JSON fields): the blocked path
+with the plain and the tuned small-block kernels (the paper's
+T_blocked / T_densified), and the split-precision FP64 emulation on INT8
+matrix cores.  Further legs: the banded uneven workload (block sizes from
+{5,13,23,32}, N ~ 50,000, 1 % and 10 % occupancy) plain vs tuned, and the
+460 x 460 sparse case's latency.  The CPU reference is timed on a bounded
+sample of the headline workload and checks the GPU results on those rows.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -46,6 +53,21 @@ def traffic_from_profile():
         return None
 
 
+def timed(torch, fn, reps):
+    """Wall time per call of fn (ms) over reps calls, bracketed by device syncs."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1e3 / reps
+
+
+def set_opts(bsmm, **kw):
+    for k, v in kw.items():
+        bsmm.bsmm_set_option(k, str(v))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -53,6 +75,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blocked", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the emulation, uneven and tiny legs")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -66,7 +89,7 @@ def main():
     import torch
 
     from paper_1910_04796_amd import bsmm
-    from synth import dense_square
+    from synth import banded_uneven, dense_square, sparse_uniform
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -80,6 +103,8 @@ def main():
         return
     bsmm.use_torch_allocator(0)
     stream = torch.cuda.current_stream()
+    bsmm.use_default_tuning()
+    set_opts(bsmm, path="auto", stack_kernel="plain")
     log("generating inputs")
     A, B = dense_square(seed=0, n=N, bs=BS)
     MA = bsmm.Matrix.from_blocks(A)
@@ -87,24 +112,20 @@ def main():
     MC = bsmm.Matrix.empty(A.rbs, B.cbs)
     F = 2.0 * N ** 3
 
-    bsmm.bsmm_set_option("path", "auto")
+    def step(C=MC):
+        bsmm.multiply(1.0, MA, MB, 0.0, C, 0.0, stream)
+
     for _ in range(args.warmup):
-        bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream)
+        step()
     torch.cuda.synchronize()
     log(f"warmup done ({args.warmup} steps)")
 
     bsmm.bsmm_set_option("time_kernels", "1")
     bsmm.bsmm_kernel_times(reset=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    ms_per_step = timed(torch, step, args.steps)
     gemm_ms, gemm_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
     bsmm.bsmm_set_option("time_kernels", "0")
     stats = bsmm.bsmm_last_stats()
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = F / (ms_per_step * 1e-3) / 1e9
     log(f"dense path: {ms_per_step:.3f} ms/step, {value:.1f} GFLOP/s, path={stats['path']}")
 
@@ -118,52 +139,123 @@ def main():
 
     blocked = None
     if not args.no_blocked:
-        bsmm.bsmm_set_option("path", "stack")
-        MC2 = bsmm.Matrix.empty(A.rbs, B.cbs)
-        bsmm.multiply(1.0, MA, MB, 0.0, MC2, 0.0, stream)
-        torch.cuda.synchronize()
-        reps = 3
-        tb0 = time.perf_counter()
-        for _ in range(reps):
-            bsmm.multiply(1.0, MA, MB, 0.0, MC2, 0.0, stream)
-        torch.cuda.synchronize()
-        tb1 = time.perf_counter()
-        bsmm.bsmm_set_option("path", "auto")
-        bms = (tb1 - tb0) * 1e3 / reps
-        blocked = {"path": "stack (plain small-block kernels)", "ms_per_step": round(bms, 3),
-                   "gflops": round(F / (bms * 1e-3) / 1e9, 1),
-                   "t_blocked_over_t_densified": round(bms / ms_per_step, 3)}
-        log(f"blocked path: {bms:.3f} ms/step")
-        MC2.close()
+        blocked = {}
+        for kern in ("plain", "tuned"):
+            set_opts(bsmm, path="stack", stack_kernel=kern)
+            MC2 = bsmm.Matrix.empty(A.rbs, B.cbs)
+            step(MC2)
+            bms = timed(torch, lambda: step(MC2), 3)
+            MC2.close()
+            blocked[kern] = {"ms_per_step": round(bms, 3), "gflops": round(F / (bms * 1e-3) / 1e9, 1),
+                             "t_blocked_over_t_densified": round(bms / ms_per_step, 3),
+                             "params_32x32x32": list(bsmm.bsmm_select_params(32, 32, 32))
+                             if kern == "tuned" else None}
+            log(f"blocked path ({kern}): {bms:.3f} ms/step")
+        set_opts(bsmm, path="auto", stack_kernel="plain")
+
+    extras = {}
+    MCe = None
+    if not args.no_extras:
+        # Split-precision emulation of the same product (7 slices).
+        set_opts(bsmm, path="emul", emul_slices=7)
+        MCe = bsmm.Matrix.empty(A.rbs, B.cbs)
+        step(MCe)
+        bsmm.bsmm_set_option("time_kernels", "1")
+        bsmm.bsmm_kernel_times(reset=True)
+        ems = timed(torch, lambda: step(MCe), 3)
+        eg_ms, eg_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
+        bsmm.bsmm_set_option("time_kernels", "0")
+        set_opts(bsmm, path="auto")
+        pairs = 7 * 8 // 2
+        ek = eg_ms / max(eg_n, 1)
+        extras["emulated_int8_s7"] = {
+            "ms_per_step": round(ems, 3), "gflops_fp64_equiv": round(F / (ems * 1e-3) / 1e9, 1),
+            "speedup_vs_dense_fp64": round(ms_per_step / ems, 3),
+            "gemm_kernel_ms": round(ek, 3),
+            "int8_tops_achieved": round(pairs * F / (ek * 1e-3) / 1e12, 1), "int8_peak_tops": 5000.0}
+        log(f"emulated path: {ems:.3f} ms/step (INT8 GEMM {ek:.3f} ms)")
+
+        # Banded uneven blocks {5,13,23,32}, N ~ 50,000: plain vs tuned stacks.
+        for occ in (0.01, 0.10):
+            U, V = banded_uneven(seed=0, occupancy=occ, target=50000)
+            MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
+            res = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
+            for kern in ("plain", "tuned"):
+                set_opts(bsmm, path="stack", stack_kernel=kern)
+                MW = bsmm.Matrix.empty(U.rbs, V.cbs)
+
+                def run(MW=MW):
+                    bsmm.multiply(1.0, MU, MV, 0.0, MW, 1e-10, stream)
+
+                run()
+                st = bsmm.bsmm_last_stats()
+                ums = timed(torch, run, 3)
+                res[kern] = {"ms_per_step": round(ums, 3),
+                             "gflops": round(st["flops"] / (ums * 1e-3) / 1e9, 1)}
+                res["flops_per_step"] = st["flops"]
+                res["products"] = st["n_products"]
+                res["classes"] = st["n_classes"]
+                MW.close()
+            res["tuned_speedup"] = round(res["plain"]["ms_per_step"] / res["tuned"]["ms_per_step"], 3)
+            extras[f"banded_uneven_{int(round(occ * 100))}pct"] = res
+            log(f"banded {occ}: plain {res['plain']['ms_per_step']} ms, tuned {res['tuned']['ms_per_step']} ms")
+            MU.close()
+            MV.close()
+            del U, V
+
+        # 460 x 460 in 23-blocks, 10 %: latency of one multiply.
+        S1, S2 = sparse_uniform(seed=0)
+        M1, M2 = bsmm.Matrix.from_blocks(S1), bsmm.Matrix.from_blocks(S2)
+        tiny = {}
+        for kern in ("plain", "tuned"):
+            set_opts(bsmm, path="stack", stack_kernel=kern)
+            M3 = bsmm.Matrix.empty(S1.rbs, S2.cbs)
+
+            def run3(M3=M3):
+                bsmm.multiply(1.0, M1, M2, 0.0, M3, 0.0, stream)
+
+            run3()
+            tiny[kern + "_us"] = round(1e3 * timed(torch, run3, 20), 1)
+            M3.close()
+        extras["sparse_460_b23_latency"] = tiny
+        set_opts(bsmm, path="auto", stack_kernel="plain")
+        M1.close()
+        M2.close()
 
     cpu = None
     rel_err = None
     if not args.no_cpu_baseline:
         # CPU baseline leg: the reference on a bounded sample of block rows,
-        # also used to check the GPU result on those rows.
+        # also used to check the GPU results on those rows.
         from oracle import oracle as orc
         threads = min(len(os.sched_getaffinity(0)), 16)
-        X = MC.to_host()
-        sizes = orc.block_sizes(X.rbs, X.cbs, X.row_ptr, X.col_ind)
-        elem_start = np.concatenate([[0], np.cumsum(sizes)])
         row_flops = 2.0 * BS * N * N  # one block row of C: 32 x 8192 x 8192
         orc.multiply(1.0, A, B, 0.0, rows=(0, 1), nthreads=threads)  # warm-up
         c0 = time.perf_counter()
         orc.multiply(1.0, A, B, 0.0, rows=(1, 2), nthreads=threads)
         t_row = time.perf_counter() - c0
-        nrows = int(max(1, min(N // BS - 17, 15.0 / max(t_row, 1e-3))))
         r0 = 17
+        nrows = int(max(1, min(N // BS - r0, 15.0 / max(t_row, 1e-3))))
         c0 = time.perf_counter()
         R = orc.multiply(1.0, A, B, 0.0, rows=(r0, r0 + nrows), nthreads=threads)
         t_cpu = time.perf_counter() - c0
-        e0 = int(elem_start[int(X.row_ptr[r0])])
-        e1 = int(elem_start[int(X.row_ptr[r0 + nrows])])
-        assert np.array_equal(X.col_ind[int(X.row_ptr[r0]):int(X.row_ptr[r0 + nrows])], R.col_ind)
-        rel_err = orc.rel_err(X.data[e0:e1], R.data)
         cpu = {"value": round(row_flops * nrows / t_cpu / 1e9, 3), "unit": "GFLOP/s",
                "cores": threads, "kind": "oracle",
                "sample": f"block rows {r0}..{r0 + nrows - 1} of 256 ({nrows * 32} of {N} rows of C), "
                          f"{t_cpu:.1f} s"}
+
+        def rows_err(M):
+            X = M.to_host()
+            sizes = orc.block_sizes(X.rbs, X.cbs, X.row_ptr, X.col_ind)
+            start = np.concatenate([[0], np.cumsum(sizes)])
+            e0 = int(start[int(X.row_ptr[r0])])
+            e1 = int(start[int(X.row_ptr[r0 + nrows])])
+            assert np.array_equal(X.col_ind[int(X.row_ptr[r0]):int(X.row_ptr[r0 + nrows])], R.col_ind)
+            return orc.rel_err(X.data[e0:e1], R.data)
+
+        rel_err = rows_err(MC)
+        if MCe is not None:
+            extras["emulated_int8_s7"]["rel_err"] = rows_err(MCe)
         log(f"cpu baseline: {cpu['value']} GFLOP/s on {threads} threads; rel_err {rel_err:.2e}")
 
     out = {
@@ -178,10 +270,12 @@ def main():
         "cpu_baseline": cpu,
         "rel_err": rel_err,
         "blocked": blocked,
+        "extras": extras,
     }
     print(json.dumps(out), flush=True)
-    for M in (MA, MB, MC):
-        M.close()
+    for M in (MA, MB, MC, MCe):
+        if M is not None:
+            M.close()
     bsmm.bsmm_set_allocator()
 
 

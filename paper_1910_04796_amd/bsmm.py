@@ -30,6 +30,11 @@ except ImportError:  # plain C-ABI use without PyTorch: the system runtime
 
 _lib = ctypes.CDLL(LIB_PATH)
 
+# Tuning results shipped with the package for gfx950 (tuning database and
+# learned-model weights); the tuned path reads them by default.
+DEFAULT_TUNE_DB = os.path.join(_HERE, "tune_db", "gfx950.txt")
+DEFAULT_MLP = os.path.join(_HERE, "tune_db", "gfx950_mlp.txt")
+
 BSMM_OK, BSMM_EINVAL, BSMM_ESHAPE, BSMM_EINDEX = 0, -1, -2, -3
 BSMM_ENOMEM, BSMM_EDEVICE, BSMM_ERANGE, BSMM_ENOTSUP = -4, -5, -6, -7
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EINDEX", -4: "ENOMEM",
@@ -359,6 +364,14 @@ def bsmm_mlp_train(params, x, t, epochs=30, batch=256, lr=1e-3, seed=0):
     return P, loss.value
 
 
+def use_default_tuning():
+    """Points the tuned path at the shipped database and model (if present)."""
+    if os.path.exists(DEFAULT_TUNE_DB):
+        bsmm_set_option("tune_db", DEFAULT_TUNE_DB)
+    if os.path.exists(DEFAULT_MLP):
+        bsmm_set_option("mlp_weights", DEFAULT_MLP)
+
+
 class HostBlockCSR:
     """Host copy of a matrix (numpy arrays)."""
 
@@ -412,3 +425,6 @@ class Matrix:
 def multiply(alpha, A, B, beta, C, filter_eps=0.0, stream=None):
     """C <- filter_eps(beta*C + alpha*A*B) on Matrix objects."""
     bsmm_multiply(alpha, A.handle, B.handle, beta, C.handle, filter_eps, stream)
+
+
+use_default_tuning()

@@ -30,34 +30,40 @@ typedef double double2_t __attribute__((ext_vector_type(2)));
 constexpr int BM = 128, BN = 128, BK = 16;
 constexpr int kGroupM = 8;
 
-// Merge: one workgroup per block row; each wave copies whole blocks into the
-// column-major panel (ld = panel rows).
-__global__ __launch_bounds__(256) void k_merge(const int32_t *rbs, const int32_t *cbs,
-                                               const int64_t *row_off, const int64_t *col_off,
-                                               const int64_t *rp, const int32_t *ci,
-                                               const int64_t *blk_off, const double *data,
-                                               double *panel, int64_t ld) {
-    const int32_t row = blockIdx.x;
-    const int nw = blockDim.x / kWave;
+// Merge: one wave per block (block row found by binary search in the row
+// pointer), copying the column-major block into the column-major panel
+// (ld = panel rows); consecutive lanes write consecutive rows of a column.
+__global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const int32_t *rbs,
+                                               const int32_t *cbs, const int64_t *row_off,
+                                               const int64_t *col_off, const int64_t *rp,
+                                               const int32_t *ci, const int64_t *blk_off,
+                                               const double *data, double *panel, int64_t ld) {
+    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (p >= nnzb) return;
+    int32_t lo = 0, hi = nbr;  // row = last lo with rp[lo] <= p
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    const int32_t row = lo;
     const int m = rbs[row];
     const int64_t r0 = row_off[row];
-    for (int64_t p = rp[row] + wave_id(); p < rp[row + 1]; p += nw) {
-        const int32_t j = ci[p];
-        const int n = cbs[j];
-        const int64_t c0 = col_off[j];
-        const double *src = data + blk_off[p];
-        const int64_t len = (int64_t)m * n;
-        if (len < (1 << 20) && m < 4096) {
-            const float rcp = 1.0f / (float)m;
-            for (int e = lane_id(); e < len; e += kWave) {
-                int ii;
-                const int jj = divmod_small(e, m, rcp, &ii);
-                panel[(c0 + jj) * ld + r0 + ii] = src[e];
-            }
-        } else {
-            for (int64_t e = lane_id(); e < len; e += kWave)
-                panel[(c0 + e / m) * ld + r0 + e % m] = src[e];
+    const int32_t j = ci[p];
+    const int n = cbs[j];
+    const int64_t c0 = col_off[j];
+    const double *src = data + blk_off[p];
+    const int64_t len = (int64_t)m * n;
+    if (len < (1 << 20) && m < 4096) {
+        const float rcp = 1.0f / (float)m;
+        for (int e = lane_id(); e < len; e += kWave) {
+            int ii;
+            const int jj = divmod_small(e, m, rcp, &ii);
+            panel[(c0 + jj) * ld + r0 + ii] = src[e];
         }
+    } else {
+        for (int64_t e = lane_id(); e < len; e += kWave)
+            panel[(c0 + e / m) * ld + r0 + e % m] = src[e];
     }
 }
 
@@ -231,13 +237,15 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     if (!A->full() || Mp != M || Kp != K) BSMM_TRY(fill_zero(ap.as<double>(), Mp * Kp, s));
     if (!B->full() || Kp != K || Np != N) BSMM_TRY(fill_zero(bp.as<double>(), Kp * Np, s));
     if (A->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge, dim3(A->nbr), dim3(256), 0, s, A->d_rbs(), A->d_cbs(),
+        hipLaunchKernelGGL(k_merge, dim3(grid_of(A->nnzb, 4)), dim3(256), 0, s, A->nbr, A->nnzb,
+                           A->d_rbs(), A->d_cbs(),
                            A->d_row_off(), A->d_col_off(), A->d_row_ptr(), A->d_col_ind(),
                            A->d_blk_off(), A->d_data(), ap.as<double>(), Mp);
         BSMM_TRY(launch_check("merge_A"));
     }
     if (B->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge, dim3(B->nbr), dim3(256), 0, s, B->d_rbs(), B->d_cbs(),
+        hipLaunchKernelGGL(k_merge, dim3(grid_of(B->nnzb, 4)), dim3(256), 0, s, B->nbr, B->nnzb,
+                           B->d_rbs(), B->d_cbs(),
                            B->d_row_off(), B->d_col_off(), B->d_row_ptr(), B->d_col_ind(),
                            B->d_blk_off(), B->d_data(), bp.as<double>(), Kp);
         BSMM_TRY(launch_check("merge_B"));

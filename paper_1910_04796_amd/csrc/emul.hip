@@ -103,6 +103,9 @@ struct EmulArgs {
 
 template <int S>
 __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
+    // The recombination rounds every product and sum separately (no fused
+    // multiply-add), matching the method's definition step by step.
+#pragma clang fp contract(off)
     __shared__ __attribute__((aligned(16))) signed char lA[S][ET * ELD];
     __shared__ __attribute__((aligned(16))) signed char lB[S][ET * ELD];
     const int tiles_n = (int)(g.Np / ET);
@@ -184,49 +187,57 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
             }
 }
 
-// Transposing merge: block (I,K) of A lands at rows r0.. of the row-major
-// panel At[i][k] (ld = panel columns).
-__global__ __launch_bounds__(256) void k_merge_t(const int32_t *rbs, const int32_t *cbs,
-                                                 const int64_t *row_off, const int64_t *col_off,
-                                                 const int64_t *rp, const int32_t *ci,
-                                                 const int64_t *blk_off, const double *data,
-                                                 double *panel, int64_t ld) {
-    const int32_t row = blockIdx.x;
-    const int nw = blockDim.x / kWave;
-    const int m = rbs[row];
-    const int64_t r0 = row_off[row];
-    for (int64_t p = rp[row] + wave_id(); p < rp[row + 1]; p += nw) {
-        const int32_t j = ci[p];
-        const int n = cbs[j];
-        const int64_t c0 = col_off[j];
-        const double *src = data + blk_off[p];
-        const int64_t len = (int64_t)m * n;
-        for (int64_t e = lane_id(); e < len; e += kWave) {
-            const int64_t jj = e / m, ii = e - jj * m;
-            panel[(r0 + ii) * ld + c0 + jj] = src[e];
-        }
+// Transposing merge (one wave per block): block (I,K) of A lands at rows
+// r0.. of the row-major panel At[i][k] (ld = panel columns).
+__global__ __launch_bounds__(256) void k_merge_t(int32_t nbr, int64_t nnzb, const int32_t *rbs,
+                                                 const int32_t *cbs, const int64_t *row_off,
+                                                 const int64_t *col_off, const int64_t *rp,
+                                                 const int32_t *ci, const int64_t *blk_off,
+                                                 const double *data, double *panel, int64_t ld) {
+    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (p >= nnzb) return;
+    int32_t lo = 0, hi = nbr;  // block row: rp[lo] <= p < rp[lo + 1]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    const int m = rbs[lo];
+    const int64_t r0 = row_off[lo];
+    const int32_t j = ci[p];
+    const int n = cbs[j];
+    const int64_t c0 = col_off[j];
+    const double *src = data + blk_off[p];
+    const int64_t len = (int64_t)m * n;
+    for (int64_t e = lane_id(); e < len; e += kWave) {
+        const int64_t jj = e / m, ii = e - jj * m;
+        panel[(r0 + ii) * ld + c0 + jj] = src[e];
     }
 }
 
-__global__ __launch_bounds__(256) void k_merge_c(const int32_t *rbs, const int32_t *cbs,
-                                                 const int64_t *row_off, const int64_t *col_off,
-                                                 const int64_t *rp, const int32_t *ci,
-                                                 const int64_t *blk_off, const double *data,
-                                                 double *panel, int64_t ld) {
-    const int32_t row = blockIdx.x;
-    const int nw = blockDim.x / kWave;
-    const int m = rbs[row];
-    const int64_t r0 = row_off[row];
-    for (int64_t p = rp[row] + wave_id(); p < rp[row + 1]; p += nw) {
-        const int32_t j = ci[p];
-        const int n = cbs[j];
-        const int64_t c0 = col_off[j];
-        const double *src = data + blk_off[p];
-        const int64_t len = (int64_t)m * n;
-        for (int64_t e = lane_id(); e < len; e += kWave) {
-            const int64_t jj = e / m, ii = e - jj * m;
-            panel[(c0 + jj) * ld + r0 + ii] = src[e];
-        }
+__global__ __launch_bounds__(256) void k_merge_c(int32_t nbr, int64_t nnzb, const int32_t *rbs,
+                                                 const int32_t *cbs, const int64_t *row_off,
+                                                 const int64_t *col_off, const int64_t *rp,
+                                                 const int32_t *ci, const int64_t *blk_off,
+                                                 const double *data, double *panel, int64_t ld) {
+    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    if (p >= nnzb) return;
+    int32_t lo = 0, hi = nbr;  // block row: rp[lo] <= p < rp[lo + 1]
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= p) lo = mid;
+        else hi = mid;
+    }
+    const int m = rbs[lo];
+    const int64_t r0 = row_off[lo];
+    const int32_t j = ci[p];
+    const int n = cbs[j];
+    const int64_t c0 = col_off[j];
+    const double *src = data + blk_off[p];
+    const int64_t len = (int64_t)m * n;
+    for (int64_t e = lane_id(); e < len; e += kWave) {
+        const int64_t jj = e / m, ii = e - jj * m;
+        panel[(c0 + jj) * ld + r0 + ii] = src[e];
     }
 }
 
@@ -283,13 +294,15 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
     BSMM_TRY(fill_zero(at.as<double>(), Mp * Kp, s));
     BSMM_TRY(fill_zero(bp.as<double>(), Kp * Np, s));
     if (A->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge_t, dim3(A->nbr), dim3(256), 0, s, A->d_rbs(), A->d_cbs(),
+        hipLaunchKernelGGL(k_merge_t, dim3(grid_of(A->nnzb, 4)), dim3(256), 0, s, A->nbr, A->nnzb,
+                           A->d_rbs(), A->d_cbs(),
                            A->d_row_off(), A->d_col_off(), A->d_row_ptr(), A->d_col_ind(),
                            A->d_blk_off(), A->d_data(), at.as<double>(), Kp);
         BSMM_TRY(launch_check("emul merge A"));
     }
     if (B->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge_c, dim3(B->nbr), dim3(256), 0, s, B->d_rbs(), B->d_cbs(),
+        hipLaunchKernelGGL(k_merge_c, dim3(grid_of(B->nnzb, 4)), dim3(256), 0, s, B->nbr, B->nnzb,
+                           B->d_rbs(), B->d_cbs(),
                            B->d_row_off(), B->d_col_off(), B->d_row_ptr(), B->d_col_ind(),
                            B->d_blk_off(), B->d_data(), bp.as<double>(), Kp);
         BSMM_TRY(launch_check("emul merge B"));
