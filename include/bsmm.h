@@ -153,6 +153,13 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
  *   "mlp_weights" path of a learned-model weight file ("" = none)
  *   "stack_params" "TM TN KC WAVES": the tuned path uses this parameter
  *                 set for every shape class ("" = select per shape)
+ *   "plan_cache"  "1": a multiply into C keeps its plan (symbolic totals,
+ *                 stacks, launches or instantiated hipGraph); the next
+ *                 multiply into C with the same A and B handles, unchanged
+ *                 patterns and buffers of A, B and C, the same alpha, beta
+ *                 and options skips the symbolic phase and the stack build
+ *                 and replays the launches (no host synchronisation unless
+ *                 the filter drops blocks).  "0" (default) plans every call.
  *   "time_kernels" "1" brackets every dense-GEMM and stack-kernel launch
  *                 with HIP events on the launch stream (see
  *                 bsmm_kernel_times); "0" (default) records nothing

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <cstdarg>
 #include <cstring>
+#include <atomic>
 #include <map>
 #include <mutex>
 #include <unordered_map>
@@ -44,6 +45,11 @@ int launch_check(const char *what) {
 Options &options() {
     static Options o;
     return o;
+}
+
+uint64_t next_version() {
+    static std::atomic<uint64_t> v{1};
+    return v.fetch_add(1);
 }
 
 // ------------------------------------------------------------------- pool
@@ -261,6 +267,7 @@ extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int
     M->max_rbs = nbr ? *std::max_element(M->rbs.begin(), M->rbs.end()) : 0;
     M->max_cbs = nbc ? *std::max_element(M->cbs.begin(), M->cbs.end()) : 0;
     M->last_stream = s;
+    M->version = next_version();
     {
         int ndev = 0;
         hipError_t e1 = hipGetDeviceCount(&ndev);
@@ -427,6 +434,10 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         for (int i = 0; i < 4; ++i) o.forced[i] = q[i];
     } else if (k == "mlp_weights") {
         o.mlp_weights = v;
+    } else if (k == "plan_cache") {
+        if (v == "0") o.plan_cache = 0;
+        else if (v == "1") o.plan_cache = 1;
+        else goto bad;
     } else if (k == "time_kernels") {
         if (v == "0") o.time_kernels = 0;
         else if (v == "1") o.time_kernels = 1;
@@ -455,6 +466,7 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     else if (k == "stack_chunk") v = std::to_string(o.stack_chunk);
     else if (k == "tune_db") v = o.tune_db;
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
+    else if (k == "plan_cache") v = std::to_string(o.plan_cache);
     else if (k == "mlp_weights") v = o.mlp_weights;
     else if (k == "stack_params")
         v = o.forced[0] ? std::to_string(o.forced[0]) + " " + std::to_string(o.forced[1]) + " " +

@@ -100,6 +100,7 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     C->b_data = std::move(n_data);
     C->nnzb = new_nnzb;
     C->nelems = new_elems;
+    C->version = next_version();
     return BSMM_OK;
 }
 

@@ -51,6 +51,7 @@ struct Options {
     int stack_kernel = 0;  // 0 plain, 1 tuned
     int64_t stack_chunk = 0;
     int time_kernels = 0;
+    int plan_cache = 0;            // reuse symbolic result + stacks + graph when patterns repeat
     std::string tune_db;
     std::string mlp_weights;
     int forced[4] = {0, 0, 0, 0};  // "stack_params": tm tn kc waves for every class
@@ -120,6 +121,12 @@ struct DevBuf {
 
 }  // namespace bsmm
 
+namespace bsmm {
+struct Plan;
+void free_plan(Plan *p);
+uint64_t next_version();
+}  // namespace bsmm
+
 // ------------------------------------------------------------------ matrix
 struct bsmm_matrix_s {
     int32_t nbr = 0, nbc = 0;
@@ -129,6 +136,9 @@ struct bsmm_matrix_s {
     int32_t max_rbs = 0, max_cbs = 0;
     int device = 0;
     hipStream_t last_stream = nullptr;
+    uint64_t version = 0;          // changes whenever the pattern or a buffer changes
+    bsmm::Plan *plan = nullptr;    // cached multiply plan of which this matrix is C
+    ~bsmm_matrix_s() { bsmm::free_plan(plan); }
 
     bsmm::DevBuf b_rbs, b_cbs, b_row_off, b_col_off, b_row_map, b_col_map;
     bsmm::DevBuf b_row_ptr, b_col_ind, b_blk_off, b_data;
@@ -243,9 +253,19 @@ unsigned smm_grid(const SmmLaunch &L, int64_t nruns);
 int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const int64_t *run_coff,
                const int64_t *run_ptr, const ulonglong2 *prods, int64_t rb, int64_t re,
                double alpha, double beta, hipStream_t s);
-int run_graph(const std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>> &launches,
-              const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, const Stacks &st,
-              double alpha, double beta, hipStream_t s);
+using LaunchList = std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>>;
+// Launches of one stack execution: per-class launches (plain) or one
+// instantiated hipGraph holding every class (tuned).
+struct StackExec {
+    LaunchList launches;
+    hipGraphExec_t exec = nullptr;
+    StackExec() = default;
+    StackExec(const StackExec &) = delete;
+    StackExec &operator=(const StackExec &) = delete;
+    ~StackExec() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+    }
+};
 SmmParams plain_params(int m, int n);
 // Selected parameters for shape (m, n, k): tuning database, then learned
 // model, then the plain rule.
@@ -255,8 +275,15 @@ std::vector<SmmParams> candidate_params(int m, int n, int k);
 // Learned model: ranks the candidates of (m, n, k) by predicted time; false
 // when no model is loaded.
 bool mlp_select(int m, int n, int k, SmmParams *out);
+// Plans and launches the stack kernels; the launches (and the instantiated
+// graph of the tuned path) are kept in *ex for replay.
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
-               const Stacks &st, double alpha, double beta, hipStream_t s);
+               const Stacks &st, double alpha, double beta, hipStream_t s, StackExec *ex);
+int build_graph(const LaunchList &launches, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
+                bsmm_matrix_s *C, const Stacks &st, double alpha, double beta,
+                hipGraphExec_t *out);
+int replay_stacks(const StackExec &ex, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
+                  bsmm_matrix_s *C, const Stacks &st, double alpha, double beta, hipStream_t s);
 
 // ----------------------------------------------------------------- dense
 int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,

@@ -136,46 +136,122 @@ int install_pattern(bsmm_matrix_s *C, const SymbolicTotals &tot, NewPattern &np,
     C->b_data = std::move(np.data);
     C->nnzb = tot.nnzb;
     C->nelems = tot.nelems;
+    C->version = next_version();
     return BSMM_OK;
+}
+
+// Options that change what a plan computes.
+std::string plan_key(const Options &o) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "%d %d %lld %d %d %d %d %d|", o.path, o.stack_kernel,
+             (long long)o.stack_chunk, o.emul_slices, o.forced[0], o.forced[1], o.forced[2],
+             o.forced[3]);
+    return std::string(buf) + o.tune_db + "|" + o.mlp_weights;
+}
+
+}  // namespace
+
+// A cached multiply: the symbolic totals, the stacks and their launches (or
+// instantiated graph), valid while A, B and C keep the versions recorded.
+struct Plan {
+    const bsmm_matrix_s *A = nullptr, *B = nullptr;
+    uint64_t va = 0, vb = 0, vc = 0;
+    std::string key;
+    double alpha = 0.0, beta = 0.0;
+    SymbolicTotals tot;
+    int path = 0;
+    Stacks st;
+    StackExec ex;
+};
+void free_plan(Plan *p) { delete p; }
+
+namespace {
+
+int numeric(int path, bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, double alpha,
+            double beta, const Options &o, Stacks &st, StackExec &ex, bool replay, hipStream_t s) {
+    switch (path) {
+    case 0:
+        if (beta != 1.0) BSMM_TRY(scale_blocks(C, nullptr, beta, s));
+        return BSMM_OK;
+    case 3:
+        return emul_multiply(A, B, C, alpha, beta, o.emul_slices, s);
+    case 2:
+        return dense_multiply(A, B, C, alpha, beta, s);
+    default:
+        if (replay) BSMM_TRY(replay_stacks(ex, A, B, C, st, alpha, beta, s));
+        else {
+            BSMM_TRY(build_stacks(A, B, C, st, s));
+            BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s, &ex));
+        }
+        if (beta != 1.0 && st.n_runs < C->nnzb)
+            BSMM_TRY(scale_blocks(C, st.c_count.as<int64_t>(), beta, s));
+        return BSMM_OK;
+    }
 }
 
 int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
                   bsmm_matrix_s *C, double eps, hipStream_t s) {
     bsmm_multiply_stats &stt = stats();
     stt = bsmm_multiply_stats{};
-    SymbolicTotals tot;
-    bool changed = false;
-    NewPattern np;
-    DevBuf row_elems;
-    BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s));
-    if (changed) BSMM_TRY(install_pattern(C, tot, np, row_elems, beta, s));
-    stt.c_nnzb_before = C->nnzb;
-    stt.n_products = tot.nprod;
-    stt.flops = tot.flops;
-
     const Options &o = options();
-    const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
-    if (alpha == 0.0 || tot.nprod == 0) {
-        if (beta != 1.0) BSMM_TRY(scale_blocks(C, nullptr, beta, s));
-        stt.path = 0;
-    } else if (o.path == 3) {
-        stt.path = 3;
-        BSMM_TRY(emul_multiply(A, B, C, alpha, beta, o.emul_slices, s));
-    } else if (dense) {
-        stt.path = 2;
-        BSMM_TRY(dense_multiply(A, B, C, alpha, beta, s));
-    } else {
-        stt.path = 1;
-        Stacks st;
-        st.n_prod = tot.nprod;
-        BSMM_TRY(build_stacks(A, B, C, st, s));
-        stt.n_runs = st.n_runs;
+    Plan *pl = C->plan;
+    const bool hit = o.plan_cache && pl && pl->A == A && pl->B == B && pl->va == A->version &&
+                     pl->vb == B->version && pl->vc == C->version && pl->alpha == alpha &&
+                     pl->beta == beta && pl->key == plan_key(o);
+    if (hit) {
+        // Same patterns, buffers and options as the planned multiply: C's
+        // pattern already holds the product, the stacks are still valid.
+        BSMM_TRY(numeric(pl->path, A, B, C, alpha, beta, o, pl->st, pl->ex, true, s));
+        stt.path = pl->path;
+        stt.c_nnzb_before = C->nnzb;
+        stt.n_products = pl->tot.nprod;
+        stt.flops = pl->tot.flops;
+        stt.n_runs = pl->st.n_runs;
         int nc = 0;
-        for (int cl = 0; cl < st.n_classes; ++cl) nc += st.class_begin[cl + 1] > st.class_begin[cl];
+        for (int cl = 0; cl < pl->st.n_classes; ++cl)
+            nc += pl->st.class_begin[cl + 1] > pl->st.class_begin[cl];
         stt.n_classes = nc;
-        BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s));
-        if (beta != 1.0 && st.n_runs < C->nnzb)
-            BSMM_TRY(scale_blocks(C, st.c_count.as<int64_t>(), beta, s));
+    } else {
+        free_plan(C->plan);
+        C->plan = nullptr;
+        SymbolicTotals tot;
+        bool changed = false;
+        NewPattern np;
+        DevBuf row_elems;
+        BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s));
+        if (changed) BSMM_TRY(install_pattern(C, tot, np, row_elems, beta, s));
+        stt.c_nnzb_before = C->nnzb;
+        stt.n_products = tot.nprod;
+        stt.flops = tot.flops;
+        const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
+        const int path = (alpha == 0.0 || tot.nprod == 0) ? 0 : o.path == 3 ? 3 : dense ? 2 : 1;
+        auto *p = new Plan();
+        p->st.n_prod = tot.nprod;
+        const int status = numeric(path, A, B, C, alpha, beta, o, p->st, p->ex, false, s);
+        if (status != BSMM_OK) {
+            delete p;
+            return status;
+        }
+        stt.path = path;
+        stt.n_runs = p->st.n_runs;
+        int nc = 0;
+        for (int cl = 0; cl < p->st.n_classes; ++cl) nc += p->st.class_begin[cl + 1] > p->st.class_begin[cl];
+        stt.n_classes = nc;
+        if (o.plan_cache) {
+            p->A = A;
+            p->B = B;
+            p->va = A->version;
+            p->vb = B->version;
+            p->vc = C->version;
+            p->key = plan_key(o);
+            p->alpha = alpha;
+            p->beta = beta;
+            p->tot = tot;
+            p->path = path;
+            C->plan = p;
+        } else {
+            delete p;
+        }
     }
     int64_t after = C->nnzb;
     BSMM_TRY(filter_blocks(C, eps, &after, s));

@@ -267,7 +267,8 @@ static int representative_k(const bsmm_matrix_s *A) {
 }
 
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
-               const Stacks &st, double alpha, double beta, hipStream_t s) {
+               const Stacks &st, double alpha, double beta, hipStream_t s, StackExec *ex) {
+    ex->launches.clear();
     if (st.n_runs == 0) return BSMM_OK;
     const int kmax = std::max(1, A->max_cbs);
     const int64_t chunk = options().stack_chunk;
@@ -280,7 +281,7 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                                 hipMemcpyDeviceToHost, s));
         BSMM_HIP(hipStreamSynchronize(s));
     }
-    std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>> launches;
+    LaunchList &launches = ex->launches;
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t rb = st.class_begin[cl], re = st.class_begin[cl + 1];
         if (re <= rb) continue;
@@ -302,8 +303,18 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         }
     }
     if (tuned && chunk <= 0 && launches.size() > 1)
-        return run_graph(launches, A, B, C, st, alpha, beta, s);
-    for (auto &l : launches)
+        BSMM_TRY(build_graph(launches, A, B, C, st, alpha, beta, &ex->exec));
+    return replay_stacks(*ex, A, B, C, st, alpha, beta, s);
+}
+
+int replay_stacks(const StackExec &ex, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
+                  bsmm_matrix_s *C, const Stacks &st, double alpha, double beta, hipStream_t s) {
+    if (ex.exec) {
+        KernelTimer kt(1, s);
+        BSMM_HIP(hipGraphLaunch(ex.exec, s));
+        return BSMM_OK;
+    }
+    for (auto &l : ex.launches)
         BSMM_TRY(launch_smm(l.first, A->d_data(), B->d_data(), C->d_data(),
                             st.run_coff.as<int64_t>(), st.run_ptr.as<int64_t>(),
                             st.prods.as<ulonglong2>(), l.second.first, l.second.second, alpha, beta,
@@ -311,21 +322,18 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
     return BSMM_OK;
 }
 
-// Tuned path: all shape classes as independent kernel nodes of one hipGraph,
-// launched once, so classes run concurrently.
-int run_graph(const std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>> &launches,
-              const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, const Stacks &st,
-              double alpha, double beta, hipStream_t s) {
+// Tuned path: all shape classes as independent kernel nodes of one hipGraph
+// (launched once, classes run concurrently).  The kernel arguments are
+// copied into the graph when the nodes are added.
+int build_graph(const LaunchList &launches, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
+                bsmm_matrix_s *C, const Stacks &st, double alpha, double beta,
+                hipGraphExec_t *out) {
     hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
     BSMM_HIP(hipGraphCreate(&graph, 0));
-    std::vector<SmmArgs> args(launches.size());
-    std::vector<void *> argp(launches.size());
     int status = BSMM_OK;
     for (size_t i = 0; i < launches.size() && status == BSMM_OK; ++i) {
         const SmmLaunch &L = launches[i].first;
-        SmmArgs &a = args[i];
-        a = L.args;
+        SmmArgs a = L.args;
         a.A = A->d_data();
         a.B = B->d_data();
         a.C = C->d_data();
@@ -336,13 +344,13 @@ int run_graph(const std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>
         a.run_end = launches[i].second.second;
         a.alpha = alpha;
         a.beta = beta;
-        argp[i] = &a;
+        void *argp = &a;
         hipKernelNodeParams kp{};
         kp.func = L.fn;
         kp.gridDim = dim3(smm_grid(L, a.run_end - a.run_begin));
         kp.blockDim = dim3(64 * L.waves);
         kp.sharedMemBytes = (unsigned)L.lds;
-        kp.kernelParams = &argp[i];
+        kp.kernelParams = &argp;
         kp.extra = nullptr;
         hipGraphNode_t node;
         if (hipGraphAddKernelNode(&node, graph, nullptr, 0, &kp) != hipSuccess) {
@@ -350,18 +358,11 @@ int run_graph(const std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>
             status = BSMM_EDEVICE;
         }
     }
-    if (status == BSMM_OK && hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+    if (status == BSMM_OK && hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess) {
         set_error(BSMM_EDEVICE, "hipGraphInstantiate failed");
+        *out = nullptr;
         status = BSMM_EDEVICE;
     }
-    if (status == BSMM_OK) {
-        KernelTimer kt(1, s);
-        if (hipGraphLaunch(exec, s) != hipSuccess) {
-            set_error(BSMM_EDEVICE, "hipGraphLaunch failed");
-            status = BSMM_EDEVICE;
-        }
-    }
-    if (exec) (void)hipGraphExecDestroy(exec);
     (void)hipGraphDestroy(graph);
     (void)hipGetLastError();
     return status;

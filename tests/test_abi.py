@@ -58,7 +58,8 @@ def test_multiply_rejects_null_handles():
 def test_options_round_trip():
     from paper_1910_04796_amd import bsmm as b
     for k, v in [("path", "dense"), ("path", "stack"), ("path", "emul"), ("path", "auto"),
-                 ("emul_slices", "5"), ("emul_slices", "7"), ("stack_kernel", "tuned"),
+                 ("emul_slices", "5"), ("emul_slices", "7"), ("plan_cache", "1"), ("plan_cache", "0"),
+                 ("stack_kernel", "tuned"),
                  ("stack_kernel", "plain"), ("stack_chunk", "30000"), ("stack_chunk", "0")]:
         b.bsmm_set_option(k, v)
         assert b.bsmm_get_option(k) == v

@@ -98,3 +98,34 @@ def test_committed_database_beats_plain():
         plain = list(b.bsmm_select_params(m, n, k))
         us = b.bsmm_tune_shape(m, n, k, np.array([best, plain, best, plain], np.int32), reps=5)
         assert min(us[0], us[2]) <= 1.10 * min(us[1], us[3]), (m, n, k, best, plain, us.tolist())
+
+
+@pytest.mark.parametrize("kernel", ["plain", "tuned"])
+def test_plan_cache_replay_matches(kernel):
+    """With the plan cache, repeated multiplies into one C replay the planned
+    launches and give the same bits as planning every call."""
+    b = lib()
+    A, B = banded_uneven(seed=33, occupancy=0.2, target=900)
+    outs = []
+    for cache in ("0", "1"):
+        b.bsmm_set_option("plan_cache", cache)
+        b.bsmm_set_option("path", "stack")
+        b.bsmm_set_option("stack_kernel", kernel)
+        try:
+            MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
+            MC = b.Matrix.empty(A.rbs, B.cbs)
+            for beta in (0.0, 0.5, 0.5, 0.5):
+                b.multiply(1.0, MA, MB, beta, MC)
+            st = b.bsmm_last_stats()
+            outs.append(MC.to_host())
+            for M in (MA, MB, MC):
+                M.close()
+        finally:
+            b.bsmm_set_option("plan_cache", "0")
+            b.bsmm_set_option("path", "auto")
+            b.bsmm_set_option("stack_kernel", "plain")
+        assert st["path"] == 1 and st["n_products"] > 0
+    assert np.array_equal(outs[0].data, outs[1].data)
+    # beta = 0 then three times beta = 0.5: C = (1 + 0.5 + 0.25 + 0.125) A B
+    R = orc.multiply(1.875, A, B, 0.0)
+    check_against_oracle(outs[1], R, TOL)
