@@ -137,6 +137,19 @@ def main():
                 "kernel_ms": round(gemm_avg_ms, 4), "launches": gemm_n,
                 "traffic": traffic_from_profile()}
 
+    # The 32-deep k-step variant of the same GEMM, for comparison.
+    bsmm.bsmm_set_option("dense_kb", "32")
+    step()
+    bsmm.bsmm_set_option("time_kernels", "1")
+    bsmm.bsmm_kernel_times(reset=True)
+    kb32_ms = timed(torch, step, 3)
+    g32_ms, g32_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
+    bsmm.bsmm_set_option("time_kernels", "0")
+    bsmm.bsmm_set_option("dense_kb", "16")
+    dense_kb32 = {"ms_per_step": round(kb32_ms, 3), "gemm_kernel_ms": round(g32_ms / max(g32_n, 1), 3),
+                  "gemm_tflops": round(F / (g32_ms / max(g32_n, 1) * 1e-3) / 1e12, 2)}
+    log(f"dense path, k step 32: {kb32_ms:.3f} ms/step")
+
     blocked = None
     if not args.no_blocked:
         blocked = {}
@@ -270,6 +283,7 @@ def main():
         "cpu_baseline": cpu,
         "rel_err": rel_err,
         "blocked": blocked,
+        "dense_kb32": dense_kb32,
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

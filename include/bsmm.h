@@ -153,6 +153,8 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
  *   "mlp_weights" path of a learned-model weight file ("" = none)
  *   "stack_params" "TM TN KC WAVES": the tuned path uses this parameter
  *                 set for every shape class ("" = select per shape)
+ *   "dense_kb"    k step of the dense FP64 GEMM: "16" (default; 64 KB of
+ *                 LDS, two workgroups per CU) or "32" (128 KB, one per CU)
  *   "plan_cache"  "1": a multiply into C keeps its plan (symbolic totals,
  *                 stacks, launches or instantiated hipGraph); the next
  *                 multiply into C with the same A and B handles, unchanged

@@ -434,6 +434,10 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         for (int i = 0; i < 4; ++i) o.forced[i] = q[i];
     } else if (k == "mlp_weights") {
         o.mlp_weights = v;
+    } else if (k == "dense_kb") {
+        if (v == "16") o.dense_kb = 16;
+        else if (v == "32") o.dense_kb = 32;
+        else goto bad;
     } else if (k == "plan_cache") {
         if (v == "0") o.plan_cache = 0;
         else if (v == "1") o.plan_cache = 1;
@@ -467,6 +471,7 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     else if (k == "tune_db") v = o.tune_db;
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
     else if (k == "plan_cache") v = std::to_string(o.plan_cache);
+    else if (k == "dense_kb") v = std::to_string(o.dense_kb);
     else if (k == "mlp_weights") v = o.mlp_weights;
     else if (k == "stack_params")
         v = o.forced[0] ? std::to_string(o.forced[0]) + " " + std::to_string(o.forced[1]) + " " +

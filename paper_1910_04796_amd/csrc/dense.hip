@@ -10,8 +10,8 @@
 // epilogue, which writes C = beta*C + alpha*(Ap Bp) straight into C's
 // blocks through per-row and per-column (block, offset) maps.
 //
-// GEMM: 128 x 128 output tile per 256-thread workgroup, k step 16, LDS double
-// buffered; each wave owns a 64 x 64 sub-tile as 4 x 4 MFMA tiles of
+// GEMM: 128 x 128 output tile per 256-thread workgroup, k step 16 (or 32),
+// LDS double buffered; each wave owns a 64 x 64 sub-tile as 4 x 4 MFMA tiles of
 // v_mfma_f64_16x16x4 (FP64 in, FP64 accumulate).  Workgroup ids are remapped
 // so that the tiles dispatched to one XCD form a contiguous band of
 // 8 tile-rows (shared A panels stay in that XCD's L2).
@@ -27,7 +27,7 @@ namespace {
 typedef double double4_t __attribute__((ext_vector_type(4)));
 typedef double double2_t __attribute__((ext_vector_type(2)));
 
-constexpr int BM = 128, BN = 128, BK = 16;
+constexpr int BM = 128, BN = 128;
 constexpr int kGroupM = 8;
 
 // Merge: one wave per block (block row found by binary search in the row
@@ -82,50 +82,56 @@ struct GemmArgs {
     const int2 *rmap, *cmap;
 };
 
-// Global -> register loads of one k step: A tile (128 rows x 16 k) as 1024
-// double2 along the rows, B tile (16 k x 128 cols) as 1024 double2 along k.
-__device__ __forceinline__ void gemm_gload(double2_t (&ra)[4], double2_t (&rb)[4], const double *Ablk,
-                                           const double *Bblk, int64_t lda, int64_t ldb, int kt,
-                                           int tid) {
-    const int64_t k0 = (int64_t)kt * BK;
+// Global -> register loads of one k step of KB: A tile (128 rows x KB k) as
+// KB * 64 double2 along the rows, B tile (KB k x 128 cols) along k.
+template <int KB>
+__device__ __forceinline__ void gemm_gload(double2_t (&ra)[KB / 4], double2_t (&rb)[KB / 4],
+                                           const double *Ablk, const double *Bblk, int64_t lda,
+                                           int64_t ldb, int kt, int tid) {
+    const int64_t k0 = (int64_t)kt * KB;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
         const int kk = e >> 6, r2 = e & 63;
         ra[i] = *reinterpret_cast<const double2_t *>(Ablk + (k0 + kk) * lda + 2 * r2);
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
-        const int col = e >> 3, k2 = e & 7;
+        const int col = e / (KB / 2), k2 = e % (KB / 2);
         rb[i] = *reinterpret_cast<const double2_t *>(Bblk + (int64_t)col * ldb + k0 + 2 * k2);
     }
 }
 
 // Register -> LDS stores: As[k][m]; Bs[n][k ^ (n & 15)] (XOR swizzle keeps
 // the 16 lanes that read one k of 16 consecutive columns on distinct banks).
-__device__ __forceinline__ void gemm_lstore(const double2_t (&ra)[4], const double2_t (&rb)[4],
-                                            double *As, double *Bs, int tid) {
+template <int KB>
+__device__ __forceinline__ void gemm_lstore(const double2_t (&ra)[KB / 4],
+                                            const double2_t (&rb)[KB / 4], double *As, double *Bs,
+                                            int tid) {
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
         const int kk = e >> 6, r2 = e & 63;
         *reinterpret_cast<double2_t *>(&As[kk * BM + 2 * r2]) = ra[i];
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
-        const int col = e >> 3, k2 = e & 7;
+        const int col = e / (KB / 2), k2 = e % (KB / 2);
         const int sw = col & 15;
         const int base = (2 * k2) ^ (sw & ~1);
         const double2_t v = (sw & 1) ? rb[i].yx : rb[i];
-        *reinterpret_cast<double2_t *>(&Bs[col * BK + base]) = v;
+        *reinterpret_cast<double2_t *>(&Bs[col * KB + base]) = v;
     }
 }
 
-__global__ __launch_bounds__(256, 2) void k_dgemm_mfma(GemmArgs g) {
-    __shared__ double As[2][BK * BM];  // [k][m]
-    __shared__ double Bs[2][BN * BK];  // [n][k ^ swizzle(n)]
+// KB = 16: 64 KB of LDS, two workgroups per CU; KB = 32: 128 KB, one
+// workgroup per CU with twice the prefetch distance and half the barriers.
+template <int KB, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
+    __shared__ double As[2][KB * BM];  // [k][m]
+    __shared__ double Bs[2][BN * KB];  // [n][k ^ swizzle(n)]
 
     // XCD-aware remap, then grouped row-major order inside the XCD's band.
     const int nwg = gridDim.x;
@@ -148,21 +154,21 @@ __global__ __launch_bounds__(256, 2) void k_dgemm_mfma(GemmArgs g) {
     const double *Ablk = g.Ap + (int64_t)tm * BM;
     const double *Bblk = g.Bp + (int64_t)tn * BN * g.ldb;
 
-    double2_t ra[4], rb[4];
+    double2_t ra[KB / 4], rb[KB / 4];
     double4_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-    gemm_gload(ra, rb, Ablk, Bblk, g.lda, g.ldb, 0, tid);
-    gemm_lstore(ra, rb, As[0], Bs[0], tid);
+    gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, 0, tid);
+    gemm_lstore<KB>(ra, rb, As[0], Bs[0], tid);
     __syncthreads();
     for (int kt = 0; kt < g.ktiles; ++kt) {
         const int cur = kt & 1;
-        if (kt + 1 < g.ktiles) gemm_gload(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
+        if (kt + 1 < g.ktiles) gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
 #pragma unroll
-        for (int ks = 0; ks < BK / 4; ++ks) {
+        for (int ks = 0; ks < KB / 4; ++ks) {
             const int k = ks * 4 + lk;
             double a[4], b[4];
 #pragma unroll
@@ -170,7 +176,7 @@ __global__ __launch_bounds__(256, 2) void k_dgemm_mfma(GemmArgs g) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 const int col = wn * 64 + t * 16 + l16;
-                b[t] = Bs[cur][col * BK + (k ^ (col & 15))];
+                b[t] = Bs[cur][col * KB + (k ^ (col & 15))];
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
@@ -178,7 +184,7 @@ __global__ __launch_bounds__(256, 2) void k_dgemm_mfma(GemmArgs g) {
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < g.ktiles) gemm_lstore(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
+        if (kt + 1 < g.ktiles) gemm_lstore<KB>(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
         __syncthreads();
     }
 
@@ -224,7 +230,8 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     const int64_t M = A->rows(), K = A->cols(), N = B->cols();
     if (M == 0 || N == 0 || C->nnzb == 0) return BSMM_OK;
     if (alpha == 0.0 || K == 0) return scale_blocks(C, nullptr, beta, s);
-    const int64_t Mp = ceil_div(M, BM) * BM, Np = ceil_div(N, BN) * BN, Kp = ceil_div(K, BK) * BK;
+    const int KB = options().dense_kb == 32 ? 32 : 16;
+    const int64_t Mp = ceil_div(M, BM) * BM, Np = ceil_div(N, BN) * BN, Kp = ceil_div(K, KB) * KB;
     const int64_t tiles = (Mp / BM) * (Np / BN);
     if (tiles > INT32_MAX || Mp * Kp > (int64_t(1) << 47) || Kp * Np > (int64_t(1) << 47)) {
         set_error(BSMM_ERANGE, "dense panels too large");
@@ -270,7 +277,7 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     g.ldb = Kp;
     g.tiles_m = (int)(Mp / BM);
     g.tiles_n = (int)(Np / BN);
-    g.ktiles = (int)(Kp / BK);
+    g.ktiles = (int)(Kp / KB);
     g.M = M;
     g.N = N;
     g.alpha = alpha;
@@ -284,7 +291,8 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     g.cmap = C->d_col_map();
     {
         KernelTimer kt(0, s);
-        hipLaunchKernelGGL(k_dgemm_mfma, dim3((unsigned)tiles), dim3(256), 0, s, g);
+        if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<32, 1>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+        else hipLaunchKernelGGL((k_dgemm_mfma<16, 2>), dim3((unsigned)tiles), dim3(256), 0, s, g);
     }
     return launch_check("dgemm_mfma");
 }

@@ -51,6 +51,7 @@ struct Options {
     int stack_kernel = 0;  // 0 plain, 1 tuned
     int64_t stack_chunk = 0;
     int time_kernels = 0;
+    int dense_kb = 16;             // k step of the dense FP64 GEMM (16 or 32)
     int plan_cache = 0;            // reuse symbolic result + stacks + graph when patterns repeat
     std::string tune_db;
     std::string mlp_weights;

@@ -331,3 +331,21 @@ def test_full_size_dense_square_sampled():
         e1 = e0 + int(sizes[s0:s1].sum())
         assert np.array_equal(X.col_ind[s0:s1], R.col_ind)
         assert orc.rel_err(X.data[e0:e1], R.data) <= TOL
+
+
+@pytest.mark.parametrize("n,bs", [(256, 32), (299, 23)])
+def test_dense_k_step_32(n, bs):
+    """The 32-deep k-step variant of the dense GEMM (zero-padded K)."""
+    b = lib()
+    rng = rng_of(n + 1)
+    sizes = np.full(n // bs, bs, np.int32)
+    A = make_matrix(rng, sizes, sizes, 1.0)
+    B = make_matrix(rng, sizes, sizes, 1.0)
+    Cin = make_matrix(rng, sizes, sizes, 1.0)
+    b.bsmm_set_option("dense_kb", "32")
+    try:
+        X, st = gpu_multiply(0.75, A, B, -0.5, Cin)
+    finally:
+        b.bsmm_set_option("dense_kb", "16")
+    assert st["path"] == 2
+    check_against_oracle(X, orc.multiply(0.75, A, B, -0.5, Cin), TOL)
