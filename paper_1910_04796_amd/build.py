@@ -20,13 +20,18 @@ FLAGS = [
     "-I" + os.path.join(HERE, "..", "include"),
 ]
 
+# The emulation's recombination is defined with every product and sum rounded
+# on its own; inlined header helpers would otherwise carry the contraction
+# flag into that file and let the backend fuse them.
+FILE_FLAGS = {"emul.hip": ["-ffp-contract=off"]}
+
 
 def _compile(src):
     obj = os.path.join(BUILD, os.path.basename(src) + ".o")
     deps = [src] + glob.glob(os.path.join(CSRC, "*.h")) + [os.path.join(HERE, "..", "include", "bsmm.h")]
     if os.path.exists(obj) and os.path.getmtime(obj) >= max(os.path.getmtime(d) for d in deps):
         return obj
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", obj + ".tmp"]
+    cmd = [HIPCC] + FLAGS + FILE_FLAGS.get(os.path.basename(src), []) + ["-c", src, "-o", obj + ".tmp"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")

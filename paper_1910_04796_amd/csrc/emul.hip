@@ -106,8 +106,10 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
     // The recombination rounds every product and sum separately (no fused
     // multiply-add), matching the method's definition step by step.
 #pragma clang fp contract(off)
-    __shared__ __attribute__((aligned(16))) signed char lA[S][ET * ELD];
-    __shared__ __attribute__((aligned(16))) signed char lB[S][ET * ELD];
+    // Double-buffered LDS: slices of step k + 1 are fetched into registers
+    // while the MFMAs of step k run, then stored to the other buffer.
+    __shared__ __attribute__((aligned(16))) signed char lA[2][S][ET * ELD];
+    __shared__ __attribute__((aligned(16))) signed char lB[2][S][ET * ELD];
     const int tiles_n = (int)(g.Np / ET);
     const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -122,28 +124,42 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
 #pragma unroll
             for (int j = 0; j < 2; ++j) acc[d][i][j] = (v4i){0, 0, 0, 0};
 
-    // global -> LDS: 64 rows x 64 bytes per slice = 256 x 16 bytes
+    // global -> registers: 64 rows x 64 bytes per slice = 256 x 16 bytes
     const int lr = tid >> 2, lc = (tid & 3) * 16;
-    for (int64_t k = g.k0; k < g.k1; k += EK) {
+    const signed char *pa = g.As + (row0 + lr) * g.Kp + lc;
+    const signed char *pb = g.Bs + (col0 + lr) * g.Kp + lc;
+    const int64_t sa = g.Mp * g.Kp, sb = g.Np * g.Kp;
+    v4i ra[S], rb[S];
 #pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const v4i a = *reinterpret_cast<const v4i *>(g.As + (int64_t)s * g.Mp * g.Kp +
-                                                         (row0 + lr) * g.Kp + k + lc);
-            const v4i b = *reinterpret_cast<const v4i *>(g.Bs + (int64_t)s * g.Np * g.Kp +
-                                                         (col0 + lr) * g.Kp + k + lc);
-            *reinterpret_cast<v4i *>(&lA[s][lr * ELD + lc]) = a;
-            *reinterpret_cast<v4i *>(&lB[s][lr * ELD + lc]) = b;
+    for (int s = 0; s < S; ++s) {
+        ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + g.k0);
+        rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + g.k0);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        *reinterpret_cast<v4i *>(&lA[0][s][lr * ELD + lc]) = ra[s];
+        *reinterpret_cast<v4i *>(&lB[0][s][lr * ELD + lc]) = rb[s];
+    }
+    __syncthreads();
+    int cur = 0;
+    for (int64_t k = g.k0; k < g.k1; k += EK) {
+        const bool more = k + EK < g.k1;
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + k + EK);
+                rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + k + EK);
+            }
         }
-        __syncthreads();
         v4i af[S][2], bf[S][2];
 #pragma unroll
         for (int s = 0; s < S; ++s)
 #pragma unroll
             for (int i = 0; i < 2; ++i) {
                 af[s][i] = *reinterpret_cast<const v4i *>(
-                    &lA[s][(wm * 32 + i * 16 + (lane & 15)) * ELD + frag_k(lane)]);
+                    &lA[cur][s][(wm * 32 + i * 16 + (lane & 15)) * ELD + frag_k(lane)]);
                 bf[s][i] = *reinterpret_cast<const v4i *>(
-                    &lB[s][(wn * 32 + i * 16 + (lane & 15)) * ELD + frag_k(lane)]);
+                    &lB[cur][s][(wn * 32 + i * 16 + (lane & 15)) * ELD + frag_k(lane)]);
             }
 #pragma unroll
         for (int s = 0; s < S; ++s)
@@ -155,7 +171,15 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
                     for (int j = 0; j < 2; ++j)
                         acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
                             af[s][i], bf[t][j], acc[s + t][i][j], 0, 0, 0);
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                *reinterpret_cast<v4i *>(&lA[cur ^ 1][s][lr * ELD + lc]) = ra[s];
+                *reinterpret_cast<v4i *>(&lB[cur ^ 1][s][lr * ELD + lc]) = rb[s];
+            }
+        }
         __syncthreads();
+        cur ^= 1;
     }
 
     // Recombination (FP64) and store.
@@ -169,9 +193,9 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
                 const int64_t col = col0 + wn * 32 + j * 16 + (lane & 15);
                 double h = (double)acc[S - 1][i][j][e];
 #pragma unroll
-                for (int d = S - 2; d >= 0; --d) h = __dadd_rn(h * (1.0 / 128.0), (double)acc[d][i][j][e]);
+                for (int d = S - 2; d >= 0; --d) h = h * (1.0 / 128.0) + (double)acc[d][i][j][e];
                 double v = ldexp(h, g.ea[row] + g.eb[col] - 14);
-                if (!(g.mode & 1)) v = __dadd_rn(g.V[col * g.Mp + row], v);
+                if (!(g.mode & 1)) v = g.V[col * g.Mp + row] + v;
                 if (!(g.mode & 4)) {
                     g.V[col * g.Mp + row] = v;
                     continue;
@@ -182,8 +206,8 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
                 const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
                 if (blk < 0) continue;
                 double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
-                const double prod = __dmul_rn(g.alpha, v);
-                *dst = (g.beta == 0.0) ? prod : __dadd_rn(__dmul_rn(g.beta, *dst), prod);
+                const double prod = g.alpha * v;
+                *dst = (g.beta == 0.0) ? prod : g.beta * *dst + prod;
             }
 }
 
