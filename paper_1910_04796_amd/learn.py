@@ -40,6 +40,43 @@ def features(rows):
     return out
 
 
+def holdout_split(shapes, count, seed):
+    """The held-out shapes: ``count`` (at most a fifth) drawn without
+    replacement from the sorted shape list with the given seed."""
+    rng = np.random.default_rng(seed)
+    pick = rng.choice(len(shapes), size=min(count, len(shapes) // 5), replace=False)
+    return set(map(tuple, np.array(shapes)[pick].tolist()))
+
+
+def read_plain(db_path):
+    """Plain-rule timings (last column) of a tuning database, by shape."""
+    plain = {}
+    for line in open(db_path):
+        if line.strip() and not line.startswith("#"):
+            f = line.split()
+            if len(f) >= 9:
+                plain[(int(f[0]), int(f[1]), int(f[2]))] = float(f[8])
+    return plain
+
+
+def evaluate(rows, held, pred, plain):
+    """Per held-out shape: exhaustive best / time of the model's first pick,
+    and plain-rule time / time of the pick (shapes with a plain timing)."""
+    key = [(int(r[0]), int(r[1]), int(r[2])) for r in rows]
+    by_shape = {}
+    for i, k in enumerate(key):
+        by_shape.setdefault(k, []).append(i)
+    ratios, speedups = [], []
+    for s in sorted(held):
+        idx = np.array(by_shape[s])
+        times = rows[idx, 7]
+        pick = times[int(np.argmin(pred[idx]))]
+        ratios.append(times.min() / pick)
+        if s in plain:
+            speedups.append(plain[s] / pick)
+    return np.array(ratios), np.array(speedups)
+
+
 def init_params(F, seed):
     """He-uniform weights, zero biases (same layout as the library)."""
     H = 64
@@ -77,11 +114,8 @@ def main():
 
     rows = read_table(args.all)
     shapes = sorted({(int(r[0]), int(r[1]), int(r[2])) for r in rows})
-    rng = np.random.default_rng(args.seed)
-    held = set(map(tuple, np.array(shapes)[rng.choice(len(shapes), size=min(args.holdout, len(shapes) // 5),
-                                                     replace=False)].tolist()))
-    key = [(int(r[0]), int(r[1]), int(r[2])) for r in rows]
-    is_held = np.array([k in held for k in key])
+    held = holdout_split(shapes, args.holdout, args.seed)
+    is_held = np.array([(int(r[0]), int(r[1]), int(r[2])) in held for r in rows])
     X = features(rows)
     y = np.log(rows[:, 7]).astype(np.float32)
     tr = ~is_held
@@ -98,38 +132,16 @@ def main():
     train_s = time.time() - t0
     log(f"trained in {train_s:.1f} s, train MSE {loss:.4f} (standardised log time)")
     pred = bsmm.bsmm_mlp_forward(P, Xn)
-    ratios, vs_default = [], []
-    t1 = time.time()
-    for s in sorted(held):
-        idx = np.nonzero(np.array([k == s for k in key]))[0]
-        times = rows[idx, 7]
-        best = times.min()
-        pick = times[int(np.argmin(pred[idx]))]
-        ratios.append(best / pick)
-    infer_us = (time.time() - t1) * 1e6 / max(len(held), 1)
-    ratios = np.array(ratios)
-    plain = {}
-    if args.db and os.path.exists(args.db):
-        for line in open(args.db):
-            if line.strip() and not line.startswith("#"):
-                f = line.split()
-                if len(f) >= 9:
-                    plain[(int(f[0]), int(f[1]), int(f[2]))] = float(f[8])
-    speedups = []
-    for s, r in zip(sorted(held), ratios):
-        if s in plain:
-            idx = np.nonzero(np.array([k == s for k in key]))[0]
-            pick = rows[idx, 7][int(np.argmin(pred[idx]))]
-            speedups.append(plain[s] / pick)
+    plain = read_plain(args.db) if args.db and os.path.exists(args.db) else {}
+    ratios, speedups = evaluate(rows, held, pred, plain)
     write_weights(args.out, mean, sd, P)
     rep = {"shapes": len(shapes), "held_out": len(held), "train_rows": int(tr.sum()),
            "train_seconds": round(train_s, 2), "train_mse": round(float(loss), 5),
            "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seed": args.seed,
            "heldout_best_over_pick": {"mean": round(float(ratios.mean()), 4),
                                       "min": round(float(ratios.min()), 4),
-                                      "share_ge_0.9": round(float((ratios >= 0.9).mean()), 4)},
-           "inference_us_per_shape_host": round(infer_us, 1)}
-    if speedups:
+                                      "share_ge_0.9": round(float((ratios >= 0.9).mean()), 4)}}
+    if len(speedups):
         sp = np.array(speedups)
         rep["heldout_plain_over_pick"] = {"mean": round(float(sp.mean()), 4),
                                           "min": round(float(sp.min()), 4),

@@ -36,10 +36,16 @@ def random_shapes(count, lo, hi, seed):
 
 
 def tune(shapes, db_path, all_path, reps=5, n_runs=3750, run_len=8, log=print):
+    """Times every candidate of every shape.  A plain-text timing table is
+    appended shape by shape, so an interrupted run keeps what it measured."""
     from . import bsmm
     rows = []
     best = {}
     t0 = time.time()
+    stream = None
+    if all_path and not all_path.endswith(".gz"):
+        stream = open(all_path, "w")
+        stream.write("m,n,k,tm,tn,kc,waves,us\n")
     for i, (m, n, k) in enumerate(shapes):
         cands = bsmm.bsmm_tune_candidates(m, n, k)
         plain = np.array([bsmm.bsmm_select_params(m, n, k)], np.int32)
@@ -47,12 +53,18 @@ def tune(shapes, db_path, all_path, reps=5, n_runs=3750, run_len=8, log=print):
                                       run_len=run_len, reps=reps)
         us, plain_us = us_all[:-1], float(us_all[-1])
         ok = us > 0
-        for c, u in zip(cands[ok], us[ok]):
-            rows.append((m, n, k, *[int(x) for x in c], float(u)))
+        new_rows = [(m, n, k, *[int(x) for x in c], float(u)) for c, u in zip(cands[ok], us[ok])]
+        rows += new_rows
+        if stream:
+            stream.write("".join(",".join(str(x) for x in r[:7]) + f",{r[7]:.3f}\n" for r in new_rows))
+            stream.flush()
         j = int(np.argmin(np.where(ok, us, np.inf)))
         best[(m, n, k)] = (tuple(int(x) for x in cands[j]), float(us[j]), plain_us)
         log(f"[tune] {i + 1}/{len(shapes)} ({m},{n},{k}): {len(cands)} candidates, best "
-            f"{tuple(int(x) for x in cands[j])} {us[j]:.1f} us ({time.time() - t0:.0f} s)")
+            f"{tuple(int(x) for x in cands[j])} {us[j]:.1f} us, plain {plain_us:.1f} us "
+            f"({time.time() - t0:.0f} s)")
+    if stream:
+        stream.close()
     if db_path:
         os.makedirs(os.path.dirname(os.path.abspath(db_path)), exist_ok=True)
         with open(db_path, "w") as f:
@@ -60,9 +72,8 @@ def tune(shapes, db_path, all_path, reps=5, n_runs=3750, run_len=8, log=print):
                     % (n_runs, run_len))
             for (m, n, k), (p, u, pu) in sorted(best.items()):
                 f.write(f"{m} {n} {k} {p[0]} {p[1]} {p[2]} {p[3]} {u:.2f} {pu:.2f}\n")
-    if all_path:
-        op = gzip.open if all_path.endswith(".gz") else open
-        with op(all_path, "wt") as f:
+    if all_path and stream is None:
+        with gzip.open(all_path, "wt") as f:
             f.write("m,n,k,tm,tn,kc,waves,us\n")
             for r in rows:
                 f.write(",".join(str(x) for x in r[:7]) + f",{r[7]:.3f}\n")

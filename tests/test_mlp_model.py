@@ -1,0 +1,96 @@
+"""The committed learned model and its held-out evaluation (paper Sec. II:
+a model trained on part of the tuning data predicts the kernel parameters of
+every other shape).
+
+The tuner's timing table over 600 random shapes, the weights trained on the
+GPU from 500 of them, and the report of the evaluation on the other 100 are
+committed together.  These CPU tests recompute that evaluation from the table
+and the weights with the numpy forward pass of the model, so the reported
+figures follow from committed data and not from the GPU run alone.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+DB_DIR = os.path.join(os.path.dirname(__file__), "..", "paper_1910_04796_amd", "tune_db")
+TABLE = os.path.join(DB_DIR, "gfx950_random_all.csv.gz")
+WEIGHTS = os.path.join(DB_DIR, "gfx950_mlp.txt")
+REPORT = os.path.join(DB_DIR, "mlp_report.json")
+RANDOM_DB = os.path.join(DB_DIR, "gfx950_random.txt")
+
+
+def read_weights(path):
+    lines = open(path).read().split("\n")
+    assert lines[0].startswith("bsmm-mlp features")
+    F = int(lines[0].split()[2])
+    mean = np.array(lines[1].split()[1:], np.float32)
+    sd = np.array(lines[2].split()[1:], np.float32)
+    n = int(lines[3].split()[1])
+    P = np.array(lines[4].split(), np.float32)
+    assert len(mean) == F and len(sd) == F and len(P) == n == mlp_ref.param_count(F)
+    return mean, sd, P
+
+
+@pytest.fixture(scope="module")
+def heldout():
+    if not all(os.path.exists(p) for p in (TABLE, WEIGHTS, REPORT, RANDOM_DB)):
+        pytest.skip("learned model files not committed")
+    from paper_1910_04796_amd import bsmm, learn
+    rows = learn.read_table(TABLE)
+    shapes = sorted({(int(r[0]), int(r[1]), int(r[2])) for r in rows})
+    rep = json.load(open(REPORT))
+    held = learn.holdout_split(shapes, rep["held_out"], rep["seed"])
+    sel = np.array([(int(r[0]), int(r[1]), int(r[2])) in held for r in rows])
+    hrows = rows[sel]
+    X = np.stack([bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[3:7].astype(np.int32))
+                  for r in hrows])
+    mean, sd, P = read_weights(WEIGHTS)
+    Xn = ((X - mean) / sd).astype(np.float32)
+    pred, _ = mlp_ref.forward(P, Xn)
+    return learn, rows, hrows, held, pred, rep
+
+
+def test_table_covers_the_shapes(heldout):
+    learn, rows, hrows, held, pred, rep = heldout
+    shapes = {(int(r[0]), int(r[1]), int(r[2])) for r in rows}
+    assert len(shapes) == rep["shapes"] == 600
+    assert len(held) == rep["held_out"] == 100
+    assert len(rows) - len(hrows) == rep["train_rows"]
+    assert all(4 <= v <= 64 for s in shapes for v in s)
+    assert (rows[:, 7] > 0).all()
+
+
+def test_heldout_evaluation_reproduces_report(heldout):
+    """Best / pick over the held-out shapes, recomputed on the CPU, agrees
+    with the GPU run's report (FP32 forward passes may break near-ties
+    differently, hence the small tolerance)."""
+    learn, rows, hrows, held, pred, rep = heldout
+    ratios, speedups = learn.evaluate(hrows, held, pred, learn.read_plain(RANDOM_DB))
+    assert len(ratios) == 100 and len(speedups) == 100
+    assert (ratios <= 1.0).all() and (ratios > 0).all()
+    r = rep["heldout_best_over_pick"]
+    assert abs(ratios.mean() - r["mean"]) < 0.01
+    assert abs((ratios >= 0.9).mean() - r["share_ge_0.9"]) <= 0.03
+    g = rep["heldout_plain_over_pick"]["geomean"]
+    assert abs(np.exp(np.log(speedups).mean()) - g) < 0.02 * g
+    # The model is useful: on shapes it never saw it picks sets within 10 %
+    # of the exhaustive best on most shapes and beats the plain rule overall.
+    assert ratios.mean() > 0.9
+    assert np.exp(np.log(speedups).mean()) > 1.2
+
+
+def test_model_beats_random_choice(heldout):
+    """Against the expected best / pick of a uniformly random candidate, the
+    model's pick is better on average (a model that learned nothing is not)."""
+    learn, rows, hrows, held, pred, rep = heldout
+    ratios, _ = learn.evaluate(hrows, held, pred, {})
+    rand = []
+    key = [(int(r[0]), int(r[1]), int(r[2])) for r in hrows]
+    for s in sorted(held):
+        t = hrows[[i for i, k in enumerate(key) if k == s], 7]
+        rand.append(np.mean(t.min() / t))
+    assert ratios.mean() > np.mean(rand) + 0.1
