@@ -18,10 +18,19 @@
 //      beta * C).
 //
 // Layout: A is merged transposed (rows of A contiguous in k) and B column-
-// major (columns contiguous in k); slices keep those layouts as int8.
-// GEMM tile: 64 x 64 outputs per 256-thread workgroup, k step 64; each wave
-// owns 32 x 32 outputs = 2 x 2 tiles of v_mfma_i32_16x16x64_i8, with S INT32
-// accumulators (one per weight d) per tile.
+// major (columns contiguous in k); the int8 slices are stored in k panels of
+// 32 bytes ([slice][k / 32][row][k % 32]) so that every k step of a tile
+// reads whole contiguous blocks.
+// GEMM kernels (option "emul_kernel"), all with S INT32 accumulators (one per
+// weight d) per output tile:
+//   t64     64 x 64 outputs per 256-thread workgroup, each wave 2 x 2 tiles of
+//           v_mfma_i32_16x16x64_i8, k step 64, two LDS stages;
+//   t128    128 x 64 outputs, each wave 4 x 2 tiles of the same MFMA, k step
+//           64, one LDS stage refilled from registers;
+//   t128k32 128 x 64 outputs, each wave 2 x 1 tiles of
+//           v_mfma_i32_32x32x32_i8, k step 32, two LDS stages (default).  Workgroup ids are remapped so that the
+// tiles resident on one XCD form a compact group of tile rows and columns
+// (their slices stay in that XCD's L2).
 #include <algorithm>
 
 #include "dev_util.h"
@@ -32,6 +41,7 @@ namespace bsmm {
 namespace {
 
 typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
 
 constexpr int ET = 64;   // output tile edge
 constexpr int EK = 64;   // k step
@@ -42,6 +52,36 @@ constexpr int ELD = 80;  // LDS row stride in bytes (64 + 16 padding)
 // Result layout: D(row, col) in lane col + 16 * (row / 4), element row % 4.
 __device__ __forceinline__ int frag_k(int lane) { return 16 * (lane >> 4); }
 __device__ __forceinline__ int out_row(int lane, int e) { return 4 * (lane >> 4) + e; }
+
+constexpr int WTM = 128;  // wide tile: rows per workgroup
+constexpr int WTN = 64;   // wide tile: columns per workgroup
+constexpr int XK = 32;    // k step of the 32 x 32 x 32 variant
+constexpr int XLD = 48;   // its LDS row stride in bytes (32 + 16 padding)
+
+// v_mfma_i32_32x32x32_i8: lane l holds row (l % 32) of A (column of B) and
+// 16 bytes of k at 16 * (l / 32); result element e of lane l is row
+// 8 (e / 4) + 4 (l / 32) + e % 4, column l % 32.
+__device__ __forceinline__ int out_row32(int lane, int e) {
+    return 8 * (e >> 2) + 4 * (lane >> 5) + (e & 3);
+}
+
+// Tile of this workgroup.  The hardware deals workgroups to the 8 XCDs round
+// robin; the remap gives each XCD a contiguous range of logical ids, walked
+// in groups of gm tile rows with the row index fastest, so concurrently
+// resident workgroups of one XCD share A and B slices.  A bijection on
+// [0, tiles_m * tiles_n) when the grid has exactly that many workgroups.
+__device__ __forceinline__ void emul_tile_of(int tiles_m, int tiles_n, int gm, int &tm, int &tn) {
+    const int nwg = gridDim.x;
+    int logical = blockIdx.x;
+    if ((nwg & 7) == 0) logical = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+    const int per_group = gm * tiles_n;
+    const int group = logical / per_group;
+    const int first_m = group * gm;
+    const int gsz = min(tiles_m - first_m, gm);
+    const int in_group = logical - group * per_group;
+    tm = first_m + in_group % gsz;
+    tn = in_group / gsz;
+}
 
 // Row exponents of a k-contiguous matrix (rows x ld): one wave per row.
 __global__ __launch_bounds__(256) void k_row_exp(const double *X, int64_t rows, int64_t K,
@@ -59,7 +99,9 @@ __global__ __launch_bounds__(256) void k_row_exp(const double *X, int64_t rows, 
 }
 
 // Digit slices of a k-contiguous matrix: each thread handles 8 consecutive k
-// of one row and writes S 8-byte groups.
+// of one row and writes S 8-byte groups.  Slice layout: k panels of 32 bytes,
+// [slice][k / 32][row][k % 32], so a tile's rows for one 32-deep k step are
+// one contiguous block.
 __global__ __launch_bounds__(256) void k_slice(const double *X, int64_t rows, int64_t ld, int S,
                                                const int *e, signed char *out) {
     const int64_t per_row = ld / 8;
@@ -79,7 +121,9 @@ __global__ __launch_bounds__(256) void k_slice(const double *X, int64_t rows, in
             v[j] = t - d;
             w |= (unsigned long long)(unsigned char)(signed char)(int)d << (8 * j);
         }
-        *reinterpret_cast<unsigned long long *>(out + (int64_t)s * rows * ld + r * ld + 8 * k8) = w;
+        const int64_t k = 8 * k8;
+        *reinterpret_cast<unsigned long long *>(out + (int64_t)s * rows * ld + (k >> 5) * rows * 32 +
+                                                r * 32 + (k & 31)) = w;
     }
 }
 
@@ -101,6 +145,32 @@ struct EmulArgs {
     const int2 *rmap, *cmap;
 };
 
+// FP64 recombination of one output element from its S weight sums (Horner
+// in 2^-7, exact power-of-two scaling), chunk accumulation, and the store
+// C = beta C + alpha value into C's block (every operation rounded on its
+// own: this file is compiled without contraction).
+template <int S>
+__device__ __forceinline__ void emul_out(const EmulArgs &g, const int (&vals)[S], int64_t row,
+                                         int64_t col) {
+    double h = (double)vals[S - 1];
+#pragma unroll
+    for (int d = S - 2; d >= 0; --d) h = h * (1.0 / 128.0) + (double)vals[d];
+    double v = ldexp(h, g.ea[row] + g.eb[col] - 14);
+    if (!(g.mode & 1)) v = g.V[col * g.Mp + row] + v;
+    if (!(g.mode & 4)) {
+        g.V[col * g.Mp + row] = v;
+        return;
+    }
+    if (row >= g.M || col >= g.N) return;
+    const int2 rm = g.rmap[row], cm = g.cmap[col];
+    const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
+    const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
+    if (blk < 0) return;
+    double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
+    const double prod = g.alpha * v;
+    *dst = (g.beta == 0.0) ? prod : g.beta * *dst + prod;
+}
+
 template <int S>
 __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
     // The recombination rounds every product and sum separately (no fused
@@ -110,8 +180,8 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
     // while the MFMAs of step k run, then stored to the other buffer.
     __shared__ __attribute__((aligned(16))) signed char lA[2][S][ET * ELD];
     __shared__ __attribute__((aligned(16))) signed char lB[2][S][ET * ELD];
-    const int tiles_n = (int)(g.Np / ET);
-    const int tm = blockIdx.x / tiles_n, tn = blockIdx.x % tiles_n;
+    int tm, tn;
+    emul_tile_of((int)(g.Mp / ET), (int)(g.Np / ET), 8, tm, tn);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
     const int64_t row0 = (int64_t)tm * ET, col0 = (int64_t)tn * ET;
@@ -126,14 +196,14 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
 
     // global -> registers: 64 rows x 64 bytes per slice = 256 x 16 bytes
     const int lr = tid >> 2, lc = (tid & 3) * 16;
-    const signed char *pa = g.As + (row0 + lr) * g.Kp + lc;
-    const signed char *pb = g.Bs + (col0 + lr) * g.Kp + lc;
-    const int64_t sa = g.Mp * g.Kp, sb = g.Np * g.Kp;
+    const signed char *pa = g.As + ((lc >> 5) * g.Mp + row0 + lr) * 32 + (lc & 31);
+    const signed char *pb = g.Bs + ((lc >> 5) * g.Np + col0 + lr) * 32 + (lc & 31);
+    const int64_t sa = g.Mp * g.Kp, sb = g.Np * g.Kp, pA = g.Mp * 32, pB = g.Np * 32;
     v4i ra[S], rb[S];
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + g.k0);
-        rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + g.k0);
+        ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + (g.k0 >> 5) * pA);
+        rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + (g.k0 >> 5) * pB);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
@@ -147,8 +217,8 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
         if (more) {
 #pragma unroll
             for (int s = 0; s < S; ++s) {
-                ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + k + EK);
-                rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + k + EK);
+                ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + ((k + EK) >> 5) * pA);
+                rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + ((k + EK) >> 5) * pB);
             }
         }
         v4i af[S][2], bf[S][2];
@@ -189,26 +259,230 @@ __global__ __launch_bounds__(256) void k_emul_gemm(EmulArgs g) {
         for (int j = 0; j < 2; ++j)
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t row = row0 + wm * 32 + i * 16 + out_row(lane, e);
-                const int64_t col = col0 + wn * 32 + j * 16 + (lane & 15);
-                double h = (double)acc[S - 1][i][j][e];
+                int vals[S];
 #pragma unroll
-                for (int d = S - 2; d >= 0; --d) h = h * (1.0 / 128.0) + (double)acc[d][i][j][e];
-                double v = ldexp(h, g.ea[row] + g.eb[col] - 14);
-                if (!(g.mode & 1)) v = g.V[col * g.Mp + row] + v;
-                if (!(g.mode & 4)) {
-                    g.V[col * g.Mp + row] = v;
-                    continue;
-                }
-                if (row >= g.M || col >= g.N) continue;
-                const int2 rm = g.rmap[row], cm = g.cmap[col];
-                const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
-                const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
-                if (blk < 0) continue;
-                double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
-                const double prod = g.alpha * v;
-                *dst = (g.beta == 0.0) ? prod : g.beta * *dst + prod;
+                for (int d = 0; d < S; ++d) vals[d] = acc[d][i][j][e];
+                emul_out<S>(g, vals, row0 + wm * 32 + i * 16 + out_row(lane, e),
+                            col0 + wn * 32 + j * 16 + (lane & 15));
             }
+}
+
+// Wide variant: 128 x 64 outputs per workgroup, waves in 2 x 2, each wave
+// 64 x 32 outputs (4 x 2 MFMA tiles).  One LDS stage (S x 192 rows of 64
+// bytes, padded stride): the slices of step k + 1 are fetched into registers
+// while the MFMAs of step k run and stored after a barrier.
+template <int S>
+__global__ __launch_bounds__(256, 1) void k_emul_gemm_w(EmulArgs g) {
+#pragma clang fp contract(off)
+    __shared__ __attribute__((aligned(16))) signed char lA[S][WTM * ELD];
+    __shared__ __attribute__((aligned(16))) signed char lB[S][WTN * ELD];
+    int tm, tn;
+    emul_tile_of((int)(g.Mp / WTM), (int)(g.Np / WTN), 4, tm, tn);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int64_t row0 = (int64_t)tm * WTM, col0 = (int64_t)tn * WTN;
+
+    v4i acc[S][4][2];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 2; ++j) acc[d][i][j] = (v4i){0, 0, 0, 0};
+
+    // global -> registers: per slice, A rows lr and lr + 64, B row lr
+    // (16 bytes each at byte lc of the k step).
+    const int lr = tid >> 2, lc = (tid & 3) * 16;
+    const signed char *pa = g.As + ((lc >> 5) * g.Mp + row0 + lr) * 32 + (lc & 31);
+    const signed char *pb = g.Bs + ((lc >> 5) * g.Np + col0 + lr) * 32 + (lc & 31);
+    const int64_t sa = g.Mp * g.Kp, sb = g.Np * g.Kp, pA = g.Mp * 32, pB = g.Np * 32;
+    const int64_t half = 64 * 32;
+    v4i ra0[S], ra1[S], rb[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        ra0[s] = *reinterpret_cast<const v4i *>(pa + s * sa + (g.k0 >> 5) * pA);
+        ra1[s] = *reinterpret_cast<const v4i *>(pa + s * sa + half + (g.k0 >> 5) * pA);
+        rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + (g.k0 >> 5) * pB);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        *reinterpret_cast<v4i *>(&lA[s][lr * ELD + lc]) = ra0[s];
+        *reinterpret_cast<v4i *>(&lA[s][(lr + 64) * ELD + lc]) = ra1[s];
+        *reinterpret_cast<v4i *>(&lB[s][lr * ELD + lc]) = rb[s];
+    }
+    __syncthreads();
+    for (int64_t k = g.k0; k < g.k1; k += EK) {
+        const bool more = k + EK < g.k1;
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                ra0[s] = *reinterpret_cast<const v4i *>(pa + s * sa + ((k + EK) >> 5) * pA);
+                ra1[s] = *reinterpret_cast<const v4i *>(pa + s * sa + half + ((k + EK) >> 5) * pA);
+                rb[s] = *reinterpret_cast<const v4i *>(pb + s * sb + ((k + EK) >> 5) * pB);
+            }
+        }
+        v4i bf[S][2];
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+#pragma unroll
+            for (int j = 0; j < 2; ++j)
+                bf[t][j] = *reinterpret_cast<const v4i *>(
+                    &lB[t][(wn * 32 + j * 16 + (lane & 15)) * ELD + frag_k(lane)]);
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            v4i af[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                af[i] = *reinterpret_cast<const v4i *>(
+                    &lA[s][(wm * 64 + i * 16 + (lane & 15)) * ELD + frag_k(lane)]);
+#pragma unroll
+            for (int t = 0; t < S - s; ++t)  // digit pair (s+1, t+1): weight d = s + t + 2
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+#pragma unroll
+                    for (int j = 0; j < 2; ++j)
+                        acc[s + t][i][j] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            af[i], bf[t][j], acc[s + t][i][j], 0, 0, 0);
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                *reinterpret_cast<v4i *>(&lA[s][lr * ELD + lc]) = ra0[s];
+                *reinterpret_cast<v4i *>(&lA[s][(lr + 64) * ELD + lc]) = ra1[s];
+                *reinterpret_cast<v4i *>(&lB[s][lr * ELD + lc]) = rb[s];
+            }
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                int vals[S];
+#pragma unroll
+                for (int d = 0; d < S; ++d) vals[d] = acc[d][i][j][e];
+                emul_out<S>(g, vals, row0 + wm * 64 + i * 16 + out_row(lane, e),
+                            col0 + wn * 32 + j * 16 + (lane & 15));
+            }
+}
+
+// 32 x 32 x 32 variant: 128 x 64 outputs per workgroup, waves in 2 x 2, each
+// wave 64 x 32 outputs (2 x 1 tiles of v_mfma_i32_32x32x32_i8).  The k step
+// of 32 halves an LDS stage (S x 192 rows of 32 bytes, padded stride), so two
+// stages fit.  Per step: the slices of the next step are fetched into
+// registers, every fragment of this step is read from LDS up front, and the
+// fetched slices are stored into the other stage part way through the MFMAs
+// (that stage was last read before the previous barrier); one barrier per
+// step.  Scheduling fences keep that order.
+template <int S>
+__global__ __launch_bounds__(256, 1) void k_emul_gemm_x(EmulArgs g) {
+#pragma clang fp contract(off)
+    constexpr int NB = (S + 1) / 2;  // B chunks per thread and step
+    __shared__ __attribute__((aligned(16))) signed char lA[2][S][WTM * XLD];
+    __shared__ __attribute__((aligned(16))) signed char lB[2][S][WTN * XLD];
+    int tm, tn;
+    emul_tile_of((int)(g.Mp / WTM), (int)(g.Np / WTN), 4, tm, tn);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int64_t row0 = (int64_t)tm * WTM, col0 = (int64_t)tn * WTN;
+
+    v16i acc[S][2];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[d][i][e] = 0;
+
+    // Staging: A chunk (s, tid) = row tid / 2, half tid % 2 of slice s; B
+    // chunk j = tid + 256 q = slice j / 128, row (j % 128) / 2, half j % 2.
+    // For odd S the last B round has chunks for the first 128 threads only
+    // (two whole waves).
+    const int ar = tid >> 1, ah = (tid & 1) * 16;
+    const bool b_last = (S % 2 == 0) || tid < 128;
+    const signed char *pa = g.As + (row0 + ar) * 32 + ah;
+    const signed char *pb[NB];
+    int lb[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int j = tid + 256 * q;
+        const int bs = min(j / 128, S - 1), br = (j % 128) >> 1;
+        pb[q] = g.Bs + bs * g.Np * g.Kp + (col0 + br) * 32 + ah;
+        lb[q] = bs * (WTN * XLD) + br * XLD + ah;
+    }
+    const int64_t sa = g.Mp * g.Kp, pA = g.Mp * 32, pB = g.Np * 32;
+    v4i ra[S], rb[NB];
+#pragma unroll
+    for (int s = 0; s < S; ++s) ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + (g.k0 >> 5) * pA);
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        if (q + 1 < NB || b_last) rb[q] = *reinterpret_cast<const v4i *>(pb[q] + (g.k0 >> 5) * pB);
+#pragma unroll
+    for (int s = 0; s < S; ++s) *reinterpret_cast<v4i *>(&lA[0][s][ar * XLD + ah]) = ra[s];
+#pragma unroll
+    for (int q = 0; q < NB; ++q)
+        if (q + 1 < NB || b_last) *reinterpret_cast<v4i *>(&lB[0][0][0] + lb[q]) = rb[q];
+    __syncthreads();
+    const int fr = (lane & 31) * XLD + 16 * (lane >> 5);  // fragment offset within a 32-row tile
+    constexpr int pairs = S * (S + 1) / 2;
+    constexpr int store_after = (pairs * 3) / 5 > 0 ? (pairs * 3) / 5 : 1;  // pairs before the stores
+    int cur = 0;
+    for (int64_t k = g.k0; k < g.k1; k += XK) {
+        // Next step's slices (the last step re-reads its own: harmless).
+        const int64_t kn = (k + XK < g.k1) ? k + XK : k;
+#pragma unroll
+        for (int s = 0; s < S; ++s) ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + (kn >> 5) * pA);
+#pragma unroll
+        for (int q = 0; q < NB; ++q)
+            if (q + 1 < NB || b_last) rb[q] = *reinterpret_cast<const v4i *>(pb[q] + (kn >> 5) * pB);
+        v4i bf[S], af[S][2];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                af[s][i] = *reinterpret_cast<const v4i *>(&lA[cur][s][(wm * 64 + i * 32) * XLD + fr]);
+            bf[s] = *reinterpret_cast<const v4i *>(&lB[cur][s][wn * 32 * XLD + fr]);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        int issued = 0;
+#pragma unroll
+        for (int s = 0; s < S; ++s)
+#pragma unroll
+            for (int t = 0; t < S - s; ++t) {  // digit pair (s+1, t+1): weight d = s + t + 2
+#pragma unroll
+                for (int i = 0; i < 2; ++i)
+                    acc[s + t][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[s][i], bf[t],
+                                                                          acc[s + t][i], 0, 0, 0);
+                if (++issued == store_after) {
+                    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                    for (int s2 = 0; s2 < S; ++s2)
+                        *reinterpret_cast<v4i *>(&lA[cur ^ 1][s2][ar * XLD + ah]) = ra[s2];
+#pragma unroll
+                    for (int q = 0; q < NB; ++q)
+                        if (q + 1 < NB || b_last)
+                            *reinterpret_cast<v4i *>(&lB[cur ^ 1][0][0] + lb[q]) = rb[q];
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            }
+        __syncthreads();
+        cur ^= 1;
+    }
+
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int vals[S];
+#pragma unroll
+            for (int d = 0; d < S; ++d) vals[d] = acc[d][i][e];
+            emul_out<S>(g, vals, row0 + wm * 64 + i * 32 + out_row32(lane, e),
+                        col0 + wn * 32 + (lane & 31));
+        }
 }
 
 // Transposing merge (one wave per block): block (I,K) of A lands at rows
@@ -275,23 +549,30 @@ __global__ __launch_bounds__(256) void k_block_map_e(int32_t nbc, const int64_t 
 }
 
 using EmulKernel = void (*)(EmulArgs);
-EmulKernel emul_kernel(int S) {
+template <int S>
+EmulKernel emul_kernel_s(int variant) {
+    return variant == 0 ? k_emul_gemm<S> : variant == 1 ? k_emul_gemm_w<S> : k_emul_gemm_x<S>;
+}
+// variant 0: 64 x 64 tiles; 1: 128 x 64, 16x16x64 MFMA, one stage; 2: 128 x 64,
+// 32x32x32 MFMA, two stages.
+EmulKernel emul_kernel(int S, int variant) {
     switch (S) {
-    case 1: return k_emul_gemm<1>;
-    case 2: return k_emul_gemm<2>;
-    case 3: return k_emul_gemm<3>;
-    case 4: return k_emul_gemm<4>;
-    case 5: return k_emul_gemm<5>;
-    case 6: return k_emul_gemm<6>;
-    case 7: return k_emul_gemm<7>;
-    case 8: return k_emul_gemm<8>;
+    case 1: return emul_kernel_s<1>(variant);
+    case 2: return emul_kernel_s<2>(variant);
+    case 3: return emul_kernel_s<3>(variant);
+    case 4: return emul_kernel_s<4>(variant);
+    case 5: return emul_kernel_s<5>(variant);
+    case 6: return emul_kernel_s<6>(variant);
+    case 7: return emul_kernel_s<7>(variant);
+    case 8: return emul_kernel_s<8>(variant);
     default: return nullptr;
     }
 }
 
 }  // namespace
 
-// Largest k chunk (multiple of 64) with K * 127^2 * S < 2^31.
+// Largest k chunk (multiple of 64, hence of every variant's k step) with
+// K * 127^2 * S < 2^31.
 int64_t emul_chunk(int S) {
     int64_t k = (int64_t(2147483647)) / (127 * 127 * (int64_t)S);
     return std::max<int64_t>(EK, k / EK * EK);
@@ -302,12 +583,16 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
     const int64_t M = A->rows(), K = A->cols(), N = B->cols();
     if (M == 0 || N == 0 || C->nnzb == 0) return BSMM_OK;
     if (alpha == 0.0 || K == 0) return scale_blocks(C, nullptr, beta, s);
-    EmulKernel fn = emul_kernel(S);
+    const int variant = options().emul_kernel;
+    const bool wide = variant != 0;
+    EmulKernel fn = emul_kernel(S, variant);
     if (!fn) {
         set_error(BSMM_EINVAL, "emulation slices must be in [1, 8]");
         return BSMM_EINVAL;
     }
-    const int64_t Mp = ceil_div(M, ET) * ET, Np = ceil_div(N, ET) * ET, Kp = ceil_div(K, EK) * EK;
+    const int64_t tile_m = wide ? WTM : ET, tile_n = wide ? WTN : ET;
+    const int64_t Mp = ceil_div(M, tile_m) * tile_m, Np = ceil_div(N, tile_n) * tile_n;
+    const int64_t Kp = ceil_div(K, EK) * EK;
     DevBuf at, bp, ea, eb, as, bs, V, cmap;
     BSMM_TRY(at.reserve(sizeof(double) * Mp * Kp, s));
     BSMM_TRY(bp.reserve(sizeof(double) * Kp * Np, s));
@@ -359,7 +644,7 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
     const int64_t chunk = emul_chunk(S);
     const int64_t nchunks = ceil_div(Kp, chunk);
     if (nchunks > 1) BSMM_TRY(V.reserve(sizeof(double) * Mp * Np, s));
-    const int64_t tiles = (Mp / ET) * (Np / ET);
+    const int64_t tiles = (Mp / tile_m) * (Np / tile_n);
     if (tiles > INT32_MAX) {
         set_error(BSMM_ERANGE, "emulated product too large");
         return BSMM_ERANGE;

@@ -60,12 +60,14 @@ def test_options_round_trip():
     for k, v in [("path", "dense"), ("path", "stack"), ("path", "emul"), ("path", "auto"),
                  ("emul_slices", "5"), ("emul_slices", "7"), ("plan_cache", "1"), ("plan_cache", "0"),
                  ("stack_kernel", "tuned"),
-                 ("stack_kernel", "plain"), ("stack_chunk", "30000"), ("stack_chunk", "0")]:
+                 ("stack_kernel", "plain"), ("stack_chunk", "30000"), ("stack_chunk", "0"),
+                 ("emul_kernel", "t64"), ("emul_kernel", "t128"), ("emul_kernel", "t128k32"), ("dense_kb", "32"), ("dense_kb", "16")]:
         b.bsmm_set_option(k, v)
         assert b.bsmm_get_option(k) == v
     assert _err(b.bsmm_set_option, "path", "sideways") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "nope", "1") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "stack_chunk", "-4") == b.BSMM_EINVAL
+    assert _err(b.bsmm_set_option, "emul_kernel", "t96") == b.BSMM_EINVAL
 
 
 def test_last_error_is_set():

@@ -71,3 +71,34 @@ def test_sparse_wide_range_within_fp64_tolerance():
     A, B = wide_range_sparse(seed=1, nb=40, bs=23, occupancy=0.2)
     X, _ = _emul(A, B, 1.0, 0.0, None, 7)
     check_against_oracle(X, orc.multiply(1.0, A, B, 0.0), 1e-12)
+
+
+@pytest.mark.parametrize("tile", ["t64", "t128", "t128k32"])
+@pytest.mark.parametrize("S", [2, 7])
+def test_tile_variants_bit_exact_over_many_tiles(tile, S):
+    """Several workgroup tiles in each direction with ragged edges, sparse
+    A, B and C (missing blocks read as zero, C's missing blocks stay
+    unstored): both tile variants equal the reference bit for bit."""
+    b = lib()
+    rng = rng_of(300 + S)
+    rbs = rng.integers(5, 33, size=14).astype(np.int32)
+    kbs = rng.integers(5, 33, size=40).astype(np.int32)
+    cbs = rng.integers(5, 33, size=11).astype(np.int32)
+    A = make_matrix(rng, rbs, kbs, 0.7, values="wide")
+    B = make_matrix(rng, kbs, cbs, 0.7, values="wide")
+    Cin = make_matrix(rng, rbs, cbs, 0.5)
+    b.bsmm_set_option("emul_kernel", tile)
+    try:
+        for alpha, beta in [(1.0, 0.0), (0.5, -2.0)]:
+            X, st = _emul(A, B, alpha, beta, Cin, S)
+            assert st["path"] == 3
+            rp, ci = orc.pattern(A, B, Cin)
+            assert np.array_equal(X.row_ptr, rp) and np.array_equal(X.col_ind, ci)
+            # Blocks outside the pattern get no product and no old value, so
+            # the dense reference is zero there as well.
+            R = er.emulate(orc.to_dense(A), orc.to_dense(B), S, alpha, beta, orc.to_dense(Cin))
+            D = orc.to_dense(X)
+            bad = np.argwhere(D != R)
+            assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:3].tolist()}"
+    finally:
+        b.bsmm_set_option("emul_kernel", "t128k32")
