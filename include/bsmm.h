@@ -142,11 +142,11 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
  *                 scales, exact INT32 sums of every digit pair s + t <= S + 1,
  *                 FP64 recombination and native FP64 beta*C)
  *   "emul_slices" S in [1, 8] (default 7)
- *   "emul_kernel" INT8 GEMM of the emulated path: "t128k32" (default;
- *                 128 x 64 outputs per workgroup, 32x32x32 MFMA, k step 32,
- *                 two LDS stages), "t128" (128 x 64, 16x16x64 MFMA, one
- *                 stage) or "t64" (64 x 64, 16x16x64, two stages); every
- *                 variant gives the same bits
+ *   "emul_kernel" INT8 GEMM of the emulated path: "t128w8" (default; 128 x 64
+ *                 outputs per 512-thread workgroup, 32x32x32 MFMA, k step
+ *                 32, two LDS stages), "t128k32" (same with 256 threads),
+ *                 "t128" (16x16x64 MFMA, k step 64, one stage) or "t64"
+ *                 (64 x 64 tiles); every variant gives the same bits
  *   "stack_kernel" "plain" (default) | "tuned"
  *                 plain: one fixed parameter rule per shape, one launch per
  *                 shape class; tuned: parameters from the tuning database,

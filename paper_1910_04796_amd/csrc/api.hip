@@ -442,6 +442,7 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         if (v == "t64") o.emul_kernel = 0;
         else if (v == "t128") o.emul_kernel = 1;
         else if (v == "t128k32") o.emul_kernel = 2;
+        else if (v == "t128w8") o.emul_kernel = 3;
         else goto bad;
     } else if (k == "plan_cache") {
         if (v == "0") o.plan_cache = 0;
@@ -477,7 +478,10 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
     else if (k == "plan_cache") v = std::to_string(o.plan_cache);
     else if (k == "dense_kb") v = std::to_string(o.dense_kb);
-    else if (k == "emul_kernel") v = o.emul_kernel == 0 ? "t64" : o.emul_kernel == 1 ? "t128" : "t128k32";
+    else if (k == "emul_kernel") v = o.emul_kernel == 0   ? "t64"
+                                        : o.emul_kernel == 1 ? "t128"
+                                        : o.emul_kernel == 2 ? "t128k32"
+                                                             : "t128w8";
     else if (k == "mlp_weights") v = o.mlp_weights;
     else if (k == "stack_params")
         v = o.forced[0] ? std::to_string(o.forced[0]) + " " + std::to_string(o.forced[1]) + " " +

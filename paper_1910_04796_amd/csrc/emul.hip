@@ -28,7 +28,9 @@
 //   t128    128 x 64 outputs, each wave 4 x 2 tiles of the same MFMA, k step
 //           64, one LDS stage refilled from registers;
 //   t128k32 128 x 64 outputs, each wave 2 x 1 tiles of
-//           v_mfma_i32_32x32x32_i8, k step 32, two LDS stages (default).  Workgroup ids are remapped so that the
+//           v_mfma_i32_32x32x32_i8, k step 32, two LDS stages;
+//   t128w8  as t128k32 with 512 threads, each of the 8 waves one 32 x 32 tile
+//           (two waves per SIMD; default).  Workgroup ids are remapped so that the
 // tiles resident on one XCD form a compact group of tile rows and columns
 // (their slices stay in that XCD's L2).
 #include <algorithm>
@@ -104,14 +106,18 @@ __global__ __launch_bounds__(256) void k_row_exp(const double *X, int64_t rows, 
 // one contiguous block.
 __global__ __launch_bounds__(256) void k_slice(const double *X, int64_t rows, int64_t ld, int S,
                                                const int *e, signed char *out) {
-    const int64_t per_row = ld / 8;
+    // Thread -> (k panel p, row r, quarter q of the panel's 32 bytes):
+    // consecutive threads write consecutive 8-byte groups of the output.
     const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * per_row) return;
-    const int64_t r = idx / per_row, k8 = idx - r * per_row;
+    if (idx >= rows * (ld / 8)) return;
+    const int q = (int)(idx & 3);
+    const int64_t rp = idx >> 2;
+    const int64_t p = rp / rows, r = rp - p * rows;
+    const int64_t k = 32 * p + 8 * q;
     const double sc = ldexp(1.0, -e[r]);
     double v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = X[r * ld + 8 * k8 + j] * sc;
+    for (int j = 0; j < 8; ++j) v[j] = X[r * ld + k + j] * sc;
     for (int s = 0; s < S; ++s) {
         unsigned long long w = 0;
 #pragma unroll
@@ -121,9 +127,8 @@ __global__ __launch_bounds__(256) void k_slice(const double *X, int64_t rows, in
             v[j] = t - d;
             w |= (unsigned long long)(unsigned char)(signed char)(int)d << (8 * j);
         }
-        const int64_t k = 8 * k8;
-        *reinterpret_cast<unsigned long long *>(out + (int64_t)s * rows * ld + (k >> 5) * rows * 32 +
-                                                r * 32 + (k & 31)) = w;
+        *reinterpret_cast<unsigned long long *>(out + (int64_t)s * rows * ld + p * rows * 32 + r * 32 +
+                                                8 * q) = w;
     }
 }
 
@@ -373,11 +378,9 @@ __global__ __launch_bounds__(256, 1) void k_emul_gemm_w(EmulArgs g) {
 // 32 x 32 x 32 variant: 128 x 64 outputs per workgroup, waves in 2 x 2, each
 // wave 64 x 32 outputs (2 x 1 tiles of v_mfma_i32_32x32x32_i8).  The k step
 // of 32 halves an LDS stage (S x 192 rows of 32 bytes, padded stride), so two
-// stages fit.  Per step: the slices of the next step are fetched into
-// registers, every fragment of this step is read from LDS up front, and the
-// fetched slices are stored into the other stage part way through the MFMAs
-// (that stage was last read before the previous barrier); one barrier per
-// step.  Scheduling fences keep that order.
+// stages fit.  Slices travel global -> registers -> LDS two steps ahead of
+// their use; one barrier per step; scheduling fences keep the order of the
+// fragment reads, the stage stores and the fetches.
 template <int S>
 __global__ __launch_bounds__(256, 1) void k_emul_gemm_x(EmulArgs g) {
 #pragma clang fp contract(off)
@@ -398,80 +401,97 @@ __global__ __launch_bounds__(256, 1) void k_emul_gemm_x(EmulArgs g) {
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[d][i][e] = 0;
 
-    // Staging: A chunk (s, tid) = row tid / 2, half tid % 2 of slice s; B
-    // chunk j = tid + 256 q = slice j / 128, row (j % 128) / 2, half j % 2.
-    // For odd S the last B round has chunks for the first 128 threads only
-    // (two whole waves).
-    const int ar = tid >> 1, ah = (tid & 1) * 16;
-    const bool b_last = (S % 2 == 0) || tid < 128;
+    // Staging.  Chunk c of a slice's 32-deep step (16 bytes) is row
+    // 32 (c / 64) + l % 16 + 16 (l / 32), half (l / 16) % 2 with l = c % 64:
+    // each wave reads one contiguous KB of the k panel, and every 16 lanes
+    // write 16 consecutive rows of one half (no LDS bank conflicts).  A
+    // chunk c = tid of every slice; B chunk j = tid + 256 q is chunk j % 128
+    // of slice min(j / 128, S - 1).  For odd S the upper 128 threads of the
+    // last round repeat the lower ones (same loads, same bytes stored), which
+    // keeps the loop body free of branches.
+    const int sl = tid & 63;
+    const int ar = 32 * (tid >> 6) + (sl & 15) + 16 * (sl >> 5), ah = 16 * ((sl >> 4) & 1);
     const signed char *pa = g.As + (row0 + ar) * 32 + ah;
     const signed char *pb[NB];
     int lb[NB];
 #pragma unroll
     for (int q = 0; q < NB; ++q) {
         const int j = tid + 256 * q;
-        const int bs = min(j / 128, S - 1), br = (j % 128) >> 1;
+        const int bs = min(j / 128, S - 1), c = j % 128;
+        const int br = 32 * (c >> 6) + (sl & 15) + 16 * (sl >> 5);
         pb[q] = g.Bs + bs * g.Np * g.Kp + (col0 + br) * 32 + ah;
         lb[q] = bs * (WTN * XLD) + br * XLD + ah;
     }
     const int64_t sa = g.Mp * g.Kp, pA = g.Mp * 32, pB = g.Np * 32;
+    const int64_t klast = g.k1 - XK;  // last step of the chunk; later fetches re-read it
     v4i ra[S], rb[NB];
-#pragma unroll
-    for (int s = 0; s < S; ++s) ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + (g.k0 >> 5) * pA);
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-        if (q + 1 < NB || b_last) rb[q] = *reinterpret_cast<const v4i *>(pb[q] + (g.k0 >> 5) * pB);
-#pragma unroll
-    for (int s = 0; s < S; ++s) *reinterpret_cast<v4i *>(&lA[0][s][ar * XLD + ah]) = ra[s];
-#pragma unroll
-    for (int q = 0; q < NB; ++q)
-        if (q + 1 < NB || b_last) *reinterpret_cast<v4i *>(&lB[0][0][0] + lb[q]) = rb[q];
+#define BSMM_EMUL_FETCH(kk)                                                                    \
+    do {                                                                                      \
+        const int64_t kf_ = ((kk) < klast ? (kk) : klast) >> 5;                               \
+        _Pragma("unroll") for (int s_ = 0; s_ < S; ++s_) ra[s_] =                             \
+            *reinterpret_cast<const v4i *>(pa + s_ * sa + kf_ * pA);                          \
+        _Pragma("unroll") for (int q_ = 0; q_ < NB; ++q_) rb[q_] =                            \
+            *reinterpret_cast<const v4i *>(pb[q_] + kf_ * pB);                                \
+    } while (0)
+#define BSMM_EMUL_STAGE(st)                                                                   \
+    do {                                                                                      \
+        _Pragma("unroll") for (int s_ = 0; s_ < S; ++s_)                                      \
+            *reinterpret_cast<v4i *>(&lA[st][s_][ar * XLD + ah]) = ra[s_];                    \
+        _Pragma("unroll") for (int q_ = 0; q_ < NB; ++q_)                                     \
+            *reinterpret_cast<v4i *>(&lB[st][0][0] + lb[q_]) = rb[q_];                        \
+    } while (0)
+    // Prologue: step k0 into stage 0, step k0 + 1 into registers.
+    BSMM_EMUL_FETCH(g.k0);
+    BSMM_EMUL_STAGE(0);
+    BSMM_EMUL_FETCH(g.k0 + XK);
     __syncthreads();
     const int fr = (lane & 31) * XLD + 16 * (lane >> 5);  // fragment offset within a 32-row tile
-    constexpr int pairs = S * (S + 1) / 2;
-    constexpr int store_after = (pairs * 3) / 5 > 0 ? (pairs * 3) / 5 : 1;  // pairs before the stores
+    const int fa = wm * 64 * XLD + fr, fb = wn * 32 * XLD + fr;
+    constexpr int kStageAfter = S > 2 ? 1 : 0;  // slice after whose MFMAs the stage is stored
     int cur = 0;
     for (int64_t k = g.k0; k < g.k1; k += XK) {
-        // Next step's slices (the last step re-reads its own: harmless).
-        const int64_t kn = (k + XK < g.k1) ? k + XK : k;
-#pragma unroll
-        for (int s = 0; s < S; ++s) ra[s] = *reinterpret_cast<const v4i *>(pa + s * sa + (kn >> 5) * pA);
-#pragma unroll
-        for (int q = 0; q < NB; ++q)
-            if (q + 1 < NB || b_last) rb[q] = *reinterpret_cast<const v4i *>(pb[q] + (kn >> 5) * pB);
+        // Software pipeline within the step: B fragments and slice 0 of A up
+        // front; slice s + 1 of A is read while slice s's MFMAs run; after
+        // slice kStageAfter, step k + 1 (fetched during the previous step)
+        // goes to the other stage and step k + 2 is fetched.  The other stage
+        // was last read before the previous barrier.
         v4i bf[S], af[S][2];
 #pragma unroll
+        for (int t = 0; t < S; ++t) bf[t] = *reinterpret_cast<const v4i *>(&lB[cur][t][fb]);
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            af[0][i] = *reinterpret_cast<const v4i *>(&lA[cur][0][fa + i * 32 * XLD]);
+        __builtin_amdgcn_sched_group_barrier(0x100, S + 2, 0);  // DS reads: B, A slice 0
+#pragma unroll
         for (int s = 0; s < S; ++s) {
+            if (s + 1 < S) {
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                af[s][i] = *reinterpret_cast<const v4i *>(&lA[cur][s][(wm * 64 + i * 32) * XLD + fr]);
-            bf[s] = *reinterpret_cast<const v4i *>(&lB[cur][s][wn * 32 * XLD + fr]);
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        int issued = 0;
-#pragma unroll
-        for (int s = 0; s < S; ++s)
+                for (int i = 0; i < 2; ++i)
+                    af[s + 1][i] = *reinterpret_cast<const v4i *>(&lA[cur][s + 1][fa + i * 32 * XLD]);
+                __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);  // DS reads: A slice s + 1
+            }
 #pragma unroll
             for (int t = 0; t < S - s; ++t) {  // digit pair (s+1, t+1): weight d = s + t + 2
 #pragma unroll
                 for (int i = 0; i < 2; ++i)
                     acc[s + t][i] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[s][i], bf[t],
                                                                           acc[s + t][i], 0, 0, 0);
-                if (++issued == store_after) {
-                    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-                    for (int s2 = 0; s2 < S; ++s2)
-                        *reinterpret_cast<v4i *>(&lA[cur ^ 1][s2][ar * XLD + ah]) = ra[s2];
-#pragma unroll
-                    for (int q = 0; q < NB; ++q)
-                        if (q + 1 < NB || b_last)
-                            *reinterpret_cast<v4i *>(&lB[cur ^ 1][0][0] + lb[q]) = rb[q];
-                    __builtin_amdgcn_sched_barrier(0);
-                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);  // the pair's MFMAs
             }
+            if (s == kStageAfter) {
+                // The registers hold step k + 1 until stored; only then are
+                // they refilled with step k + 2.
+                BSMM_EMUL_STAGE(cur ^ 1);
+                __builtin_amdgcn_sched_group_barrier(0x200, S + NB, 0);  // DS writes: next stage
+                BSMM_EMUL_FETCH(k + 2 * XK);
+                __builtin_amdgcn_sched_group_barrier(0x020, S + NB, 0);  // global reads
+            }
+        }
         __syncthreads();
         cur ^= 1;
     }
+#undef BSMM_EMUL_FETCH
+#undef BSMM_EMUL_STAGE
 
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -483,6 +503,121 @@ __global__ __launch_bounds__(256, 1) void k_emul_gemm_x(EmulArgs g) {
             emul_out<S>(g, vals, row0 + wm * 64 + i * 32 + out_row32(lane, e),
                         col0 + wn * 32 + (lane & 31));
         }
+}
+
+// Eight-wave variant of the 32 x 32 x 32 kernel: 512 threads per workgroup,
+// the same 128 x 64 tile, waves in 4 x 2, each wave one 32 x 32 tile (S
+// accumulators of 16 registers), so that two waves share each SIMD and hide
+// each other's LDS and barrier waits.  Stages, slice layout and pipeline as
+// in k_emul_gemm_x.
+template <int S>
+__global__ __launch_bounds__(512, 1) void k_emul_gemm_x8(EmulArgs g) {
+#pragma clang fp contract(off)
+    constexpr int NA = (S + 1) / 2;  // A chunks per thread and step
+    constexpr int NB = (S + 3) / 4;  // B chunks per thread and step
+    __shared__ __attribute__((aligned(16))) signed char lA[2][S][WTM * XLD];
+    __shared__ __attribute__((aligned(16))) signed char lB[2][S][WTN * XLD];
+    int tm, tn;
+    emul_tile_of((int)(g.Mp / WTM), (int)(g.Np / WTN), 4, tm, tn);
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 3, wn = w >> 2;
+    const int64_t row0 = (int64_t)tm * WTM, col0 = (int64_t)tn * WTN;
+
+    v16i acc[S];
+#pragma unroll
+    for (int d = 0; d < S; ++d)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[d][e] = 0;
+
+    // Staging (chunk -> row/half map as in k_emul_gemm_x).  A: chunk tid %
+    // 256 of slices tid / 256 + 2 m; B: chunk j % 128 of slice j / 128 for
+    // j = tid + 512 q.  Slice indices past S - 1 are clamped: those threads
+    // repeat another thread's load and store the same bytes, which keeps the
+    // loop body free of branches.
+    const int sl = tid & 63;
+    const int crow = (sl & 15) + 16 * (sl >> 5), ah = 16 * ((sl >> 4) & 1);
+    const int ar = 32 * ((tid & 255) >> 6) + crow;
+    const signed char *pa[NA];
+    int la[NA];
+#pragma unroll
+    for (int m = 0; m < NA; ++m) {
+        const int as = min((tid >> 8) + 2 * m, S - 1);
+        pa[m] = g.As + as * g.Mp * g.Kp + (row0 + ar) * 32 + ah;
+        la[m] = as * (WTM * XLD) + ar * XLD + ah;
+    }
+    const signed char *pb[NB];
+    int lb[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int j = tid + 512 * q;
+        const int bs = min(j / 128, S - 1), c = j % 128;
+        const int br = 32 * (c >> 6) + crow;
+        pb[q] = g.Bs + bs * g.Np * g.Kp + (col0 + br) * 32 + ah;
+        lb[q] = bs * (WTN * XLD) + br * XLD + ah;
+    }
+    const int64_t pA = g.Mp * 32, pB = g.Np * 32;
+    const int64_t klast = g.k1 - XK;  // last step of the chunk; later fetches re-read it
+    v4i ra[NA], rb[NB];
+#define BSMM_EMUL_FETCH(kk)                                                                    \
+    do {                                                                                      \
+        const int64_t kf_ = ((kk) < klast ? (kk) : klast) >> 5;                               \
+        _Pragma("unroll") for (int m_ = 0; m_ < NA; ++m_) ra[m_] =                            \
+            *reinterpret_cast<const v4i *>(pa[m_] + kf_ * pA);                                \
+        _Pragma("unroll") for (int q_ = 0; q_ < NB; ++q_) rb[q_] =                            \
+            *reinterpret_cast<const v4i *>(pb[q_] + kf_ * pB);                                \
+    } while (0)
+#define BSMM_EMUL_STAGE(st)                                                                   \
+    do {                                                                                      \
+        _Pragma("unroll") for (int m_ = 0; m_ < NA; ++m_)                                     \
+            *reinterpret_cast<v4i *>(&lA[st][0][0] + la[m_]) = ra[m_];                        \
+        _Pragma("unroll") for (int q_ = 0; q_ < NB; ++q_)                                     \
+            *reinterpret_cast<v4i *>(&lB[st][0][0] + lb[q_]) = rb[q_];                        \
+    } while (0)
+    BSMM_EMUL_FETCH(g.k0);
+    BSMM_EMUL_STAGE(0);
+    BSMM_EMUL_FETCH(g.k0 + XK);
+    __syncthreads();
+    const int fr = (lane & 31) * XLD + 16 * (lane >> 5);
+    const int fa = wm * 32 * XLD + fr, fb = wn * 32 * XLD + fr;
+    constexpr int kStageAfter = S > 2 ? 1 : 0;
+    int cur = 0;
+    for (int64_t k = g.k0; k < g.k1; k += XK) {
+        v4i bf[S], af[S];
+#pragma unroll
+        for (int t = 0; t < S; ++t) bf[t] = *reinterpret_cast<const v4i *>(&lB[cur][t][fb]);
+        af[0] = *reinterpret_cast<const v4i *>(&lA[cur][0][fa]);
+        __builtin_amdgcn_sched_group_barrier(0x100, S + 1, 0);  // DS reads: B, A slice 0
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s + 1 < S) {
+                af[s + 1] = *reinterpret_cast<const v4i *>(&lA[cur][s + 1][fa]);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read: A slice s + 1
+            }
+#pragma unroll
+            for (int t = 0; t < S - s; ++t) {  // digit pair (s+1, t+1): weight d = s + t + 2
+                acc[s + t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(af[s], bf[t], acc[s + t], 0, 0, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            }
+            if (s == kStageAfter) {
+                BSMM_EMUL_STAGE(cur ^ 1);
+                __builtin_amdgcn_sched_group_barrier(0x200, NA + NB, 0);  // DS writes: next stage
+                BSMM_EMUL_FETCH(k + 2 * XK);
+                __builtin_amdgcn_sched_group_barrier(0x020, NA + NB, 0);  // global reads
+            }
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+#undef BSMM_EMUL_FETCH
+#undef BSMM_EMUL_STAGE
+
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+        int vals[S];
+#pragma unroll
+        for (int d = 0; d < S; ++d) vals[d] = acc[d][e];
+        emul_out<S>(g, vals, row0 + wm * 32 + out_row32(lane, e), col0 + wn * 32 + (lane & 31));
+    }
 }
 
 // Transposing merge (one wave per block): block (I,K) of A lands at rows
@@ -551,10 +686,13 @@ __global__ __launch_bounds__(256) void k_block_map_e(int32_t nbc, const int64_t 
 using EmulKernel = void (*)(EmulArgs);
 template <int S>
 EmulKernel emul_kernel_s(int variant) {
-    return variant == 0 ? k_emul_gemm<S> : variant == 1 ? k_emul_gemm_w<S> : k_emul_gemm_x<S>;
+    return variant == 0 ? k_emul_gemm<S>
+         : variant == 1 ? k_emul_gemm_w<S>
+         : variant == 2 ? k_emul_gemm_x<S>
+                        : k_emul_gemm_x8<S>;
 }
 // variant 0: 64 x 64 tiles; 1: 128 x 64, 16x16x64 MFMA, one stage; 2: 128 x 64,
-// 32x32x32 MFMA, two stages.
+// 32x32x32 MFMA, two stages; 3: as 2 with eight waves per workgroup.
 EmulKernel emul_kernel(int S, int variant) {
     switch (S) {
     case 1: return emul_kernel_s<1>(variant);
@@ -674,7 +812,7 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
         g.rmap = C->d_row_map();
         g.cmap = C->d_col_map();
         KernelTimer kt(0, s);
-        hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(256), 0, s, g);
+        hipLaunchKernelGGL(fn, dim3((unsigned)tiles), dim3(variant == 3 ? 512 : 256), 0, s, g);
         BSMM_TRY(launch_check("emul gemm"));
     }
     return BSMM_OK;

@@ -52,7 +52,7 @@ struct Options {
     int64_t stack_chunk = 0;
     int time_kernels = 0;
     int dense_kb = 16;             // k step of the dense FP64 GEMM (16 or 32)
-    int emul_kernel = 2;           // emulated GEMM: 0 t64, 1 t128, 2 t128k32
+    int emul_kernel = 3;           // emulated GEMM: 0 t64, 1 t128, 2 t128k32, 3 t128w8
     int plan_cache = 0;            // reuse symbolic result + stacks + graph when patterns repeat
     std::string tune_db;
     std::string mlp_weights;

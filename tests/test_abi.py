@@ -61,7 +61,7 @@ def test_options_round_trip():
                  ("emul_slices", "5"), ("emul_slices", "7"), ("plan_cache", "1"), ("plan_cache", "0"),
                  ("stack_kernel", "tuned"),
                  ("stack_kernel", "plain"), ("stack_chunk", "30000"), ("stack_chunk", "0"),
-                 ("emul_kernel", "t64"), ("emul_kernel", "t128"), ("emul_kernel", "t128k32"), ("dense_kb", "32"), ("dense_kb", "16")]:
+                 ("emul_kernel", "t64"), ("emul_kernel", "t128"), ("emul_kernel", "t128w8"), ("emul_kernel", "t128k32"), ("dense_kb", "32"), ("dense_kb", "16")]:
         b.bsmm_set_option(k, v)
         assert b.bsmm_get_option(k) == v
     assert _err(b.bsmm_set_option, "path", "sideways") == b.BSMM_EINVAL

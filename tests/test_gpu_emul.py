@@ -73,7 +73,7 @@ def test_sparse_wide_range_within_fp64_tolerance():
     check_against_oracle(X, orc.multiply(1.0, A, B, 0.0), 1e-12)
 
 
-@pytest.mark.parametrize("tile", ["t64", "t128", "t128k32"])
+@pytest.mark.parametrize("tile", ["t64", "t128", "t128k32", "t128w8"])
 @pytest.mark.parametrize("S", [2, 7])
 def test_tile_variants_bit_exact_over_many_tiles(tile, S):
     """Several workgroup tiles in each direction with ragged edges, sparse
@@ -101,4 +101,4 @@ def test_tile_variants_bit_exact_over_many_tiles(tile, S):
             bad = np.argwhere(D != R)
             assert len(bad) == 0, f"{len(bad)} mismatches, first {bad[:3].tolist()}"
     finally:
-        b.bsmm_set_option("emul_kernel", "t128k32")
+        b.bsmm_set_option("emul_kernel", "t128w8")
