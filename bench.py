@@ -89,7 +89,7 @@ def main():
     import torch
 
     from paper_1910_04796_amd import bsmm
-    from synth import banded_uneven, dense_square, sparse_uniform
+    from synth import banded_uneven, dense_square, sparse_uniform, wide_range_dense
 
     torch.cuda.set_device(0)
     if args.calibrate_copy:
@@ -168,6 +168,7 @@ def main():
 
     extras = {}
     MCe = None
+    MWe = None
     if not args.no_extras:
         # Split-precision emulation of the same product (7 slices).
         set_opts(bsmm, path="emul", emul_slices=7)
@@ -187,6 +188,38 @@ def main():
             "gemm_kernel_ms": round(ek, 3),
             "int8_tops_achieved": round(pairs * F / (ek * 1e-3) / 1e12, 1), "int8_peak_tops": 5000.0}
         log(f"emulated path: {ems:.3f} ms/step (INT8 GEMM {ek:.3f} ms)")
+
+        # Split-precision configuration of the paper's sizes: N = 16384 in
+        # 32-blocks, entries sign * 10^U(-6, 2); native FP64 dense path vs
+        # the emulation with 7 slices.
+        W1, W2 = wide_range_dense(seed=0, n=16384, bs=BS)
+        MW1, MW2 = bsmm.Matrix.from_blocks(W1), bsmm.Matrix.from_blocks(W2)
+        Fw = 2.0 * 16384 ** 3
+        wres = {"N": 16384, "values": "sign * 10^U(-6,2)", "slices": 7}
+        outs = {}
+        for name, opts in (("native_fp64", dict(path="dense")), ("emulated_int8", dict(path="emul", emul_slices=7))):
+            set_opts(bsmm, **opts)
+            MWc = bsmm.Matrix.empty(W1.rbs, W2.cbs)
+
+            def runw(MWc=MWc):
+                bsmm.multiply(1.0, MW1, MW2, 0.0, MWc, 0.0, stream)
+
+            wms = timed(torch, runw, 3)
+            wres[name] = {"ms_per_step": round(wms, 3), "gflops_fp64_equiv": round(Fw / (wms * 1e-3) / 1e9, 1)}
+            outs[name] = MWc
+            log(f"wide-range 16384 {name}: {wms:.3f} ms")
+        set_opts(bsmm, path="auto")
+        wres["speedup_emulated_vs_native"] = round(wres["native_fp64"]["ms_per_step"] /
+                                                   wres["emulated_int8"]["ms_per_step"], 3)
+        Xn = outs["native_fp64"].to_host().data
+        Xe = outs["emulated_int8"].to_host().data
+        wres["rel_err_emulated_vs_native"] = float(np.linalg.norm(Xe - Xn) / np.linalg.norm(Xn))
+        del Xn, Xe
+        outs["native_fp64"].close()
+        MWe = outs["emulated_int8"]
+        MW1.close()
+        MW2.close()
+        extras["emulated_wide_dense_16384"] = wres
 
         # Banded uneven blocks {5,13,23,32}, N ~ 50,000: plain vs tuned stacks.
         for occ in (0.01, 0.10):
@@ -269,6 +302,19 @@ def main():
         rel_err = rows_err(MC)
         if MCe is not None:
             extras["emulated_int8_s7"]["rel_err"] = rows_err(MCe)
+        if MWe is not None:
+            # Emulated wide-range product against the reference on three
+            # sampled block rows.
+            Xw = MWe.to_host()
+            sizes = orc.block_sizes(Xw.rbs, Xw.cbs, Xw.row_ptr, Xw.col_ind)
+            start = np.concatenate([[0], np.cumsum(sizes)])
+            errs = []
+            for r in (5, 200, 511):
+                Rw = orc.multiply(1.0, W1, W2, 0.0, rows=(r, r + 1), nthreads=threads)
+                a0, a1 = int(Xw.row_ptr[r]), int(Xw.row_ptr[r + 1])
+                errs.append(orc.rel_err(Xw.data[int(start[a0]):int(start[a1])], Rw.data))
+            extras["emulated_wide_dense_16384"]["rel_err_rows_5_200_511"] = max(errs)
+            del Xw
         log(f"cpu baseline: {cpu['value']} GFLOP/s on {threads} threads; rel_err {rel_err:.2e}")
 
     out = {
@@ -287,7 +333,7 @@ def main():
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
-    for M in (MA, MB, MC, MCe):
+    for M in (MA, MB, MC, MCe, MWe):
         if M is not None:
             M.close()
     bsmm.bsmm_set_allocator()
