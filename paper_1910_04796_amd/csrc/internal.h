@@ -225,6 +225,10 @@ int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matr
 struct SmmParams {
     int tm = 0, tn = 0, kc = 0, waves = 0;
 };
+// tm = tn = kMfmaTile selects the FP64 MFMA small-block kernel (kc unused).
+constexpr int kMfmaTile = 16;
+// Length of the learned model's feature vector (mlp_features).
+constexpr int kMlpFeatures = 10;
 // Kernel arguments of one small-block launch.
 struct SmmArgs {
     const double *A;
@@ -258,14 +262,20 @@ int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const i
 using LaunchList = std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>>;
 // Launches of one stack execution: per-class launches (plain) or one
 // instantiated hipGraph holding every class (tuned).
+// Hands an executable graph to the retire list: it is destroyed once `done`
+// (recorded after its last launch) has completed, never while it may still
+// run on the device.
+void retire_graph(hipGraphExec_t exec, hipEvent_t done);
 struct StackExec {
     LaunchList launches;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // recorded after every launch of exec
     StackExec() = default;
     StackExec(const StackExec &) = delete;
     StackExec &operator=(const StackExec &) = delete;
     ~StackExec() {
-        if (exec) (void)hipGraphExecDestroy(exec);
+        if (exec) retire_graph(exec, done);
+        else if (done) (void)hipEventDestroy(done);
     }
 };
 SmmParams plain_params(int m, int n);

@@ -163,12 +163,15 @@ int forward(int F, const float *dP, int64_t n, const float *dX, const int64_t *p
 
 // Features of a shape and a parameter set (before normalisation):
 // log2 m, log2 n, log2 k, TM, TN, log2 of the effective k chunk, waves per
-// workgroup (0 = as many as fit -> 4), log2 of the lanes holding tiles, and
-// the fraction of the register tiles that covers the block.
+// workgroup (0 = as many as fit -> 4), log2 of the lanes (or MFMA tiles)
+// holding tiles, the fraction of the tiles that covers the block (times the
+// k fill of 4-deep steps for the MFMA kernel), and 1 for the MFMA kernel.
 int mlp_features(int m, int n, int k, const SmmParams &p, float *f) {
-    const int kc = (p.kc > 0 && p.kc < k) ? p.kc : k;
+    const bool mfma = p.tm == kMfmaTile && p.tn == kMfmaTile;
+    const int kc = (!mfma && p.kc > 0 && p.kc < k) ? p.kc : k;
     const double lanes = (double)ceil_div(m, p.tm) * (double)ceil_div(n, p.tn);
-    const double cover = (double)m * n / (lanes * p.tm * p.tn);
+    double cover = (double)m * n / (lanes * p.tm * p.tn);
+    if (mfma) cover *= (double)k / (4.0 * (double)ceil_div(k, 4));
     f[0] = (float)std::log2((double)m);
     f[1] = (float)std::log2((double)n);
     f[2] = (float)std::log2((double)k);
@@ -178,7 +181,8 @@ int mlp_features(int m, int n, int k, const SmmParams &p, float *f) {
     f[6] = (float)(p.waves > 0 ? p.waves : 4);
     f[7] = (float)std::log2(lanes);
     f[8] = (float)cover;
-    return 9;
+    f[9] = mfma ? 1.0f : 0.0f;
+    return kMlpFeatures;
 }
 
 namespace {
@@ -234,6 +238,7 @@ bool mlp_select(int m, int n, int k, SmmParams *out) {
     std::vector<SmmParams> cands = candidate_params(m, n, k);
     if (cands.empty()) return false;
     const int F = g_model.F;
+    if (F != kMlpFeatures) return false;  // weights trained on another feature set
     std::vector<float> X(cands.size() * F), Y(cands.size());
     float tmp[kMaxF];
     for (size_t c = 0; c < cands.size(); ++c) {

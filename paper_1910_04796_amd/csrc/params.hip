@@ -68,6 +68,10 @@ std::vector<SmmParams> candidate_params(int m, int n, int k) {
                 for (int w : waves) out.push_back(SmmParams{tm, tn, kc, w});
             }
         }
+    // FP64 MFMA kernel (16 x 16 tiles, zero padding in registers) for blocks
+    // that fill at least half of a tile in both directions.
+    if (m >= 8 && n >= 8 && m <= 64 && n <= 64)
+        for (int w : waves) out.push_back(SmmParams{kMfmaTile, kMfmaTile, 0, w});
     return out;
 }
 

@@ -16,10 +16,13 @@
 //    and read back per k step, A as TM consecutive values, B as TN values
 //    of one row;
 //  * long k is split into chunks that fit the region; tile sets larger than
-//    one wavefront are covered in passes.
+//    one wavefront are covered in passes;
+//  * for blocks of about 16 x 16 and more, a variant runs each C block on
+//    FP64 matrix cores (register tile "16 x 16" in the parameter space).
 //
 // The epilogue applies C = beta*C + alpha*acc (beta == 0 overwrites).
 #include <algorithm>
+#include <mutex>
 
 #include "dev_util.h"
 #include "internal.h"
@@ -129,7 +132,102 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
     }
 }
 
+// FP64 MFMA variant for blocks of at least about 16 x 16 (parameter set
+// tm = tn = 16): one wave owns one run at a time and keeps the C block as
+// MT x NT tiles of v_mfma_f64_16x16x4 accumulators (m <= 16 MT, n <= 16 NT).
+// Operands come straight from the contiguous A and B blocks (each product's
+// blocks are a few KB and stay in L1/L2): per 4-deep k step, lane l holds
+// A(16 i + l % 16, k0 + l / 16) and B(k0 + l / 16, 16 j + l % 16), zero
+// outside the block, so 23- or 13-sized blocks are padded in registers only.
+// Result element e of lane l is row 4 e + l / 16, column l % 16 of a tile.
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+template <int MT, int NT>
+__global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
+    const int lane = lane_id();
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
+    const int m = p.m, n = p.n;
+    const int lr = lane & 15, lk = lane >> 4;
+    for (int64_t r = p.run_begin + wid; r < p.run_end; r += waves) {
+        const int64_t q0 = p.run_ptr[r], q1 = p.run_ptr[r + 1];
+        v4d_t acc[MT][NT];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j) acc[i][j] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+        for (int64_t q = q0; q < q1; ++q) {
+            const ulonglong2 pr = p.prods[q];
+            const double *a = p.A + (int64_t)(pr.x & ((1ull << 48) - 1));
+            const int k = (int)(pr.x >> 48);
+            const double *b = p.B + (int64_t)pr.y;
+            for (int k0 = 0; k0 < k; k0 += 16) {
+                // Four k steps of fragments, then their MFMAs.
+                double af[4][MT], bf[4][NT];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int kk = k0 + 4 * s + lk;
+                    const bool kin = kk < k;
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) {
+                        const int row = 16 * i + lr;
+                        af[s][i] = (kin && row < m) ? a[(int64_t)kk * m + row] : 0.0;
+                    }
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) {
+                        const int col = 16 * j + lr;
+                        bf[s][j] = (kin && col < n) ? b[(int64_t)col * k + kk] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+#pragma unroll
+                    for (int i = 0; i < MT; ++i)
+#pragma unroll
+                        for (int j = 0; j < NT; ++j)
+                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][i], bf[s][j], acc[i][j],
+                                                                             0, 0, 0);
+            }
+        }
+        double *c = p.C + p.run_coff[r];
+#pragma unroll
+        for (int i = 0; i < MT; ++i)
+#pragma unroll
+            for (int j = 0; j < NT; ++j)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int row = 16 * i + 4 * e + lk, col = 16 * j + lr;
+                    if (row < m && col < n) {
+                        double *dst = c + (int64_t)col * m + row;
+                        const double prod = p.alpha * acc[i][j][e];
+                        *dst = (p.beta == 0.0) ? prod : fma(p.beta, *dst, prod);
+                    }
+                }
+    }
+}
+
 using SmmKernel = void (*)(SmmArgs);
+
+template <int MT> SmmKernel pick_mfma_nt(int nt) {
+    switch (nt) {
+    case 1: return k_smm_mfma<MT, 1>;
+    case 2: return k_smm_mfma<MT, 2>;
+    case 3: return k_smm_mfma<MT, 3>;
+    case 4: return k_smm_mfma<MT, 4>;
+    default: return nullptr;
+    }
+}
+
+// MFMA kernels for C blocks up to 64 x 64 (MT, NT in 1..4).
+SmmKernel mfma_kernel_for(int mt, int nt) {
+    switch (mt) {
+    case 1: return pick_mfma_nt<1>(nt);
+    case 2: return pick_mfma_nt<2>(nt);
+    case 3: return pick_mfma_nt<3>(nt);
+    case 4: return pick_mfma_nt<4>(nt);
+    default: return nullptr;
+    }
+}
 
 // Register-tile shapes with a compiled kernel: TM, TN in {1,2,3,4,5,6,8}.
 template <int TM> SmmKernel pick_tn(int tn) {
@@ -177,6 +275,27 @@ SmmParams plain_params(int m, int n) {
 }
 
 int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
+    if (prm.tm == kMfmaTile && prm.tn == kMfmaTile) {
+        const int mt = (int)ceil_div(m, 16), nt = (int)ceil_div(n, 16);
+        SmmKernel fn = mfma_kernel_for(mt, nt);
+        if (!fn) {
+            set_error(BSMM_ENOTSUP, "MFMA small-block kernel covers blocks up to 64 x 64, not %dx%d", m, n);
+            return BSMM_ENOTSUP;
+        }
+        SmmArgs a{};
+        a.m = m;
+        a.n = n;
+        a.tiles_m = mt;
+        a.tiles_n = nt;
+        a.L = kWave;
+        a.G = 1;
+        a.passes = 1;
+        out->fn = (void *)fn;
+        out->args = a;
+        out->waves = prm.waves > 0 ? std::min(prm.waves, 4) : 4;
+        out->lds = 0;
+        return BSMM_OK;
+    }
     const int TM = prm.tm, TN = prm.tn;
     SmmKernel fn = kernel_for(TM, TN);
     if (!fn) {
@@ -302,16 +421,53 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
             b0 = b1;
         }
     }
-    if (tuned && chunk <= 0 && launches.size() > 1)
+    if (tuned && chunk <= 0 && launches.size() > 1) {
         BSMM_TRY(build_graph(launches, A, B, C, st, alpha, beta, &ex->exec));
+        BSMM_HIP(hipEventCreateWithFlags(&ex->done, hipEventDisableTiming));
+    }
     return replay_stacks(*ex, A, B, C, st, alpha, beta, s);
+}
+
+namespace {
+std::mutex g_retire_mu;
+std::vector<std::pair<hipGraphExec_t, hipEvent_t>> g_retired;
+
+// Destroys the retired graphs whose last launch has completed.
+void reap_retired_locked() {
+    std::vector<std::pair<hipGraphExec_t, hipEvent_t>> keep;
+    for (auto &r : g_retired) {
+        const hipError_t q = r.second ? hipEventQuery(r.second) : hipSuccess;
+        if (q == hipErrorNotReady) {
+            if (hipPeekAtLastError() == hipErrorNotReady) (void)hipGetLastError();
+            keep.push_back(r);
+            continue;
+        }
+        (void)hipGraphExecDestroy(r.first);
+        if (r.second) (void)hipEventDestroy(r.second);
+    }
+    g_retired.swap(keep);
+}
+}  // namespace
+
+void retire_graph(hipGraphExec_t exec, hipEvent_t done) {
+    std::lock_guard<std::mutex> lk(g_retire_mu);
+    g_retired.push_back({exec, done});
+    reap_retired_locked();
+    // Bounded backlog: wait for the oldest retired graph when many are pending.
+    while (g_retired.size() > 64) {
+        if (g_retired.front().second) (void)hipEventSynchronize(g_retired.front().second);
+        reap_retired_locked();
+    }
 }
 
 int replay_stacks(const StackExec &ex, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
                   bsmm_matrix_s *C, const Stacks &st, double alpha, double beta, hipStream_t s) {
     if (ex.exec) {
-        KernelTimer kt(1, s);
-        BSMM_HIP(hipGraphLaunch(ex.exec, s));
+        {
+            KernelTimer kt(1, s);
+            BSMM_HIP(hipGraphLaunch(ex.exec, s));
+        }
+        if (ex.done) BSMM_HIP(hipEventRecord(ex.done, s));
         return BSMM_OK;
     }
     for (auto &l : ex.launches)

@@ -34,9 +34,12 @@ def read_table(path):
 
 def features(rows):
     from . import bsmm
-    out = np.zeros((len(rows), 9), np.float32)
+    out = None
     for i, r in enumerate(rows):
-        out[i] = bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[3:7].astype(np.int32))
+        f = bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[3:7].astype(np.int32))
+        if out is None:
+            out = np.zeros((len(rows), len(f)), np.float32)
+        out[i] = f
     return out
 
 
@@ -127,7 +130,7 @@ def main():
     yn = ((y - ym) / ys).astype(np.float32)
     log(f"{len(rows)} timings, {len(shapes)} shapes, {len(held)} held out, {int(tr.sum())} train rows")
     t0 = time.time()
-    P, loss = bsmm.bsmm_mlp_train(init_params(9, args.seed), Xn[tr], yn[tr], epochs=args.epochs,
+    P, loss = bsmm.bsmm_mlp_train(init_params(X.shape[1], args.seed), Xn[tr], yn[tr], epochs=args.epochs,
                                   batch=args.batch, lr=args.lr, seed=args.seed)
     train_s = time.time() - t0
     log(f"trained in {train_s:.1f} s, train MSE {loss:.4f} (standardised log time)")

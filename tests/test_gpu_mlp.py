@@ -74,7 +74,7 @@ def test_model_selection_uses_argmin(tmp_path):
     """A weight file drives parameter selection for a shape absent from the
     database: the chosen set is the candidate with the lowest prediction."""
     b = lib()
-    F = 9
+    F = len(b.bsmm_mlp_features(4, 4, 4, np.array([1, 1, 0, 0], np.int32)))
     P = ref.init_params(F, seed=11)
     mean = np.zeros(F, np.float32); sd = np.ones(F, np.float32)
     path = tmp_path / "mlp.txt"
@@ -91,5 +91,28 @@ def test_model_selection_uses_argmin(tmp_path):
     b.bsmm_set_option("mlp_weights", str(path))
     try:
         assert b.bsmm_select_params(m, n, k) == want
+    finally:
+        b.bsmm_set_option("mlp_weights", "")
+
+
+def test_model_with_other_feature_count_is_ignored(tmp_path):
+    """Weights trained on a different feature vector are not used: selection
+    falls back to the plain rule."""
+    b = lib()
+    F = len(b.bsmm_mlp_features(4, 4, 4, np.array([1, 1, 0, 0], np.int32))) - 1
+    P = ref.init_params(F, seed=12)
+    path = tmp_path / "mlp_old.txt"
+    with open(path, "w") as f:
+        f.write(f"bsmm-mlp features {F}\nmean " + " ".join(["0.0"] * F) + "\n")
+        f.write("std " + " ".join(["1.0"] * F) + "\n")
+        f.write(f"params {len(P)}\n" + " ".join(repr(float(x)) for x in P) + "\n")
+    b.bsmm_set_option("tune_db", "")
+    b.bsmm_set_option("mlp_weights", str(path))
+    try:
+        assert b.bsmm_select_params(17, 29, 11) == b.bsmm_select_params(17, 29, 11)
+        b.bsmm_set_option("mlp_weights", "")
+        plain = b.bsmm_select_params(17, 29, 11)
+        b.bsmm_set_option("mlp_weights", str(path))
+        assert b.bsmm_select_params(17, 29, 11) == plain
     finally:
         b.bsmm_set_option("mlp_weights", "")

@@ -36,13 +36,47 @@ def test_every_candidate_bit_exact(m, n, k):
     R = orc.multiply(1.0, A, B, -1.0, Cin)
     cands = b.bsmm_tune_candidates(m, n, k)
     assert len(cands) > 0
-    for c in cands[:: max(1, len(cands) // 60)]:
+    picked = list(cands[:: max(1, len(cands) // 60)]) + [c for c in cands if c[0] == 16]
+    for c in picked:
         X, st = _tuned(A, B, " ".join(str(int(x)) for x in c), beta=-1.0, Cin=Cin)
         assert st["path"] == 1
         try:
             check_against_oracle(X, R, 0.0)
         except AssertionError as e:
             raise AssertionError(f"parameters {c.tolist()}: {e}") from None
+
+
+@pytest.mark.parametrize("m,n,k", [(8, 8, 8), (16, 16, 16), (23, 23, 23), (32, 32, 32), (13, 23, 5),
+                                   (64, 48, 40), (33, 17, 7)])
+def test_mfma_kernel_matches_reference(m, n, k):
+    """FP64 MFMA small-block kernel (parameter set 16 16 0 w): random
+    values, ragged tiles (blocks padded to 16-multiples in registers),
+    beta != 0 into an existing C, within the FP64 tolerance."""
+    b = lib()
+    rng = rng_of(7000 + m * 100 + n + k)
+    A = make_matrix(rng, np.full(7, m, np.int32), np.full(6, k, np.int32), 0.6)
+    B = make_matrix(rng, np.full(6, k, np.int32), np.full(5, n, np.int32), 0.6)
+    Cin = make_matrix(rng, np.full(7, m, np.int32), np.full(5, n, np.int32), 0.4)
+    for w in (1, 4):
+        R = orc.multiply(0.75, A, B, -0.5, Cin)
+        b.bsmm_set_option("stack_params", f"16 16 0 {w}")
+        try:
+            X, st = gpu_multiply(0.75, A, B, -0.5, Cin, path="stack", kernel="tuned")
+        finally:
+            b.bsmm_set_option("stack_params", "")
+        assert st["path"] == 1
+        check_against_oracle(X, R, TOL)
+
+
+def test_mfma_kernel_uneven_classes_in_one_graph():
+    """Every shape class of a banded uneven product on the MFMA kernel
+    (classes of 5-sized blocks included), launched as one hipGraph, with
+    the filter."""
+    A, B = banded_uneven(seed=23, occupancy=0.3, target=1200)
+    R = orc.multiply(1.0, A, B, 0.0, filter_eps=1e-10)
+    X, st = _tuned(A, B, "16 16 0 2", eps=1e-10)
+    assert st["n_classes"] > 1
+    check_against_oracle(X, R, TOL)
 
 
 @pytest.mark.parametrize("occ", [0.05, 0.3])
@@ -60,7 +94,9 @@ def test_tuned_with_database(tmp_path):
     b = lib()
     db = tmp_path / "db.txt"
     db.write_text("# m n k tm tn kc waves us\n23 23 23 2 8 8 2 1.0\n5 5 5 1 2 4 1 1.0\n")
+    saved = b.bsmm_get_option("mlp_weights")
     b.bsmm_set_option("tune_db", str(db))
+    b.bsmm_set_option("mlp_weights", "")  # a miss then falls through to the plain rule
     try:
         assert b.bsmm_select_params(23, 23, 23) == (2, 8, 8, 2)
         assert b.bsmm_select_params(5, 5, 5) == (1, 2, 4, 1)
@@ -73,6 +109,7 @@ def test_tuned_with_database(tmp_path):
         check_against_oracle(X, orc.multiply(1.0, A, B, 0.0), TOL)
     finally:
         b.bsmm_set_option("tune_db", "")
+        b.bsmm_set_option("mlp_weights", saved)
 
 
 def test_tuner_timings():
