@@ -25,6 +25,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -63,6 +65,90 @@ def timed(torch, fn, reps):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
+def sampled_err(orc, X, A, B, rows, threads, eps=0.0):
+    """Largest relative error of the host copy X against the reference on
+    the given block rows (inf if a row's pattern differs)."""
+    sizes = orc.block_sizes(X.rbs, X.cbs, X.row_ptr, X.col_ind)
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    errs = []
+    for r in rows:
+        R = orc.multiply(1.0, A, B, 0.0, filter_eps=eps, rows=(r, r + 1), nthreads=threads)
+        a0, a1 = int(X.row_ptr[r]), int(X.row_ptr[r + 1])
+        if not np.array_equal(X.col_ind[a0:a1], R.col_ind):
+            errs.append(float("inf"))
+            continue
+        errs.append(orc.rel_err(X.data[int(start[a0]):int(start[a1])], R.data))
+    return max(errs)
+
+
+def all_configs(bsmm, torch, stream):
+    """The remaining workloads of the method's evaluation set: rectangular
+    dense (4096 x 65536 times 65536 x 4096), banded uneven blocks at 30 %,
+    and the sparse split-precision case (1,424^2 blocks of 23, 20 %, entries
+    sign * 10^U(-6,2)).  Returns the timings and, for the reference check,
+    host copies of the results with their inputs."""
+    from synth import banded_uneven, dense_rect, wide_range_sparse
+    res, keep = {}, {}
+
+    def time_path(MA, MB, rbs, cbs, eps, reps, **opts):
+        set_opts(bsmm, **opts)
+        MC = bsmm.Matrix.empty(rbs, cbs)
+
+        def run():
+            bsmm.multiply(1.0, MA, MB, 0.0, MC, eps, stream)
+
+        run()
+        st = bsmm.bsmm_last_stats()
+        ms = timed(torch, run, reps)
+        set_opts(bsmm, path="auto", stack_kernel="plain")
+        return MC, ms, st
+
+    A, B = dense_rect(seed=0)
+    MA, MB = bsmm.Matrix.from_blocks(A), bsmm.Matrix.from_blocks(B)
+    MC, ms, st = time_path(MA, MB, A.rbs, B.cbs, 0.0, 3, path="auto")
+    Fr = 2.0 * 4096 * 4096 * 65536
+    res["dense_rect_4096x4096x65536"] = {"path": st["path"], "ms_per_step": round(ms, 3),
+                                         "gflops": round(Fr / (ms * 1e-3) / 1e9, 1)}
+    keep["rect"] = (MC.to_host(), A, B, 0.0, (0, 61, 127))
+    log(f"dense rect: {ms:.3f} ms")
+    for M in (MA, MB, MC):
+        M.close()
+
+    U, V = banded_uneven(seed=0, occupancy=0.30, target=50000)
+    MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
+    b30 = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
+    for kern in ("plain", "tuned"):
+        MW, ms, st = time_path(MU, MV, U.rbs, V.cbs, 1e-10, 2, path="stack", stack_kernel=kern)
+        b30[kern] = {"ms_per_step": round(ms, 3), "gflops": round(st["flops"] / (ms * 1e-3) / 1e9, 1)}
+        b30["flops_per_step"] = st["flops"]
+        b30["products"] = st["n_products"]
+        if kern == "tuned":
+            keep["banded30"] = (MW.to_host(), U, V, 1e-10, (3, len(U.rbs) // 2, len(U.rbs) - 4))
+        MW.close()
+        log(f"banded 0.3 {kern}: {ms:.3f} ms")
+    b30["tuned_speedup"] = round(b30["plain"]["ms_per_step"] / b30["tuned"]["ms_per_step"], 3)
+    res["banded_uneven_30pct"] = b30
+    MU.close()
+    MV.close()
+    del U, V
+
+    S1, S2 = wide_range_sparse(seed=0)
+    M1, M2 = bsmm.Matrix.from_blocks(S1), bsmm.Matrix.from_blocks(S2)
+    sp = {"N": int(np.sum(S1.rbs)), "block": 23, "occupancy": 0.2, "values": "sign * 10^U(-6,2)"}
+    for name, opts in (("native_fp64_stack_tuned", dict(path="stack", stack_kernel="tuned")),
+                       ("emulated_int8_densified", dict(path="emul", emul_slices=7))):
+        MS, ms, st = time_path(M1, M2, S1.rbs, S2.cbs, 0.0, 2, **opts)
+        sp[name] = {"ms_per_step": round(ms, 3), "gflops_fp64_equiv": round(st["flops"] / (ms * 1e-3) / 1e9, 1)}
+        sp["flops_per_step"] = st["flops"]
+        keep["sparse_" + name] = (MS.to_host(), S1, S2, 0.0, (3, 700, 1420))
+        MS.close()
+        log(f"sparse split-precision workload {name}: {ms:.3f} ms")
+    res["sparse_wide_range_32752_b23"] = sp
+    M1.close()
+    M2.close()
+    return res, keep
+
+
 def set_opts(bsmm, **kw):
     for k, v in kw.items():
         bsmm.bsmm_set_option(k, str(v))
@@ -76,6 +162,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-blocked", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the emulation, uneven and tiny legs")
+    ap.add_argument("--all-configs", action="store_true",
+                    help="also run the rectangular dense, 30 %% banded and sparse split-precision workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -268,6 +356,10 @@ def main():
         M1.close()
         M2.close()
 
+    keep = {}
+    if args.all_configs:
+        extras["all_configs"], keep = all_configs(bsmm, torch, stream)
+
     cpu = None
     rel_err = None
     if not args.no_cpu_baseline:
@@ -315,6 +407,16 @@ def main():
                 errs.append(orc.rel_err(Xw.data[int(start[a0]):int(start[a1])], Rw.data))
             extras["emulated_wide_dense_16384"]["rel_err_rows_5_200_511"] = max(errs)
             del Xw
+        for name, (X, Aref, Bref, eps, rows) in keep.items():
+            e = sampled_err(orc, X, Aref, Bref, rows, threads, eps)
+            key = {"rect": ("dense_rect_4096x4096x65536",), "banded30": ("banded_uneven_30pct", "tuned"),
+                   "sparse_native_fp64_stack_tuned": ("sparse_wide_range_32752_b23", "native_fp64_stack_tuned"),
+                   "sparse_emulated_int8_densified": ("sparse_wide_range_32752_b23", "emulated_int8_densified")}[name]
+            d = extras["all_configs"]
+            for k in key:
+                d = d[k]
+            d["rel_err_sampled_rows"] = e
+            d["sampled_block_rows"] = list(rows)
         log(f"cpu baseline: {cpu['value']} GFLOP/s on {threads} threads; rel_err {rel_err:.2e}")
 
     out = {

@@ -642,9 +642,11 @@ __global__ __launch_bounds__(256) void k_merge_t(int32_t nbr, int64_t nnzb, cons
     const int64_t c0 = col_off[j];
     const double *src = data + blk_off[p];
     const int64_t len = (int64_t)m * n;
+    // Consecutive lanes write consecutive columns of one panel row (reads
+    // stride through the block, which stays in cache).
     for (int64_t e = lane_id(); e < len; e += kWave) {
-        const int64_t jj = e / m, ii = e - jj * m;
-        panel[(r0 + ii) * ld + c0 + jj] = src[e];
+        const int64_t ii = e / n, jj = e - ii * n;
+        panel[(r0 + ii) * ld + c0 + jj] = src[jj * m + ii];
     }
 }
 
@@ -738,8 +740,9 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
     BSMM_TRY(eb.reserve(sizeof(int) * Np, s));
     BSMM_TRY(as.reserve((size_t)S * Mp * Kp, s));
     BSMM_TRY(bs.reserve((size_t)S * Np * Kp, s));
-    BSMM_TRY(fill_zero(at.as<double>(), Mp * Kp, s));
-    BSMM_TRY(fill_zero(bp.as<double>(), Kp * Np, s));
+    // Panels need zeros where no block lands: padding and missing blocks.
+    if (!(A->full() && Mp == M && Kp == K)) BSMM_TRY(fill_zero(at.as<double>(), Mp * Kp, s));
+    if (!(B->full() && Np == N && Kp == K)) BSMM_TRY(fill_zero(bp.as<double>(), Kp * Np, s));
     if (A->nnzb > 0) {
         hipLaunchKernelGGL(k_merge_t, dim3(grid_of(A->nnzb, 4)), dim3(256), 0, s, A->nbr, A->nnzb,
                            A->d_rbs(), A->d_cbs(),
