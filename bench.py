@@ -350,6 +350,14 @@ def main():
 
             run3()
             tiny[kern + "_us"] = round(1e3 * timed(torch, run3, 20), 1)
+            if kern == "tuned":
+                # Repeated multiply into the same C with the plan cache: the
+                # symbolic phase and stack build are skipped and the planned
+                # hipGraph is replayed (same result, see the plan-cache tests).
+                bsmm.bsmm_set_option("plan_cache", "1")
+                run3()
+                tiny["tuned_plan_cache_us"] = round(1e3 * timed(torch, run3, 20), 1)
+                bsmm.bsmm_set_option("plan_cache", "0")
             M3.close()
         extras["sparse_460_b23_latency"] = tiny
         set_opts(bsmm, path="auto", stack_kernel="plain")
