@@ -15,12 +15,22 @@ __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *
     const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (b >= nnzb) return;
     const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
-    double s = 0.0;
-    for (int64_t e = lane_id(); e < len; e += kWave) {
-        const double x = data[o + e];
-        s = fma(x, x, s);
+    // Four independent partial sums per lane keep four loads in flight.
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int64_t e = lane_id();
+    for (; e + 3 * kWave < len; e += 4 * kWave) {
+        const double x0 = data[o + e], x1 = data[o + e + kWave];
+        const double x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
+        s0 = fma(x0, x0, s0);
+        s1 = fma(x1, x1, s1);
+        s2 = fma(x2, x2, s2);
+        s3 = fma(x3, x3, s3);
     }
-    s = wave_sum(s);
+    for (; e < len; e += kWave) {
+        const double x = data[o + e];
+        s0 = fma(x, x, s0);
+    }
+    double s = wave_sum((s0 + s1) + (s2 + s3));
     if (lane_id() == 0) {
         const int64_t k = (s < eps2) ? 0 : 1;
         keep[b] = k;
@@ -51,7 +61,16 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
         new_ci[nb] = ci[b];
         new_off[nb] = no;
     }
-    for (int64_t e = lane_id(); e < len; e += kWave) new_data[no + e] = data[o + e];
+    int64_t e = lane_id();
+    for (; e + 3 * kWave < len; e += 4 * kWave) {
+        const double x0 = data[o + e], x1 = data[o + e + kWave];
+        const double x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
+        new_data[no + e] = x0;
+        new_data[no + e + kWave] = x1;
+        new_data[no + e + 2 * kWave] = x2;
+        new_data[no + e + 3 * kWave] = x3;
+    }
+    for (; e < len; e += kWave) new_data[no + e] = data[o + e];
 }
 
 }  // namespace
