@@ -173,7 +173,6 @@ def main():
               "--gpus N > 1 is not supported", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1910_04796_amd import bsmm

@@ -4,7 +4,7 @@ import numpy as np
 import pytest
 
 from oracle import oracle as orc
-from synth import banded_uneven, dense_rect, wide_range_dense
+from synth import banded_uneven, dense_rect, wide_range_dense, wide_range_sparse
 
 from tests.helpers import gpu_multiply, lib
 
@@ -31,7 +31,7 @@ def test_dense_rect_4096x65536():
     _check_rows(X, A, B, [0, 77])
 
 
-@pytest.mark.parametrize("occ,kernel", [(0.01, "plain"), (0.02, "tuned")])
+@pytest.mark.parametrize("occ,kernel", [(0.01, "plain"), (0.02, "tuned"), (0.10, "tuned")])
 def test_banded_uneven_50000(occ, kernel):
     """Block sizes from {5,13,23,32}, N ~ 50,000, magnitudes exp(-|I-J|/50),
     filter 1e-10; tolerance after filtering (dropped blocks are compared as
@@ -61,3 +61,16 @@ def test_emulated_dense_16384_wide_range():
     X, st = gpu_multiply(1.0, A, B, 0.0, path="emul")
     assert st["path"] == 3
     _check_rows(X, A, B, [3, 400])
+
+
+@pytest.mark.parametrize("path", ["stack", "emul"])
+def test_sparse_wide_range_32752(path):
+    """1,424 x 1,424 blocks of 23 (N = 32,752), 20 % occupancy, entries
+    sign * 10^U(-6,2): the tuned stack path (FP64) and the emulation on
+    densified panels (7 slices), each within 1e-12 on sampled block rows."""
+    b = lib()
+    A, B = wide_range_sparse(seed=0)
+    b.bsmm_set_option("emul_slices", "7")
+    X, st = gpu_multiply(1.0, A, B, 0.0, path=path, kernel="tuned")
+    assert st["path"] == (1 if path == "stack" else 3)
+    _check_rows(X, A, B, [3, 700, 1420])
