@@ -136,11 +136,11 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
 // tm = tn = 16): one wave owns one run at a time and keeps the C block as
 // MT x NT tiles of v_mfma_f64_16x16x4 accumulators (m <= 16 MT, n <= 16 NT).
 // Operands come straight from the contiguous A and B blocks (each product's
-// blocks are a few KB and stay in L1/L2): per 4-deep k step, lane l holds
-// A(16 i + l % 16, k0 + l / 16) and B(k0 + l / 16, 16 j + l % 16), zero
-// outside the block, so 23- or 13-sized blocks are padded in registers only.
+// blocks are a few KB and stay in L1/L2), zero outside the block, so 23- or
+// 13-sized blocks are padded in registers only.
 // Result element e of lane l is row 4 e + l / 16, column l % 16 of a tile.
 typedef double v4d_t __attribute__((ext_vector_type(4)));
+typedef double v2d_t __attribute__((ext_vector_type(2)));
 
 template <int MT, int NT>
 __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
@@ -162,21 +162,33 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
             const int k = (int)(pr.x >> 48);
             const double *b = p.B + (int64_t)pr.y;
             for (int k0 = 0; k0 < k; k0 += 16) {
-                // Four k steps of fragments, then their MFMAs.
+                // Four k steps of fragments, then their MFMAs.  Lane group
+                // g = l / 16 supplies k = k0 + 4 g + s to step s (any
+                // assignment of k to steps is valid when A and B agree), so a
+                // lane's B operands are four consecutive doubles of a column.
                 double af[4][MT], bf[4][NT];
+                const int kb = k0 + 4 * lk;
 #pragma unroll
-                for (int s = 0; s < 4; ++s) {
-                    const int kk = k0 + 4 * s + lk;
-                    const bool kin = kk < k;
+                for (int i = 0; i < MT; ++i) {
+                    const int row = 16 * i + lr;
 #pragma unroll
-                    for (int i = 0; i < MT; ++i) {
-                        const int row = 16 * i + lr;
-                        af[s][i] = (kin && row < m) ? a[(int64_t)kk * m + row] : 0.0;
-                    }
+                    for (int s = 0; s < 4; ++s)
+                        af[s][i] = (row < m && kb + s < k) ? a[(int64_t)(kb + s) * m + row] : 0.0;
+                }
 #pragma unroll
-                    for (int j = 0; j < NT; ++j) {
-                        const int col = 16 * j + lr;
-                        bf[s][j] = (kin && col < n) ? b[(int64_t)col * k + kk] : 0.0;
+                for (int j = 0; j < NT; ++j) {
+                    const int col = 16 * j + lr;
+                    const double *bc = b + (int64_t)col * k + kb;
+                    if (col < n && kb + 3 < k && (reinterpret_cast<uintptr_t>(bc) & 15) == 0) {
+                        const v2d_t lo = *reinterpret_cast<const v2d_t *>(bc);
+                        const v2d_t hi = *reinterpret_cast<const v2d_t *>(bc + 2);
+                        bf[0][j] = lo[0];
+                        bf[1][j] = lo[1];
+                        bf[2][j] = hi[0];
+                        bf[3][j] = hi[1];
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) bf[s][j] = (col < n && kb + s < k) ? bc[s] : 0.0;
                     }
                 }
 #pragma unroll
