@@ -179,9 +179,12 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
                 for (int j = 0; j < NT; ++j) {
                     const int col = 16 * j + lr;
                     const double *bc = b + (int64_t)col * k + kb;
-                    if (col < n && kb + 3 < k && (reinterpret_cast<uintptr_t>(bc) & 15) == 0) {
-                        const v2d_t lo = *reinterpret_cast<const v2d_t *>(bc);
-                        const v2d_t hi = *reinterpret_cast<const v2d_t *>(bc + 2);
+                    if (col < n && kb + 3 < k) {
+                        // 16-byte loads at 8-byte alignment (dword alignment
+                        // is all the vector loads need).
+                        v2d_t lo, hi;
+                        __builtin_memcpy(&lo, bc, sizeof lo);
+                        __builtin_memcpy(&hi, bc + 2, sizeof hi);
                         bf[0][j] = lo[0];
                         bf[1][j] = lo[1];
                         bf[2][j] = hi[0];
