@@ -149,6 +149,73 @@ def all_configs(bsmm, torch, stream):
     return res, keep
 
 
+PAPER_SHAPES = {"square_63360": (63360, 63360, 63360),
+                "rect_1408x1408x1982464": (1408, 1408, 1982464)}
+
+
+def paper_workloads(bsmm, torch, stream, names, threads):
+    """The paper's own benchmark products (Sec. IV) on one GPU: square
+    M = N = K = 63,360 and tall-and-skinny M = N = 1,408, K = 1,982,464, in
+    square blocks of 22 or 64, every block present, values U[-1, 1].  Each
+    is run densified (merged panels + one FP64 MFMA GEMM) and blocked (tuned
+    stacks, built in row panels when the products exceed the stack cap);
+    reported: time per multiply, T_blocked / T_densified per block size, and
+    the densified time for blocks of 22 over that for 64.  One warm-up
+    multiply and two timed ones per mode; a warm-up longer than 20 s is
+    itself the timing.  Every result is checked against the reference on
+    two sampled block rows."""
+    from oracle import oracle as orc
+    from synth import BlockCSR, pattern_full, rng_of, values_uniform
+    out = {}
+    for name in names:
+        M, Nn, K = PAPER_SHAPES[name]
+        rng = rng_of(0)
+        log(f"{name}: drawing {M * K + K * Nn:.3e} values")
+        a_vals = values_uniform(rng, M * K)
+        b_vals = values_uniform(rng, K * Nn)
+        F = 2.0 * M * Nn * K
+        res = {"M": M, "N": Nn, "K": K, "flops_per_multiply": F}
+        for bs in (64, 22):  # the longest run (blocked, blocks of 22) last
+            ms_, ns_, ks_ = (np.full(x // bs, bs, np.int32) for x in (M, Nn, K))
+            A = BlockCSR(ms_, ks_, *pattern_full(len(ms_), len(ks_)), a_vals)
+            B = BlockCSR(ks_, ns_, *pattern_full(len(ks_), len(ns_)), b_vals)
+            MA, MB = bsmm.Matrix.from_blocks(A), bsmm.Matrix.from_blocks(B)
+            r = {"blocks_A": int(A.nnzb), "blocks_B": int(B.nnzb)}
+            for mode, opts in (("densified", dict(path="dense")),
+                               ("blocked", dict(path="stack", stack_kernel="tuned", verbose=1))):
+                set_opts(bsmm, **opts)
+                MC = bsmm.Matrix.empty(ms_, ns_)
+
+                def run(MC=MC):
+                    bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream)
+
+                t_first = timed(torch, run, 1)
+                st = bsmm.bsmm_last_stats()
+                ms = t_first if t_first > 20e3 else timed(torch, run, 2)
+                set_opts(bsmm, path="auto", stack_kernel="plain", verbose=0)
+                r[mode] = {"ms": round(ms, 2), "gflops": round(F / (ms * 1e-3) / 1e9, 1),
+                           "timed_runs": 1 if t_first > 20e3 else 2, "path": st["path"],
+                           "products": st["n_products"], "row_panels": st["n_row_panels"]}
+                log(f"{name} b{bs} {mode}: {ms:.1f} ms ({r[mode]['gflops']} GFLOP/s), "
+                    f"{st['n_products']} products, {st['n_row_panels']} row panels")
+                X = MC.to_host()
+                MC.close()
+                rows = (0, len(ms_) - 1)
+                r[mode]["rel_err_sampled_rows"] = sampled_err(orc, X, A, B, rows, threads)
+                r[mode]["sampled_block_rows"] = list(rows)
+                log(f"{name} b{bs} {mode}: rel err {r[mode]['rel_err_sampled_rows']:.2e} on block rows {rows}")
+                del X
+            r["t_blocked_over_t_densified"] = round(r["blocked"]["ms"] / r["densified"]["ms"], 3)
+            res[f"b{bs}"] = r
+            MA.close()
+            MB.close()
+            del A, B
+        res["densified_b22_over_b64"] = round(res["b22"]["densified"]["ms"] / res["b64"]["densified"]["ms"], 4)
+        out[name] = res
+        del a_vals, b_vals
+    return out
+
+
 def set_opts(bsmm, **kw):
     for k, v in kw.items():
         bsmm.bsmm_set_option(k, str(v))
@@ -164,6 +231,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the emulation, uneven and tiny legs")
     ap.add_argument("--all-configs", action="store_true",
                     help="also run the rectangular dense, 30 %% banded and sparse split-precision workloads")
+    ap.add_argument("--paper-workloads", default="",
+                    help="only run the paper's products: comma list of " + ", ".join(PAPER_SHAPES))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -192,6 +261,17 @@ def main():
     stream = torch.cuda.current_stream()
     bsmm.use_default_tuning()
     set_opts(bsmm, path="auto", stack_kernel="plain")
+    if args.paper_workloads:
+        names = [x for x in args.paper_workloads.split(",") if x]
+        bad = [x for x in names if x not in PAPER_SHAPES]
+        if bad:
+            sys.exit(f"bench.py: unknown paper workload(s) {bad}")
+        threads = min(len(os.sched_getaffinity(0)), 16)
+        res = paper_workloads(bsmm, torch, stream, names, threads)
+        print(json.dumps({"paper_workloads": res, "dtype": "f64", "data": "synthetic", "n_gpus": 1}),
+              flush=True)
+        bsmm.bsmm_set_allocator()
+        return
     log("generating inputs")
     A, B = dense_square(seed=0, n=N, bs=BS)
     MA = bsmm.Matrix.from_blocks(A)
@@ -375,11 +455,11 @@ def main():
         from oracle import oracle as orc
         threads = min(len(os.sched_getaffinity(0)), 16)
         row_flops = 2.0 * BS * N * N  # one block row of C: 32 x 8192 x 8192
-        orc.multiply(1.0, A, B, 0.0, rows=(0, 1), nthreads=threads)  # warm-up
+        orc.multiply(1.0, A, B, 0.0, rows=(0, 2), nthreads=threads)  # warm-up (threads, pages)
         c0 = time.perf_counter()
-        orc.multiply(1.0, A, B, 0.0, rows=(1, 2), nthreads=threads)
-        t_row = time.perf_counter() - c0
-        r0 = 17
+        orc.multiply(1.0, A, B, 0.0, rows=(2, 6), nthreads=threads)
+        t_row = (time.perf_counter() - c0) / 4
+        r0 = 6
         nrows = int(max(1, min(N // BS - r0, 15.0 / max(t_row, 1e-3))))
         c0 = time.perf_counter()
         R = orc.multiply(1.0, A, B, 0.0, rows=(r0, r0 + nrows), nthreads=threads)

@@ -154,6 +154,15 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
  *                 classes launched together as nodes of one hipGraph
  *   "stack_chunk" maximum products per stack launch, "0" = unlimited
  *                 (paper, Sec. II: batches of at most 30000 products)
+ *   "stack_panel" maximum products held in the stacks at once (default
+ *                 "1073741824", 16 GiB of product entries; "0" = no
+ *                 limit): a multiply with more products builds and runs
+ *                 its stacks over panels of consecutive C block rows, one
+ *                 panel after another on the stream (a row whose products
+ *                 alone exceed the limit forms a panel of its own); such a
+ *                 multiply leaves no plan for "plan_cache" to replay
+ *   "verbose"     "1": one line on stderr per stack row panel as it is
+ *                 queued (progress of long multiplies); "0" (default): quiet
  *   "tune_db"     path of a tuning database file ("" = none)
  *   "mlp_weights" path of a learned-model weight file ("" = none)
  *   "stack_params" "TM TN KC WAVES": the tuned path uses this parameter
@@ -195,6 +204,9 @@ typedef struct bsmm_multiply_stats {
     int64_t c_nnzb_before; /* C blocks before the filter                    */
     int64_t c_nnzb_after;  /* C blocks after the filter                     */
     double flops;          /* sum of 2*m*n*k over the block products        */
+    int64_t n_row_panels;  /* stack path: C block-row panels the stacks were
+                              built and run in (option "stack_panel"); 0 on
+                              the other paths                               */
 } bsmm_multiply_stats;
 int bsmm_last_stats(bsmm_multiply_stats *out);
 
@@ -232,8 +244,15 @@ int bsmm_kernel_times(double *gemm_ms, int64_t *gemm_launches, double *stack_ms,
  * autotuner times the parameter sets of each (m, n, k)).
  *
  * A parameter set is 4 int32: register tile rows TM and columns TN per lane
- * (each in {1,2,3,4,5,6,8}), k chunk staged per step (0 = as large as LDS
- * allows), waves per workgroup (1, 2 or 4; 0 = as many as fit).
+ * (each in {1,2,3,4,5,6,8}) of the FP64 VALU kernel, k chunk staged per step
+ * (0 = as large as LDS allows), waves per workgroup (1, 2 or 4; 0 = as many
+ * as fit).  TM = TN = 16 selects the FP64 MFMA kernel instead (one wave per
+ * C block, 16 x 16 tiles of v_mfma_f64_16x16x4, blocks up to 64 x 64; the k
+ * chunk is ignored).
+ *
+ * The run length is the number of products per C block; short and long runs
+ * favour different sets, so the database and the learned model are keyed by
+ * it as well as by the shape.
  *
  * bsmm_tune_candidates: the legal candidate sets of shape (m, n, k).
  *   *n_cands: in = capacity (sets), out = count; cands may be NULL to query.
@@ -243,14 +262,19 @@ int bsmm_kernel_times(double *gemm_ms, int64_t *gemm_launches, double *stack_ms,
  *   timed launches (HIP events); out_us[c] = median microseconds, or -1 when
  *   the set cannot be launched.  1 <= m, n, k <= 256; n_runs * run_len <=
  *   2^26.  The library's own device memory holds the synthetic data.
- * bsmm_select_params: the parameters the tuned path uses for (m, n, k):
- *   database entry, else the learned model's choice, else the plain rule.
+ * bsmm_select_params: the parameters the tuned path uses for (m, n, k) in
+ *   runs of about run_len products: the database entry of that shape timed
+ *   at the run length nearest to run_len (log scale), else the learned
+ *   model's choice, else the plain rule.  Database lines are
+ *   "m n k R tm tn kc waves [best_us plain_us]"; lines without R
+ *   ("m n k tm tn kc waves [best_us plain_us]") count as R = 8; lines of
+ *   any other length are skipped.  run_len < 1: BSMM_EINVAL.
  */
 int bsmm_tune_candidates(int32_t m, int32_t n, int32_t k, int32_t *n_cands, int32_t *cands);
 int bsmm_tune_shape(int32_t m, int32_t n, int32_t k, int64_t n_runs, int32_t run_len,
                     int32_t n_cands, const int32_t *cands, int32_t reps, double *out_us,
                     void *stream);
-int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t *params4);
+int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t run_len, int32_t *params4);
 
 /*
  * Learned performance model (paper, Sec. II: a model learned from part of the
@@ -262,10 +286,13 @@ int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t *params4);
  * row-major, b2 [64], W3 [64], b3 [1].  Every array argument is host memory;
  * the work runs on the device (null stream) and the call returns when done.
  *
- * bsmm_mlp_features: the F raw features of (m, n, k, params4) (F = 9 here):
- *   log2 m, log2 n, log2 k, TM, TN, log2 effective k chunk, waves per
- *   workgroup, log2 lanes holding tiles, fraction of the tiles that covers
- *   the block.  Training and selection both use this definition.
+ * bsmm_mlp_features: the F raw features of (m, n, k, run_len, params4)
+ *   (F = 11 here): log2 m, log2 n, log2 k, TM, TN, log2 effective k chunk,
+ *   waves per workgroup, log2 lanes (or MFMA tiles) holding the block,
+ *   fraction of the tiles that covers the block (times the k fill of 4-deep
+ *   steps for the MFMA kernel), 1 for the MFMA kernel else 0, log2 run_len.
+ *   Training and selection both use this definition; a weight file trained
+ *   on another feature count is not used for selection.
  * bsmm_mlp_forward: y[i] for the n rows of x (n x F, row-major).
  * bsmm_mlp_grad: gradient of the mean squared error over the n samples
  *   (per-sample gradients summed in sample order) and the loss.
@@ -281,8 +308,8 @@ int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t *params4);
  * lowest prediction.  Errors: EINVAL on bad arguments, ENOMEM, EDEVICE.
  */
 int bsmm_mlp_param_count(int32_t n_features, int64_t *count);
-int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, const int32_t *params4, float *features,
-                      int32_t *n_features);
+int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, int32_t run_len, const int32_t *params4,
+                      float *features, int32_t *n_features);
 int bsmm_mlp_forward(int32_t n_features, const float *params, int64_t n, const float *x, float *y);
 int bsmm_mlp_grad(int32_t n_features, const float *params, int64_t n, const float *x,
                   const float *t, float *grad, float *loss);

@@ -90,28 +90,40 @@ def check_compatible(A, B, C=None):
             raise ValueError("C block sizes do not match A rows x B columns")
 
 
-def pattern(A, B, C=None, mutant: int = 0):
-    """Output pattern: old C pattern united with {(I,J): some K has A(I,K), B(K,J)}."""
+def pattern(A, B, C=None, mutant: int = 0, rows: Optional[tuple] = None):
+    """Output pattern: old C pattern united with {(I,J): some K has A(I,K), B(K,J)}.
+
+    rows=(r0, r1) computes block rows [r0, r1) only (every other row is
+    returned empty): each output row depends on its own A and C rows alone.
+    """
     lib = load(mutant)
     check_compatible(A, B, C)
     a = _arrays(A)
     b = _arrays(B)
     nbr, nbc = len(a[0]), len(b[1])
+    r0, r1 = (0, nbr) if rows is None else (int(rows[0]), int(rows[1]))
+    if not (0 <= r0 <= r1 <= nbr):
+        raise ValueError("row range out of bounds")
+    a_rp = a[2][r0:r1 + 1] - a[2][r0]
+    a_ci = a[3][a[2][r0]:a[2][r1]]
     c_rp = c_ci = None
     if C is not None:
         c = _arrays(C)
-        c_rp, c_ci = c[2], c[3]
-    rp = np.zeros(nbr + 1, dtype=np.int64)
-    st = lib.orc_pattern(nbr, nbc, _p(a[2], _i64p), _p(a[3], _i32p), _p(b[2], _i64p), _p(b[3], _i32p),
+        c_rp = c[2][r0:r1 + 1] - c[2][r0]
+        c_ci = c[3][c[2][r0]:c[2][r1]]
+    n = r1 - r0
+    rp = np.zeros(n + 1, dtype=np.int64)
+    st = lib.orc_pattern(n, nbc, _p(a_rp, _i64p), _p(a_ci, _i32p), _p(b[2], _i64p), _p(b[3], _i32p),
                          _p(c_rp, _i64p), _p(c_ci, _i32p), _p(rp, _i64p), None)
     if st:
         raise MemoryError("reference pattern: out of memory")
     ci = np.zeros(max(int(rp[-1]), 1), dtype=np.int32)
-    st = lib.orc_pattern(nbr, nbc, _p(a[2], _i64p), _p(a[3], _i32p), _p(b[2], _i64p), _p(b[3], _i32p),
+    st = lib.orc_pattern(n, nbc, _p(a_rp, _i64p), _p(a_ci, _i32p), _p(b[2], _i64p), _p(b[3], _i32p),
                          _p(c_rp, _i64p), _p(c_ci, _i32p), _p(rp, _i64p), _p(ci, _i32p))
     if st:
         raise MemoryError("reference pattern: out of memory")
-    return rp, ci[: int(rp[-1])]
+    full = np.concatenate([np.zeros(r0, np.int64), rp, np.full(nbr - r1, rp[-1], np.int64)])
+    return full, ci[: int(rp[-1])]
 
 
 def block_sizes(rbs, cbs, row_ptr, col_ind):
@@ -166,10 +178,10 @@ def multiply(alpha: float, A, B, beta: float, C=None, filter_eps: float = 0.0, *
     b = _arrays(B)
     nbr, nbk, nbc = len(a[0]), len(b[0]), len(b[1])
     c = _arrays(C) if C is not None else (None,) * 5
-    o_rp, o_ci = pattern(A, B, C, mutant)
     r0, r1 = (0, nbr) if rows is None else (int(rows[0]), int(rows[1]))
     if not (0 <= r0 <= r1 <= nbr):
         raise ValueError("row range out of bounds")
+    o_rp, o_ci = pattern(A, B, C, mutant, rows=(r0, r1))
     sizes = block_sizes(a[0], b[1], o_rp, o_ci)
     nelem = int(sizes[o_rp[r0]:o_rp[r1]].sum())
     o_data = np.zeros(max(nelem, 1), dtype=np.float64)

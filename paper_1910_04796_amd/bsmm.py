@@ -55,7 +55,7 @@ class bsmm_multiply_stats(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("n_classes", ctypes.c_int32),
                 ("n_products", ctypes.c_int64), ("n_runs", ctypes.c_int64),
                 ("c_nnzb_before", ctypes.c_int64), ("c_nnzb_after", ctypes.c_int64),
-                ("flops", ctypes.c_double)]
+                ("flops", ctypes.c_double), ("n_row_panels", ctypes.c_int64)]
 
 
 _lib.bsmm_create_matrix.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _vp, ctypes.c_int,
@@ -74,10 +74,10 @@ _lib.bsmm_inspect_stacks.argtypes = [_vp, _vp, _vp, _i64p, _i64p, _i64p, _i32p, 
 _lib.bsmm_kernel_times.argtypes = [_f64p, _i64p, _f64p, _i64p, ctypes.c_int]
 _lib.bsmm_tune_candidates.argtypes = [_i32, _i32, _i32, _i32p, _i32p]
 _lib.bsmm_tune_shape.argtypes = [_i32, _i32, _i32, _i64, _i32, _i32, _i32p, _i32, _f64p, _vp]
-_lib.bsmm_select_params.argtypes = [_i32, _i32, _i32, _i32p]
+_lib.bsmm_select_params.argtypes = [_i32, _i32, _i32, _i32, _i32p]
 _f32p = ctypes.POINTER(ctypes.c_float)
 _lib.bsmm_mlp_param_count.argtypes = [_i32, _i64p]
-_lib.bsmm_mlp_features.argtypes = [_i32, _i32, _i32, _i32p, _f32p, _i32p]
+_lib.bsmm_mlp_features.argtypes = [_i32, _i32, _i32, _i32, _i32p, _f32p, _i32p]
 _lib.bsmm_mlp_forward.argtypes = [_i32, _f32p, _i64, _f32p, _f32p]
 _lib.bsmm_mlp_grad.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _f32p, _f32p]
 _lib.bsmm_mlp_adam_step.argtypes = [_i32, _f32p, _f32p, _f32p, _f32p, _i32, ctypes.c_float,
@@ -300,9 +300,11 @@ def bsmm_tune_shape(m, n, k, cands, n_runs=3750, run_len=8, reps=5, stream=None)
     return out[:len(c)]
 
 
-def bsmm_select_params(m, n, k):
+def bsmm_select_params(m, n, k, run_len=8):
+    """Parameters of the tuned path for (m, n, k) in runs of about run_len
+    products per C block."""
     p = np.zeros(4, np.int32)
-    _check(_lib.bsmm_select_params(m, n, k, p.ctypes.data_as(_i32p)))
+    _check(_lib.bsmm_select_params(m, n, k, run_len, p.ctypes.data_as(_i32p)))
     return tuple(int(x) for x in p)
 
 
@@ -316,11 +318,11 @@ def bsmm_mlp_param_count(n_features):
     return c.value
 
 
-def bsmm_mlp_features(m, n, k, params4):
+def bsmm_mlp_features(m, n, k, params4, run_len=8):
     p = np.ascontiguousarray(params4, dtype=np.int32)
     out = np.zeros(32, np.float32)
     nf = _i32()
-    _check(_lib.bsmm_mlp_features(m, n, k, p.ctypes.data_as(_i32p), out.ctypes.data_as(_f32p),
+    _check(_lib.bsmm_mlp_features(m, n, k, run_len, p.ctypes.data_as(_i32p), out.ctypes.data_as(_f32p),
                                   ctypes.byref(nf)))
     return out[:nf.value]
 

@@ -420,6 +420,11 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         long long x = strtoll(value, &end, 10);
         if (!end || *end || x < 0) goto bad;
         o.stack_chunk = x;
+    } else if (k == "stack_panel") {
+        char *end = nullptr;
+        long long x = strtoll(value, &end, 10);
+        if (!end || *end || x < 0) goto bad;
+        o.stack_panel = x;
     } else if (k == "tune_db") {
         o.tune_db = v;
     } else if (k == "emul_slices") {
@@ -443,6 +448,10 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         else if (v == "t128") o.emul_kernel = 1;
         else if (v == "t128k32") o.emul_kernel = 2;
         else if (v == "t128w8") o.emul_kernel = 3;
+        else goto bad;
+    } else if (k == "verbose") {
+        if (v == "0") o.verbose = 0;
+        else if (v == "1") o.verbose = 1;
         else goto bad;
     } else if (k == "plan_cache") {
         if (v == "0") o.plan_cache = 0;
@@ -474,8 +483,10 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     else if (k == "emul_slices") v = std::to_string(o.emul_slices);
     else if (k == "stack_kernel") v = o.stack_kernel ? "tuned" : "plain";
     else if (k == "stack_chunk") v = std::to_string(o.stack_chunk);
+    else if (k == "stack_panel") v = std::to_string(o.stack_panel);
     else if (k == "tune_db") v = o.tune_db;
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
+    else if (k == "verbose") v = std::to_string(o.verbose);
     else if (k == "plan_cache") v = std::to_string(o.plan_cache);
     else if (k == "dense_kb") v = std::to_string(o.dense_kb);
     else if (k == "emul_kernel") v = o.emul_kernel == 0   ? "t64"

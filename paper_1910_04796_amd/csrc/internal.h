@@ -50,7 +50,9 @@ struct Options {
     int emul_slices = 7;   // digit slices of the emulated path
     int stack_kernel = 0;  // 0 plain, 1 tuned
     int64_t stack_chunk = 0;
+    int64_t stack_panel = int64_t(1) << 30;  // products of one row panel of stacks (0: no limit)
     int time_kernels = 0;
+    int verbose = 0;       // one stderr line per stack row panel
     int dense_kb = 16;             // k step of the dense FP64 GEMM (16 or 32)
     int emul_kernel = 3;           // emulated GEMM: 0 t64, 1 t128, 2 t128k32, 3 t128w8
     int plan_cache = 0;            // reuse symbolic result + stacks + graph when patterns repeat
@@ -213,9 +215,27 @@ struct Stacks {
     DevBuf run_class;  // int32[n_runs]
     DevBuf prods;      // ulonglong2[n_prod]: {a_off | k << 48, b_off}
     DevBuf c_count;    // int64[C.nnzb]   products per C block
+    DevBuf c_row;      // int32[C.nnzb]   block row of every C block
+    DevBuf run_of_c;   // int64[C.nnzb]   run of every C block in its panel, or -1
+    DevBuf d_rsi, d_csi, missing;     // size-class index of rows / columns; pattern flag
+    std::vector<char> class_active;   // class holds runs (any panel so far)
 };
+// Whole stacks: stack_count, then stack_rows over every C block row.
+// st.n_prod must hold the product count of the symbolic phase on entry.
 int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
                  Stacks &st, hipStream_t s);
+// Products per C block for every C block row (and the size classes).
+int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                Stacks &st, hipStream_t s);
+// After stack_count: products and C blocks before every C block row
+// (host vectors of nbr + 1 entries); EINDEX when C misses a product block.
+int stack_row_bounds(const bsmm_matrix_s *C, const Stacks &st, std::vector<int64_t> *prod_before,
+                     std::vector<int64_t> *blk_before, hipStream_t s);
+// After stack_count: the runs and products of C block rows [r0, r1) (C
+// blocks [c0, c1), nprod products), replacing the previous panel's.
+int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+               Stacks &st, int32_t r0, int32_t r1, int64_t c0, int64_t c1, int64_t nprod,
+               hipStream_t s);
 
 // --------------------------------------------------------- small blocks
 // Parameters of the small-block kernel (the tuning space): register tile
@@ -228,7 +248,7 @@ struct SmmParams {
 // tm = tn = kMfmaTile selects the FP64 MFMA small-block kernel (kc unused).
 constexpr int kMfmaTile = 16;
 // Length of the learned model's feature vector (mlp_features).
-constexpr int kMlpFeatures = 10;
+constexpr int kMlpFeatures = 11;
 // Kernel arguments of one small-block launch.
 struct SmmArgs {
     const double *A;
@@ -279,14 +299,14 @@ struct StackExec {
     }
 };
 SmmParams plain_params(int m, int n);
-// Selected parameters for shape (m, n, k): tuning database, then learned
-// model, then the plain rule.
-SmmParams select_params(int m, int n, int k);
+// Selected parameters for shape (m, n, k) in runs of about run_len products
+// per C block: tuning database, then learned model, then the plain rule.
+SmmParams select_params(int m, int n, int k, int run_len);
 // Legal candidate parameter sets of a shape (the tuning space).
 std::vector<SmmParams> candidate_params(int m, int n, int k);
 // Learned model: ranks the candidates of (m, n, k) by predicted time; false
 // when no model is loaded.
-bool mlp_select(int m, int n, int k, SmmParams *out);
+bool mlp_select(int m, int n, int k, int run_len, SmmParams *out);
 // Plans and launches the stack kernels; the launches (and the instantiated
 // graph of the tuned path) are kept in *ex for replay.
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,

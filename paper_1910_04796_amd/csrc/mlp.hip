@@ -165,8 +165,9 @@ int forward(int F, const float *dP, int64_t n, const float *dX, const int64_t *p
 // log2 m, log2 n, log2 k, TM, TN, log2 of the effective k chunk, waves per
 // workgroup (0 = as many as fit -> 4), log2 of the lanes (or MFMA tiles)
 // holding tiles, the fraction of the tiles that covers the block (times the
-// k fill of 4-deep steps for the MFMA kernel), and 1 for the MFMA kernel.
-int mlp_features(int m, int n, int k, const SmmParams &p, float *f) {
+// k fill of 4-deep steps for the MFMA kernel), 1 for the MFMA kernel, and
+// log2 of the run length (products per C block).
+int mlp_features(int m, int n, int k, int run_len, const SmmParams &p, float *f) {
     const bool mfma = p.tm == kMfmaTile && p.tn == kMfmaTile;
     const int kc = (!mfma && p.kc > 0 && p.kc < k) ? p.kc : k;
     const double lanes = (double)ceil_div(m, p.tm) * (double)ceil_div(n, p.tn);
@@ -182,6 +183,7 @@ int mlp_features(int m, int n, int k, const SmmParams &p, float *f) {
     f[7] = (float)std::log2(lanes);
     f[8] = (float)cover;
     f[9] = mfma ? 1.0f : 0.0f;
+    f[10] = (float)std::log2((double)std::max(run_len, 1));
     return kMlpFeatures;
 }
 
@@ -191,7 +193,7 @@ struct Model {
     std::string path;
     int F = 0;
     std::vector<float> mean, stdev, params;
-    std::map<std::tuple<int, int, int>, SmmParams> cache;
+    std::map<std::tuple<int, int, int, int>, SmmParams> cache;
 };
 std::mutex g_mlp_mu;
 Model g_model;
@@ -225,12 +227,12 @@ bool load_model_locked(const std::string &path) {
 }
 }  // namespace
 
-bool mlp_select(int m, int n, int k, SmmParams *out) {
+bool mlp_select(int m, int n, int k, int run_len, SmmParams *out) {
     std::lock_guard<std::mutex> lk(g_mlp_mu);
     const std::string &want = options().mlp_weights;
     if (!g_model.loaded || g_model.path != want) load_model_locked(want);
     if (g_model.params.empty()) return false;
-    auto it = g_model.cache.find({m, n, k});
+    auto it = g_model.cache.find({m, n, k, run_len});
     if (it != g_model.cache.end()) {
         *out = it->second;
         return true;
@@ -242,7 +244,7 @@ bool mlp_select(int m, int n, int k, SmmParams *out) {
     std::vector<float> X(cands.size() * F), Y(cands.size());
     float tmp[kMaxF];
     for (size_t c = 0; c < cands.size(); ++c) {
-        mlp_features(m, n, k, cands[c], tmp);
+        mlp_features(m, n, k, run_len, cands[c], tmp);
         for (int f = 0; f < F; ++f) X[c * F + f] = (tmp[f] - g_model.mean[f]) / g_model.stdev[f];
     }
     // Inference on the device, on the null stream, outside any caller stream.
@@ -257,7 +259,7 @@ bool mlp_select(int m, int n, int k, SmmParams *out) {
         return false;
     }
     const size_t best = (size_t)(std::min_element(Y.begin(), Y.end()) - Y.begin());
-    g_model.cache[{m, n, k}] = cands[best];
+    g_model.cache[{m, n, k, run_len}] = cands[best];
     *out = cands[best];
     return true;
 }
@@ -277,15 +279,16 @@ extern "C" int bsmm_mlp_param_count(int32_t n_features, int64_t *count) {
     return BSMM_OK;
 }
 
-extern "C" int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, const int32_t *params4,
-                                 float *features, int32_t *n_features) {
+extern "C" int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, int32_t run_len,
+                                 const int32_t *params4, float *features, int32_t *n_features) {
     clear_error();
-    if (!params4 || !features || m < 1 || n < 1 || k < 1 || params4[0] < 1 || params4[1] < 1) {
+    if (!params4 || !features || m < 1 || n < 1 || k < 1 || run_len < 1 || params4[0] < 1 ||
+        params4[1] < 1) {
         set_error(BSMM_EINVAL, "bad arguments");
         return BSMM_EINVAL;
     }
-    const int F = mlp_features(m, n, k, SmmParams{params4[0], params4[1], params4[2], params4[3]},
-                               features);
+    const int F = mlp_features(m, n, k, run_len,
+                               SmmParams{params4[0], params4[1], params4[2], params4[3]}, features);
     if (n_features) *n_features = F;
     return BSMM_OK;
 }

@@ -9,6 +9,7 @@
 //      products grouped by shape -> batched small-block kernels;
 //   3. filter.
 #include <algorithm>
+#include <cstdio>
 
 #include "dev_util.h"
 #include "internal.h"
@@ -140,12 +141,18 @@ int install_pattern(bsmm_matrix_s *C, const SymbolicTotals &tot, NewPattern &np,
     return BSMM_OK;
 }
 
+int active_classes(const Stacks &st) {
+    int nc = 0;
+    for (char a : st.class_active) nc += a != 0;
+    return nc;
+}
+
 // Options that change what a plan computes.
 std::string plan_key(const Options &o) {
     char buf[128];
-    snprintf(buf, sizeof buf, "%d %d %lld %d %d %d %d %d|", o.path, o.stack_kernel,
-             (long long)o.stack_chunk, o.emul_slices, o.forced[0], o.forced[1], o.forced[2],
-             o.forced[3]);
+    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d|", o.path, o.stack_kernel,
+             (long long)o.stack_chunk, (long long)o.stack_panel, o.emul_slices, o.forced[0],
+             o.forced[1], o.forced[2], o.forced[3]);
     return std::string(buf) + o.tune_db + "|" + o.mlp_weights;
 }
 
@@ -167,8 +174,41 @@ void free_plan(Plan *p) { delete p; }
 
 namespace {
 
+// Stack path over panels of consecutive C block rows whose products fit
+// the stack buffers (option "stack_panel"); each panel's stacks are built,
+// executed and then replaced by the next panel's, in stream order.
+int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, double alpha,
+                     double beta, int64_t cap, Stacks &st, int64_t *n_panels, hipStream_t s) {
+    std::vector<int64_t> pb, cb;
+    BSMM_TRY(stack_row_bounds(C, st, &pb, &cb, s));
+    int64_t runs = 0;
+    for (int32_t r0 = 0; r0 < C->nbr;) {
+        int32_t r1 = r0 + 1;
+        while (r1 < C->nbr && pb[r1 + 1] - pb[r0] <= cap) ++r1;
+        if (pb[r1] > pb[r0]) {
+            BSMM_TRY(stack_rows(A, B, C, st, r0, r1, cb[r0], cb[r1], pb[r1] - pb[r0], s));
+            StackExec ex;  // a graph is retired only after its launch has completed
+            BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s, &ex));
+            runs += st.n_runs;
+            ++*n_panels;
+            if (options().verbose) {
+                // Host progress of a long multiply (the panel is queued, not finished).
+                fprintf(stderr, "[bsmm] stack panel %lld: block rows %d..%d of %d, %lld products\n",
+                        (long long)*n_panels, r0, r1 - 1, C->nbr, (long long)(pb[r1] - pb[r0]));
+                fflush(stderr);
+            }
+        }
+        r0 = r1;
+    }
+    st.n_runs = runs;
+    st.n_prod = pb[C->nbr];
+    return BSMM_OK;
+}
+
 int numeric(int path, bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, double alpha,
-            double beta, const Options &o, Stacks &st, StackExec &ex, bool replay, hipStream_t s) {
+            double beta, const Options &o, Stacks &st, StackExec &ex, bool replay,
+            int64_t *n_panels, hipStream_t s) {
+    *n_panels = 0;
     switch (path) {
     case 0:
         if (beta != 1.0) BSMM_TRY(scale_blocks(C, nullptr, beta, s));
@@ -178,10 +218,16 @@ int numeric(int path, bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doub
     case 2:
         return dense_multiply(A, B, C, alpha, beta, s);
     default:
-        if (replay) BSMM_TRY(replay_stacks(ex, A, B, C, st, alpha, beta, s));
-        else {
+        if (replay) {
+            BSMM_TRY(replay_stacks(ex, A, B, C, st, alpha, beta, s));
+            *n_panels = 1;
+        } else if (o.stack_panel > 0 && st.n_prod > o.stack_panel) {
+            BSMM_TRY(stack_count(A, B, C, st, s));
+            BSMM_TRY(stacks_by_panels(A, B, C, alpha, beta, o.stack_panel, st, n_panels, s));
+        } else {
             BSMM_TRY(build_stacks(A, B, C, st, s));
             BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s, &ex));
+            *n_panels = 1;
         }
         if (beta != 1.0 && st.n_runs < C->nnzb)
             BSMM_TRY(scale_blocks(C, st.c_count.as<int64_t>(), beta, s));
@@ -201,16 +247,14 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
     if (hit) {
         // Same patterns, buffers and options as the planned multiply: C's
         // pattern already holds the product, the stacks are still valid.
-        BSMM_TRY(numeric(pl->path, A, B, C, alpha, beta, o, pl->st, pl->ex, true, s));
+        BSMM_TRY(numeric(pl->path, A, B, C, alpha, beta, o, pl->st, pl->ex, true,
+                         &stt.n_row_panels, s));
         stt.path = pl->path;
         stt.c_nnzb_before = C->nnzb;
         stt.n_products = pl->tot.nprod;
         stt.flops = pl->tot.flops;
         stt.n_runs = pl->st.n_runs;
-        int nc = 0;
-        for (int cl = 0; cl < pl->st.n_classes; ++cl)
-            nc += pl->st.class_begin[cl + 1] > pl->st.class_begin[cl];
-        stt.n_classes = nc;
+        stt.n_classes = active_classes(pl->st);
     } else {
         free_plan(C->plan);
         C->plan = nullptr;
@@ -227,17 +271,17 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         const int path = (alpha == 0.0 || tot.nprod == 0) ? 0 : o.path == 3 ? 3 : dense ? 2 : 1;
         auto *p = new Plan();
         p->st.n_prod = tot.nprod;
-        const int status = numeric(path, A, B, C, alpha, beta, o, p->st, p->ex, false, s);
+        const int status = numeric(path, A, B, C, alpha, beta, o, p->st, p->ex, false,
+                                   &stt.n_row_panels, s);
         if (status != BSMM_OK) {
             delete p;
             return status;
         }
         stt.path = path;
         stt.n_runs = p->st.n_runs;
-        int nc = 0;
-        for (int cl = 0; cl < p->st.n_classes; ++cl) nc += p->st.class_begin[cl + 1] > p->st.class_begin[cl];
-        stt.n_classes = nc;
-        if (o.plan_cache) {
+        stt.n_classes = active_classes(p->st);
+        // A multiply built in several row panels keeps no stacks to replay.
+        if (o.plan_cache && stt.n_row_panels <= 1) {
             p->A = A;
             p->B = B;
             p->va = A->version;

@@ -9,8 +9,10 @@
 //     of one shape (the exhaustive tuner; its driver writes the database);
 //   * select_params looks a shape up in the database, then asks the learned
 //     model (mlp.hip) to rank the legal candidates, then falls back to the
-//     plain rule.
+//     plain rule.  Both are keyed by the run length (products per C block)
+//     as well as the shape: short and long runs favour different kernels.
 #include <algorithm>
+#include <cmath>
 #include <cstdlib>
 #include <fstream>
 #include <map>
@@ -26,8 +28,12 @@ namespace {
 std::mutex g_db_mu;
 std::string g_db_path;
 bool g_db_loaded = false;
-std::map<std::tuple<int, int, int>, SmmParams> g_db;
+// (m, n, k) -> run length -> best parameter set.
+std::map<std::tuple<int, int, int>, std::map<int, SmmParams>> g_db;
 
+// Database lines: "m n k R tm tn kc waves [best_us plain_us]" (eight or ten
+// fields; R = run length the set was timed at).  Lines without R ("m n k tm
+// tn kc waves [best_us plain_us]", seven or nine fields) count as R = 8.
 void load_db_locked(const std::string &path) {
     g_db.clear();
     g_db_path = path;
@@ -38,10 +44,37 @@ void load_db_locked(const std::string &path) {
     while (std::getline(f, line)) {
         if (line.empty() || line[0] == '#') continue;
         std::istringstream is(line);
-        int m, n, k;
+        std::vector<double> v;
+        double x;
+        while (is >> x) v.push_back(x);
         SmmParams p;
-        if (is >> m >> n >> k >> p.tm >> p.tn >> p.kc >> p.waves) g_db[{m, n, k}] = p;
+        int m, n, k, R;
+        if (v.size() == 10 || v.size() == 8) {
+            m = (int)v[0], n = (int)v[1], k = (int)v[2], R = (int)v[3];
+            p = SmmParams{(int)v[4], (int)v[5], (int)v[6], (int)v[7]};
+        } else if (v.size() == 9 || v.size() == 7) {
+            m = (int)v[0], n = (int)v[1], k = (int)v[2], R = 8;
+            p = SmmParams{(int)v[3], (int)v[4], (int)v[5], (int)v[6]};
+        } else {
+            continue;
+        }
+        if (R >= 1) g_db[{m, n, k}][R] = p;
     }
+}
+
+// Entry whose run length is nearest to R on a log scale (ties: the shorter).
+bool db_lookup_locked(int m, int n, int k, int R, SmmParams *out) {
+    auto it = g_db.find({m, n, k});
+    if (it == g_db.end() || it->second.empty()) return false;
+    double best = 1e300;
+    for (auto &e : it->second) {
+        const double d = std::fabs(std::log2((double)e.first) - std::log2((double)std::max(R, 1)));
+        if (d < best - 1e-12) {
+            best = d;
+            *out = e.second;
+        }
+    }
+    return true;
 }
 }  // namespace
 
@@ -68,25 +101,25 @@ std::vector<SmmParams> candidate_params(int m, int n, int k) {
                 for (int w : waves) out.push_back(SmmParams{tm, tn, kc, w});
             }
         }
-    // FP64 MFMA kernel (16 x 16 tiles, zero padding in registers) for blocks
-    // that fill at least half of a tile in both directions.
-    if (m >= 8 && n >= 8 && m <= 64 && n <= 64)
+    // FP64 MFMA kernel (16 x 16 tiles, zero padding in registers) for every
+    // block up to 64 x 64: even 5-sized blocks can gain on long runs.
+    if (m <= 64 && n <= 64)
         for (int w : waves) out.push_back(SmmParams{kMfmaTile, kMfmaTile, 0, w});
     return out;
 }
 
-SmmParams select_params(int m, int n, int k) {
+SmmParams select_params(int m, int n, int k, int run_len) {
     const Options &o = options();
     if (o.forced[0] > 0) return SmmParams{o.forced[0], o.forced[1], o.forced[2], o.forced[3]};
     {
         std::lock_guard<std::mutex> lk(g_db_mu);
         const std::string &want = options().tune_db;
         if (!g_db_loaded || want != g_db_path) load_db_locked(want);
-        auto it = g_db.find({m, n, k});
-        if (it != g_db.end()) return it->second;
+        SmmParams p;
+        if (db_lookup_locked(m, n, k, run_len, &p)) return p;
     }
     SmmParams p;
-    if (mlp_select(m, n, k, &p)) return p;
+    if (mlp_select(m, n, k, run_len, &p)) return p;
     return plain_params(m, n);
 }
 
@@ -211,13 +244,14 @@ extern "C" int bsmm_tune_candidates(int32_t m, int32_t n, int32_t k, int32_t *n_
     return BSMM_OK;
 }
 
-extern "C" int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t *params4) {
+extern "C" int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t run_len,
+                                  int32_t *params4) {
     clear_error();
-    if (!params4 || m < 1 || n < 1 || k < 1) {
+    if (!params4 || m < 1 || n < 1 || k < 1 || run_len < 1) {
         set_error(BSMM_EINVAL, "bad arguments");
         return BSMM_EINVAL;
     }
-    SmmParams p = select_params(m, n, k);
+    SmmParams p = select_params(m, n, k, run_len);
     params4[0] = p.tm;
     params4[1] = p.tn;
     params4[2] = p.kc;

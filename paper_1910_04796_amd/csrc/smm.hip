@@ -381,18 +381,53 @@ int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const i
     return launch_check("smm_valu");
 }
 
-// Most frequent k of the products of a class, as seen from A's block-column
-// sizes: the key under which tuned parameters are looked up.
+namespace {
+// out[i] = run_ptr[idx[i]]: products before the first run of each class.
+__global__ void k_gather_run_ptr(const int64_t *run_ptr, const int64_t *idx, int n, int64_t *out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = run_ptr[idx[i]];
+}
+}  // namespace
+
+// Average products per run of every class (tuned path: the run length is
+// part of the parameter lookup).
+static int class_run_lengths(const Stacks &st, hipStream_t s, std::vector<int> *out) {
+    const int n = st.n_classes + 1;
+    std::vector<int64_t> first(n);
+    DevBuf idx, val;
+    BSMM_TRY(idx.reserve(sizeof(int64_t) * n, s));
+    BSMM_TRY(val.reserve(sizeof(int64_t) * n, s));
+    BSMM_HIP(hipMemcpyAsync(idx.p, st.class_begin.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_gather_run_ptr, dim3(grid_of(n, 256)), dim3(256), 0, s,
+                       (const int64_t *)st.run_ptr.as<int64_t>(), (const int64_t *)idx.as<int64_t>(), n,
+                       val.as<int64_t>());
+    BSMM_TRY(launch_check("gather_run_ptr"));
+    BSMM_HIP(hipMemcpyAsync(first.data(), val.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    out->assign(st.n_classes, 1);
+    for (int cl = 0; cl < st.n_classes; ++cl) {
+        const int64_t runs = st.class_begin[cl + 1] - st.class_begin[cl];
+        if (runs > 0) (*out)[cl] = (int)std::max<int64_t>(1, (first[cl + 1] - first[cl] + runs / 2) / runs);
+    }
+    return BSMM_OK;
+}
+
+// The k under which tuned parameters are looked up: a run mixes the k of
+// A's block columns, and a product's work grows with k, so the key is the
+// block-column size k carrying the most work (count of columns of size k,
+// times k; ties: the smaller k).
 static int representative_k(const bsmm_matrix_s *A) {
     std::vector<int32_t> v = A->cbs;
     if (v.empty()) return 1;
     std::sort(v.begin(), v.end());
-    int best = v[0], bestc = 0;
+    int best = v[0];
+    int64_t bestw = 0;
     for (size_t i = 0; i < v.size();) {
         size_t j = i;
         while (j < v.size() && v[j] == v[i]) ++j;
-        if ((int)(j - i) > bestc) {
-            bestc = (int)(j - i);
+        const int64_t w = (int64_t)(j - i) * v[i];
+        if (w > bestw) {
+            bestw = w;
             best = v[i];
         }
         i = j;
@@ -415,12 +450,14 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                                 hipMemcpyDeviceToHost, s));
         BSMM_HIP(hipStreamSynchronize(s));
     }
+    std::vector<int> rlen;
+    if (tuned) BSMM_TRY(class_run_lengths(st, s, &rlen));
     LaunchList &launches = ex->launches;
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t rb = st.class_begin[cl], re = st.class_begin[cl + 1];
         if (re <= rb) continue;
         const int m = st.row_sizes[cl / st.ncs], n = st.col_sizes[cl % st.ncs];
-        SmmParams prm = tuned ? select_params(m, n, krep) : plain_params(m, n);
+        SmmParams prm = tuned ? select_params(m, n, krep, rlen[cl]) : plain_params(m, n);
         SmmLaunch L;
         BSMM_TRY(plan_smm(prm, m, n, kmax, &L));
         if (chunk <= 0) {

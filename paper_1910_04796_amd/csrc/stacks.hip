@@ -20,6 +20,10 @@
 //               wave-level ranking with ballots);
 //   3. offsets  scan of the product counts in run order;
 //   4. fill     products written per row, K ascending.
+// Phase 1 covers every C block row; phases 2-4 cover one panel of
+// consecutive C block rows, so a product count beyond what the stack
+// buffers may hold is built and executed panel by panel (the paper's
+// batches, at the granularity of block rows).
 #include <algorithm>
 
 #include "dev_util.h"
@@ -74,7 +78,7 @@ __device__ __forceinline__ int class_of(int64_t c, const int32_t *c_row, const i
 
 // One wave per tile of kTile C blocks: per-class counts of the blocks that
 // receive products, written class-major (hist[cl * ntiles + tile]).
-__global__ __launch_bounds__(256) void k_class_hist(int64_t nnzb, int64_t ntiles,
+__global__ __launch_bounds__(256) void k_class_hist(int64_t c_base, int64_t nnzb, int64_t ntiles,
                                                     const int64_t *c_count, const int32_t *c_row,
                                                     const int32_t *c_ci, const int32_t *rsi,
                                                     const int32_t *csi, int ncs, int ncl,
@@ -85,8 +89,8 @@ __global__ __launch_bounds__(256) void k_class_hist(int64_t nnzb, int64_t ntiles
     if (tile >= ntiles) return;
     for (int cl = lane_id(); cl < ncl; cl += kWave) cnt[cl] = 0;
     wave_lds_sync();
-    const int64_t end = std::min<int64_t>(nnzb, (tile + 1) * kTile);
-    for (int64_t c = tile * kTile + lane_id(); c < end; c += kWave)
+    const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
+    for (int64_t c = c_base + tile * kTile + lane_id(); c < end; c += kWave)
         if (c_count[c] > 0) atomicAdd(&cnt[class_of(c, c_row, c_ci, rsi, csi, ncs)], 1);
     wave_lds_sync();
     for (int cl = lane_id(); cl < ncl; cl += kWave) hist[(int64_t)cl * ntiles + tile] = cnt[cl];
@@ -94,7 +98,7 @@ __global__ __launch_bounds__(256) void k_class_hist(int64_t nnzb, int64_t ntiles
 
 // Stable scatter of the runs into class-major order.
 __global__ __launch_bounds__(256) void k_class_scatter(
-    int64_t nnzb, int64_t ntiles, const int64_t *c_count, const int32_t *c_row,
+    int64_t c_base, int64_t nnzb, int64_t ntiles, const int64_t *c_count, const int32_t *c_row,
     const int32_t *c_ci, const int64_t *c_blk_off, const int32_t *rsi, const int32_t *csi,
     int ncs, int ncl, const int64_t *hoff, int64_t *run_cblk, int32_t *run_class,
     int64_t *run_coff, int64_t *run_cnt, int64_t *run_of_c) {
@@ -104,8 +108,8 @@ __global__ __launch_bounds__(256) void k_class_scatter(
     if (tile >= ntiles) return;
     for (int cl = lane_id(); cl < ncl; cl += kWave) next[cl] = hoff[(int64_t)cl * ntiles + tile];
     wave_lds_sync();
-    const int64_t end = std::min<int64_t>(nnzb, (tile + 1) * kTile);
-    for (int64_t base = tile * kTile; base < end; base += kWave) {
+    const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
+    for (int64_t base = c_base + tile * kTile; base < end; base += kWave) {
         const int64_t c = base + lane_id();
         const bool inb = c < end;
         const int64_t cnt = inb ? c_count[c] : 0;
@@ -135,6 +139,12 @@ __global__ __launch_bounds__(256) void k_class_scatter(
 
 __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
+// out[r] = scan[rp[r]] for r = 0..nbr: products before each C block row.
+__global__ void k_gather_rows(const int64_t *scan, const int64_t *rp, int32_t nbr, int64_t *out) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r <= nbr) out[r] = scan[rp[r]];
+}
+
 __global__ void k_gather_class_begin(const int64_t *hoff, int64_t ntiles, int ncl, int64_t *out) {
     for (int cl = threadIdx.x; cl <= ncl; cl += blockDim.x) out[cl] = hoff[(int64_t)cl * ntiles];
 }
@@ -142,7 +152,7 @@ __global__ void k_gather_class_begin(const int64_t *hoff, int64_t ntiles, int nc
 // Products of one C block row, K ascending inside every run.  Within one K
 // every C slot is hit at most once, so the per-slot cursors need no atomics;
 // a barrier separates consecutive K.
-__global__ __launch_bounds__(256) void k_stack_fill(int32_t nbc, const int64_t *a_rp,
+__global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int32_t nbc, const int64_t *a_rp,
                                                     const int32_t *a_ci, const int64_t *a_off,
                                                     const int64_t *b_rp, const int32_t *b_ci,
                                                     const int64_t *b_off, const int32_t *kbs,
@@ -152,7 +162,7 @@ __global__ __launch_bounds__(256) void k_stack_fill(int32_t nbc, const int64_t *
     extern __shared__ int32_t lds[];
     int32_t *map = lds;
     int32_t *cur = lds + nbc;
-    const int32_t row = blockIdx.x;
+    const int32_t row = row0 + (int32_t)blockIdx.x;
     const int64_t p0 = c_rp[row];
     const int32_t len = (int32_t)(c_rp[row + 1] - p0);
     for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
@@ -191,9 +201,10 @@ static void size_classes(const std::vector<int32_t> &sizes, std::vector<int32_t>
                              distinct.begin());
 }
 
-// st.n_prod must hold the product count of the symbolic phase on entry.
-int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
-                 Stacks &st, hipStream_t s) {
+// Phase 1 for every C block row: products per C block, the size classes,
+// and the check that C's pattern holds every product block.
+int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                Stacks &st, hipStream_t s) {
     const int32_t nbr = C->nbr, nbc = C->nbc;
     const int64_t nnzb = C->nnzb;
     if (nbc > kMapMaxCols) {
@@ -212,79 +223,129 @@ int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matr
         return BSMM_ENOTSUP;
     }
     st.class_begin.assign(ncl + 1, 0);
+    st.class_active.assign(ncl, 0);
     st.n_runs = 0;
     if (nbr == 0 || nnzb == 0) return BSMM_OK;
 
-    DevBuf d_rsi, d_csi, c_row, missing, hist, hoff, run_cnt, run_of_c, cb;
-    const int64_t ntiles = ceil_div(nnzb, kTile);
-    BSMM_TRY(d_rsi.reserve(sizeof(int32_t) * nbr, s));
-    BSMM_TRY(d_csi.reserve(sizeof(int32_t) * nbc, s));
-    BSMM_TRY(c_row.reserve(sizeof(int32_t) * nnzb, s));
-    BSMM_TRY(missing.reserve(sizeof(int32_t), s));
-    BSMM_TRY(hist.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
-    BSMM_TRY(hoff.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
-    BSMM_TRY(run_cnt.reserve(sizeof(int64_t) * (nnzb + 1), s));
-    BSMM_TRY(run_of_c.reserve(sizeof(int64_t) * nnzb, s));
-    BSMM_TRY(cb.reserve(sizeof(int64_t) * (ncl + 1), s));
+    BSMM_TRY(st.d_rsi.reserve(sizeof(int32_t) * nbr, s));
+    BSMM_TRY(st.d_csi.reserve(sizeof(int32_t) * nbc, s));
+    BSMM_TRY(st.c_row.reserve(sizeof(int32_t) * nnzb, s));
     BSMM_TRY(st.c_count.reserve(sizeof(int64_t) * nnzb, s));
-    BSMM_TRY(st.run_cblk.reserve(sizeof(int64_t) * nnzb, s));
-    BSMM_TRY(st.run_coff.reserve(sizeof(int64_t) * nnzb, s));
-    BSMM_TRY(st.run_class.reserve(sizeof(int32_t) * nnzb, s));
-    BSMM_TRY(st.run_ptr.reserve(sizeof(int64_t) * (nnzb + 1), s));
-
-    BSMM_HIP(hipMemcpyAsync(d_rsi.p, rsi.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice, s));
-    BSMM_HIP(hipMemcpyAsync(d_csi.p, csi.data(), sizeof(int32_t) * nbc, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, missing.as<int32_t>());
+    BSMM_TRY(st.missing.reserve(sizeof(int32_t), s));
+    BSMM_HIP(hipMemcpyAsync(st.d_rsi.p, rsi.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice, s));
+    BSMM_HIP(hipMemcpyAsync(st.d_csi.p, csi.data(), sizeof(int32_t) * nbc, hipMemcpyHostToDevice, s));
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, st.missing.as<int32_t>());
     BSMM_TRY(launch_check("zero_i32"));
-
     const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
     hipLaunchKernelGGL(k_stack_count, dim3(nbr), dim3(256), map_lds, s, nbc, A->d_row_ptr(),
                        A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(), C->d_row_ptr(),
-                       C->d_col_ind(), st.c_count.as<int64_t>(), c_row.as<int32_t>(),
-                       missing.as<int32_t>());
-    BSMM_TRY(launch_check("stack_count"));
+                       C->d_col_ind(), st.c_count.as<int64_t>(), st.c_row.as<int32_t>(),
+                       st.missing.as<int32_t>());
+    return launch_check("stack_count");
+}
+
+// The flag of k_stack_count, read after a host synchronisation.
+static int check_missing(int32_t miss) {
+    if (!miss) return BSMM_OK;
+    set_error(BSMM_EINDEX, "C pattern does not contain every product block");
+    return BSMM_EINDEX;
+}
+
+int stack_row_bounds(const bsmm_matrix_s *C, const Stacks &st, std::vector<int64_t> *prod_before,
+                     std::vector<int64_t> *blk_before, hipStream_t s) {
+    const int32_t nbr = C->nbr;
+    prod_before->assign(nbr + 1, 0);
+    blk_before->assign(nbr + 1, 0);
+    if (nbr == 0 || C->nnzb == 0) return BSMM_OK;
+    DevBuf scan, out;
+    BSMM_TRY(scan.reserve(sizeof(int64_t) * (C->nnzb + 1), s));
+    BSMM_TRY(out.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(scan_exclusive_i64(st.c_count.as<int64_t>(), scan.as<int64_t>(), C->nnzb, s));
+    hipLaunchKernelGGL(k_gather_rows, dim3(grid_of(nbr + 1, 256)), dim3(256), 0, s,
+                       (const int64_t *)scan.as<int64_t>(), C->d_row_ptr(), nbr, out.as<int64_t>());
+    BSMM_TRY(launch_check("gather_rows"));
+    BSMM_HIP(hipMemcpyAsync(prod_before->data(), out.p, sizeof(int64_t) * (nbr + 1),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(blk_before->data(), C->d_row_ptr(), sizeof(int64_t) * (nbr + 1),
+                            hipMemcpyDeviceToHost, s));
+    int32_t miss = 0;
+    BSMM_HIP(hipMemcpyAsync(&miss, st.missing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    return check_missing(miss);
+}
+
+int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+               Stacks &st, int32_t r0, int32_t r1, int64_t c0, int64_t c1, int64_t nprod,
+               hipStream_t s) {
+    const int32_t nbc = C->nbc;
+    const int ncl = st.n_classes;
+    const int64_t nblk = c1 - c0;
+    st.class_begin.assign(ncl + 1, 0);
+    st.n_runs = 0;
+    st.n_prod = nprod;
+    if (r1 <= r0 || nblk <= 0) return BSMM_OK;
+
+    DevBuf hist, hoff, run_cnt, cb;
+    const int64_t ntiles = ceil_div(nblk, kTile);
+    BSMM_TRY(hist.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    BSMM_TRY(hoff.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    BSMM_TRY(run_cnt.reserve(sizeof(int64_t) * (nblk + 1), s));
+    BSMM_TRY(cb.reserve(sizeof(int64_t) * (ncl + 1), s));
+    BSMM_TRY(st.run_of_c.reserve(sizeof(int64_t) * C->nnzb, s));
+    BSMM_TRY(st.run_cblk.reserve(sizeof(int64_t) * nblk, s));
+    BSMM_TRY(st.run_coff.reserve(sizeof(int64_t) * nblk, s));
+    BSMM_TRY(st.run_class.reserve(sizeof(int32_t) * nblk, s));
+    BSMM_TRY(st.run_ptr.reserve(sizeof(int64_t) * (nblk + 1), s));
 
     const unsigned tgrid = grid_of(ntiles, 4);
-    hipLaunchKernelGGL(k_class_hist, dim3(tgrid), dim3(256), sizeof(int32_t) * 4 * ncl, s, nnzb,
-                       ntiles, (const int64_t *)st.c_count.as<int64_t>(),
-                       (const int32_t *)c_row.as<int32_t>(), C->d_col_ind(),
-                       (const int32_t *)d_rsi.as<int32_t>(), (const int32_t *)d_csi.as<int32_t>(),
-                       st.ncs, ncl, hist.as<int64_t>());
+    hipLaunchKernelGGL(k_class_hist, dim3(tgrid), dim3(256), sizeof(int32_t) * 4 * ncl, s, c0,
+                       nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
+                       (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(),
+                       (const int32_t *)st.d_rsi.as<int32_t>(),
+                       (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl, hist.as<int64_t>());
     BSMM_TRY(launch_check("class_hist"));
     BSMM_TRY(scan_exclusive_i64(hist.as<int64_t>(), hoff.as<int64_t>(), ncl * ntiles, s));
-    hipLaunchKernelGGL(k_class_scatter, dim3(tgrid), dim3(256), sizeof(int64_t) * 4 * ncl, s,
-                       nnzb, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
-                       (const int32_t *)c_row.as<int32_t>(), C->d_col_ind(), C->d_blk_off(),
-                       (const int32_t *)d_rsi.as<int32_t>(), (const int32_t *)d_csi.as<int32_t>(),
-                       st.ncs, ncl, (const int64_t *)hoff.as<int64_t>(), st.run_cblk.as<int64_t>(),
+    hipLaunchKernelGGL(k_class_scatter, dim3(tgrid), dim3(256), sizeof(int64_t) * 4 * ncl, s, c0,
+                       nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
+                       (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(), C->d_blk_off(),
+                       (const int32_t *)st.d_rsi.as<int32_t>(),
+                       (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl,
+                       (const int64_t *)hoff.as<int64_t>(), st.run_cblk.as<int64_t>(),
                        st.run_class.as<int32_t>(), st.run_coff.as<int64_t>(),
-                       run_cnt.as<int64_t>(), run_of_c.as<int64_t>());
+                       run_cnt.as<int64_t>(), st.run_of_c.as<int64_t>());
     BSMM_TRY(launch_check("class_scatter"));
     hipLaunchKernelGGL(k_gather_class_begin, dim3(1), dim3(256), 0, s,
                        (const int64_t *)hoff.as<int64_t>(), ntiles, ncl, cb.as<int64_t>());
     BSMM_TRY(launch_check("gather_class_begin"));
-
     int32_t miss = 0;
     BSMM_HIP(hipMemcpyAsync(st.class_begin.data(), cb.p, sizeof(int64_t) * (ncl + 1),
                             hipMemcpyDeviceToHost, s));
-    BSMM_HIP(hipMemcpyAsync(&miss, missing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(&miss, st.missing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BSMM_HIP(hipStreamSynchronize(s));
-    if (miss) {
-        set_error(BSMM_EINDEX, "C pattern does not contain every product block");
-        return BSMM_EINDEX;
-    }
+    BSMM_TRY(check_missing(miss));
     st.n_runs = st.class_begin[ncl];
+    for (int cl = 0; cl < ncl; ++cl)
+        if (st.class_begin[cl + 1] > st.class_begin[cl]) st.class_active[cl] = 1;
     BSMM_TRY(scan_exclusive_i64(run_cnt.as<int64_t>(), st.run_ptr.as<int64_t>(), st.n_runs, s));
-    if (st.n_prod > 0) {
-        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * st.n_prod, s));
-        hipLaunchKernelGGL(k_stack_fill, dim3(nbr), dim3(256), map_lds, s, nbc, A->d_row_ptr(),
-                           A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(), B->d_col_ind(),
-                           B->d_blk_off(), B->d_rbs(), C->d_row_ptr(), C->d_col_ind(),
-                           (const int64_t *)run_of_c.as<int64_t>(),
+    if (nprod > 0) {
+        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
+        const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
+        hipLaunchKernelGGL(k_stack_fill, dim3(r1 - r0), dim3(256), map_lds, s, r0, nbc,
+                           A->d_row_ptr(), A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(),
+                           B->d_col_ind(), B->d_blk_off(), B->d_rbs(), C->d_row_ptr(),
+                           C->d_col_ind(), (const int64_t *)st.run_of_c.as<int64_t>(),
                            (const int64_t *)st.run_ptr.as<int64_t>(), st.prods.as<ulonglong2>());
         BSMM_TRY(launch_check("stack_fill"));
     }
     return BSMM_OK;
+}
+
+// st.n_prod must hold the product count of the symbolic phase on entry.
+int build_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                 Stacks &st, hipStream_t s) {
+    const int64_t nprod = st.n_prod;
+    BSMM_TRY(stack_count(A, B, C, st, s));
+    return stack_rows(A, B, C, st, 0, C->nbr, 0, C->nnzb, nprod, s);
 }
 
 }  // namespace bsmm

@@ -32,11 +32,15 @@ def read_table(path):
     return rows
 
 
+# Timing table columns: m, n, k, R (run length), tm, tn, kc, waves, us.
+T_US = 8
+
+
 def features(rows):
     from . import bsmm
     out = None
     for i, r in enumerate(rows):
-        f = bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[3:7].astype(np.int32))
+        f = bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[4:8].astype(np.int32), int(r[3]))
         if out is None:
             out = np.zeros((len(rows), len(f)), np.float32)
         out[i] = f
@@ -52,31 +56,33 @@ def holdout_split(shapes, count, seed):
 
 
 def read_plain(db_path):
-    """Plain-rule timings (last column) of a tuning database, by shape."""
+    """Plain-rule timings (last column) of a tuning database, by (m, n, k, R)."""
     plain = {}
     for line in open(db_path):
         if line.strip() and not line.startswith("#"):
             f = line.split()
-            if len(f) >= 9:
-                plain[(int(f[0]), int(f[1]), int(f[2]))] = float(f[8])
+            if len(f) == 10:
+                plain[(int(f[0]), int(f[1]), int(f[2]), int(f[3]))] = float(f[9])
     return plain
 
 
 def evaluate(rows, held, pred, plain):
-    """Per held-out shape: exhaustive best / time of the model's first pick,
-    and plain-rule time / time of the pick (shapes with a plain timing)."""
-    key = [(int(r[0]), int(r[1]), int(r[2])) for r in rows]
-    by_shape = {}
+    """Per held-out shape and run length: exhaustive best / time of the
+    model's first pick, and plain-rule time / time of the pick."""
+    key = [(int(r[0]), int(r[1]), int(r[2]), int(r[3])) for r in rows]
+    by_case = {}
     for i, k in enumerate(key):
-        by_shape.setdefault(k, []).append(i)
+        by_case.setdefault(k, []).append(i)
     ratios, speedups = [], []
-    for s in sorted(held):
-        idx = np.array(by_shape[s])
-        times = rows[idx, 7]
+    for c in sorted(by_case):
+        if c[:3] not in held:
+            continue
+        idx = np.array(by_case[c])
+        times = rows[idx, T_US]
         pick = times[int(np.argmin(pred[idx]))]
         ratios.append(times.min() / pick)
-        if s in plain:
-            speedups.append(plain[s] / pick)
+        if c in plain:
+            speedups.append(plain[c] / pick)
     return np.array(ratios), np.array(speedups)
 
 
@@ -120,7 +126,7 @@ def main():
     held = holdout_split(shapes, args.holdout, args.seed)
     is_held = np.array([(int(r[0]), int(r[1]), int(r[2])) in held for r in rows])
     X = features(rows)
-    y = np.log(rows[:, 7]).astype(np.float32)
+    y = np.log(rows[:, T_US]).astype(np.float32)
     tr = ~is_held
     mean = X[tr].mean(axis=0)
     sd = X[tr].std(axis=0)
@@ -139,6 +145,7 @@ def main():
     ratios, speedups = evaluate(rows, held, pred, plain)
     write_weights(args.out, mean, sd, P)
     rep = {"shapes": len(shapes), "held_out": len(held), "train_rows": int(tr.sum()),
+           "run_lengths": sorted({int(r[3]) for r in rows}), "heldout_cases": int(len(ratios)),
            "train_seconds": round(train_s, 2), "train_mse": round(float(loss), 5),
            "epochs": args.epochs, "batch": args.batch, "lr": args.lr, "seed": args.seed,
            "heldout_best_over_pick": {"mean": round(float(ratios.mean()), 4),

@@ -61,12 +61,15 @@ def test_options_round_trip():
                  ("emul_slices", "5"), ("emul_slices", "7"), ("plan_cache", "1"), ("plan_cache", "0"),
                  ("stack_kernel", "tuned"),
                  ("stack_kernel", "plain"), ("stack_chunk", "30000"), ("stack_chunk", "0"),
+                 ("stack_panel", "1000"), ("stack_panel", "0"), ("stack_panel", "1073741824"),
                  ("emul_kernel", "t64"), ("emul_kernel", "t128"), ("emul_kernel", "t128w8"), ("emul_kernel", "t128k32"), ("dense_kb", "32"), ("dense_kb", "16")]:
         b.bsmm_set_option(k, v)
         assert b.bsmm_get_option(k) == v
     assert _err(b.bsmm_set_option, "path", "sideways") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "nope", "1") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "stack_chunk", "-4") == b.BSMM_EINVAL
+    assert _err(b.bsmm_set_option, "stack_panel", "-1") == b.BSMM_EINVAL
+    assert _err(b.bsmm_set_option, "stack_panel", "1e9") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "emul_kernel", "t96") == b.BSMM_EINVAL
 
 
@@ -74,3 +77,49 @@ def test_last_error_is_set():
     from paper_1910_04796_amd import bsmm as b
     _err(b.bsmm_set_option, "nope", "1")
     assert "nope" in b.bsmm_last_error()
+
+
+def test_tuning_database_lookup_by_run_length(tmp_path):
+    """Parameter selection from a database file is host work: the entry of a
+    shape is the one whose run length is nearest on a log scale, a line
+    without a run length counts as R = 8, and absent shapes take the plain
+    rule."""
+    from paper_1910_04796_amd import bsmm as b
+    db = tmp_path / "db.txt"
+    db.write_text("# m n k R tm tn kc waves best plain\n"
+                  "23 23 23 1 4 4 8 1 1.0 2.0\n"
+                  "23 23 23 16 16 16 0 4 1.0 2.0\n"
+                  "5 5 5 1 2 4 1\n")
+    saved = {o: b.bsmm_get_option(o) for o in ("tune_db", "mlp_weights")}
+    b.bsmm_set_option("mlp_weights", "")
+    b.bsmm_set_option("tune_db", "")
+    plain = b.bsmm_select_params(23, 23, 23, 8)
+    b.bsmm_set_option("tune_db", str(db))
+    try:
+        assert b.bsmm_select_params(23, 23, 23, 1) == (4, 4, 8, 1)
+        assert b.bsmm_select_params(23, 23, 23, 3) == (4, 4, 8, 1)   # log2 3 < 2
+        assert b.bsmm_select_params(23, 23, 23, 5) == (16, 16, 0, 4)  # log2 5 > 2
+        assert b.bsmm_select_params(23, 23, 23, 1000) == (16, 16, 0, 4)
+        assert b.bsmm_select_params(5, 5, 5, 64) == (1, 2, 4, 1)
+        assert b.bsmm_select_params(13, 13, 13, 8) == b.bsmm_select_params(13, 13, 13, 1)
+        assert _err(b.bsmm_select_params, 23, 23, 23, 0) == b.BSMM_EINVAL
+        b.bsmm_set_option("tune_db", "")
+        assert b.bsmm_select_params(23, 23, 23, 8) == plain
+    finally:
+        for o, v in saved.items():
+            b.bsmm_set_option(o, v)
+
+
+def test_model_features_of_run_length():
+    """The learned model's feature vector is host work; only the last
+    feature, log2 of the run length, depends on the run length."""
+    from paper_1910_04796_amd import bsmm as b
+    p = np.array([16, 16, 0, 4], np.int32)
+    f1, f8, f64 = (b.bsmm_mlp_features(23, 13, 7, p, R) for R in (1, 8, 64))
+    assert len(f1) == 11
+    assert np.array_equal(f1[:-1], f8[:-1]) and np.array_equal(f1[:-1], f64[:-1])
+    assert (f1[-1], f8[-1], f64[-1]) == (0.0, 3.0, 6.0)
+    assert f1[9] == 1.0  # matrix-core set
+    assert b.bsmm_mlp_features(23, 13, 7, np.array([2, 2, 0, 0], np.int32), 8)[9] == 0.0
+    # lanes cover m x n; the matrix-core tile also pads k to a multiple of 4
+    assert np.isclose(f1[8], (23 * 13) / (2 * 1 * 256) * 7 / 8)

@@ -84,13 +84,14 @@ def test_model_selection_uses_argmin(tmp_path):
         f.write(f"params {len(P)}\n" + " ".join(repr(float(x)) for x in P) + "\n")
     m, n, k = 17, 29, 11
     cands = b.bsmm_tune_candidates(m, n, k)
-    X = np.stack([b.bsmm_mlp_features(m, n, k, c) for c in cands])
-    y, _ = ref.forward(P, X)
-    want = tuple(int(x) for x in cands[int(np.argmin(y))])
     b.bsmm_set_option("tune_db", "")
     b.bsmm_set_option("mlp_weights", str(path))
     try:
-        assert b.bsmm_select_params(m, n, k) == want
+        for R in (1, 8, 27):
+            X = np.stack([b.bsmm_mlp_features(m, n, k, c, R) for c in cands])
+            y, _ = ref.forward(P, X)
+            want = tuple(int(x) for x in cands[int(np.argmin(y))])
+            assert b.bsmm_select_params(m, n, k, R) == want, R
     finally:
         b.bsmm_set_option("mlp_weights", "")
 

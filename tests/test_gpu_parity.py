@@ -261,6 +261,63 @@ def test_stack_chunk_bitwise():
         assert np.array_equal(X.data, ref.data)
 
 
+@pytest.mark.parametrize("kernel", ["plain", "tuned"])
+@pytest.mark.parametrize("panel", [1, 397, 1500])
+def test_stack_row_panels(kernel, panel):
+    """Stacks built and run over panels of C block rows (a cap on the
+    products held at once) give the same bits as whole stacks: every C
+    block is updated by one run in one panel, in the same product order.
+    A cap of 1 puts every block row in a panel of its own; beta != 0 into an
+    existing C and the filter run after the last panel."""
+    b = lib()
+    A, B = banded_uneven(seed=41, occupancy=0.15, target=1100)
+    rng = rng_of(42)
+    Cin = make_matrix(rng, A.rbs, B.cbs, 0.2)
+    ref, st0 = gpu_multiply(0.75, A, B, -0.5, Cin, eps=1e-3, kernel=kernel)
+    assert st0["n_row_panels"] == 1
+    b.bsmm_set_option("stack_panel", str(panel))
+    try:
+        X, st = gpu_multiply(0.75, A, B, -0.5, Cin, eps=1e-3, kernel=kernel)
+    finally:
+        b.bsmm_set_option("stack_panel", "1073741824")
+    assert st["n_products"] == st0["n_products"] and st["n_runs"] == st0["n_runs"]
+    assert st["n_classes"] == st0["n_classes"]
+    brp, arp = np.asarray(B.row_ptr), np.asarray(A.row_ptr)
+    busy = sum(any(brp[k + 1] > brp[k] for k in np.asarray(A.col_ind)[arp[i]:arp[i + 1]])
+               for i in range(len(A.rbs)))
+    if panel == 1:
+        assert st["n_row_panels"] == busy
+    else:
+        assert st["n_row_panels"] >= -(-st0["n_products"] // panel) > 1
+    check_against_oracle(X, ref, 0.0)
+    R = orc.multiply(0.75, A, B, -0.5, Cin, filter_eps=1e-3)
+    check_against_oracle(X, R, TOL)
+
+
+def test_stack_row_panels_no_plan_reuse():
+    """A multiply built in row panels keeps no plan: with the plan cache on,
+    repeated multiplies into one C still give beta*C + alpha*A*B."""
+    b = lib()
+    A, B = banded_uneven(seed=43, occupancy=0.2, target=700)
+    b.bsmm_set_option("stack_panel", "3000")
+    b.bsmm_set_option("plan_cache", "1")
+    set_path("stack", "tuned")
+    try:
+        MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
+        MC = b.Matrix.empty(A.rbs, B.cbs)
+        for beta in (0.0, 0.5, 0.5):
+            b.multiply(1.0, MA, MB, beta, MC)
+            assert b.bsmm_last_stats()["n_row_panels"] > 1
+        X = MC.to_host()
+        for M in (MA, MB, MC):
+            M.close()
+    finally:
+        b.bsmm_set_option("stack_panel", "1073741824")
+        b.bsmm_set_option("plan_cache", "0")
+        set_path()
+    check_against_oracle(X, orc.multiply(1.75, A, B, 0.0), TOL)
+
+
 def test_run_to_run_deterministic():
     A, B = banded_uneven(seed=6, occupancy=0.3, target=800)
     X1, _ = gpu_multiply(1.0, A, B, 0.0)

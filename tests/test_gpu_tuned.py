@@ -93,13 +93,18 @@ def test_tuned_graph_uneven(occ):
 def test_tuned_with_database(tmp_path):
     b = lib()
     db = tmp_path / "db.txt"
-    db.write_text("# m n k tm tn kc waves us\n23 23 23 2 8 8 2 1.0\n5 5 5 1 2 4 1 1.0\n")
+    db.write_text("# m n k R tm tn kc waves best plain\n23 23 23 8 2 8 8 2 1.0 2.0\n"
+                  "23 23 23 64 16 16 0 4 1.0 2.0\n5 5 5 1 2 4 1\n")
     saved = b.bsmm_get_option("mlp_weights")
     b.bsmm_set_option("tune_db", str(db))
     b.bsmm_set_option("mlp_weights", "")  # a miss then falls through to the plain rule
     try:
-        assert b.bsmm_select_params(23, 23, 23) == (2, 8, 8, 2)
-        assert b.bsmm_select_params(5, 5, 5) == (1, 2, 4, 1)
+        # nearest run length on a log scale; a line without R counts as R = 8
+        assert b.bsmm_select_params(23, 23, 23, 8) == (2, 8, 8, 2)
+        assert b.bsmm_select_params(23, 23, 23, 1) == (2, 8, 8, 2)
+        assert b.bsmm_select_params(23, 23, 23, 30) == (16, 16, 0, 4)
+        assert b.bsmm_select_params(23, 23, 23, 256) == (16, 16, 0, 4)
+        assert b.bsmm_select_params(5, 5, 5, 3) == (1, 2, 4, 1)
         assert b.bsmm_select_params(13, 13, 13) == (2, 2, 0, 0)  # plain rule
         rng = rng_of(4)
         s = np.full(9, 23, np.int32)
@@ -130,10 +135,13 @@ def test_committed_database_beats_plain():
     rows = [l.split() for l in open(DEFAULT_DB) if l.strip() and not l.startswith("#")]
     for r in rows[:: max(1, len(rows) // 8)]:
         m, n, k = (int(x) for x in r[:3])
-        best = [int(x) for x in r[3:7]]
+        # "m n k R tm tn kc waves best plain", or the older "m n k tm tn kc waves ..."
+        R, p = (int(r[3]), 4) if len(r) == 10 else (8, 3)
+        best = [int(x) for x in r[p:p + 4]]
         b.bsmm_set_option("tune_db", "")
-        plain = list(b.bsmm_select_params(m, n, k))
-        us = b.bsmm_tune_shape(m, n, k, np.array([best, plain, best, plain], np.int32), reps=5)
+        plain = list(b.bsmm_select_params(m, n, k, R))
+        us = b.bsmm_tune_shape(m, n, k, np.array([best, plain, best, plain], np.int32),
+                               n_runs=max(30000 // R, 3750), run_len=R, reps=5)
         assert min(us[0], us[2]) <= 1.10 * min(us[1], us[3]), (m, n, k, best, plain, us.tolist())
 
 

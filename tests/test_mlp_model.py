@@ -2,9 +2,9 @@
 a model trained on part of the tuning data predicts the kernel parameters of
 every other shape).
 
-The tuner's timing table over 600 random shapes, the weights trained on the
-GPU from 500 of them, and the report of the evaluation on the other 100 are
-committed together.  These CPU tests recompute that evaluation from the table
+The tuner's timing table over 600 random shapes (each at several run
+lengths), the weights trained on the GPU from 500 of them, and the report of
+the evaluation on the other 100 are committed together.  These CPU tests recompute that evaluation from the table
 and the weights with the numpy forward pass of the model, so the reported
 figures follow from committed data and not from the GPU run alone.
 """
@@ -46,7 +46,7 @@ def heldout():
     held = learn.holdout_split(shapes, rep["held_out"], rep["seed"])
     sel = np.array([(int(r[0]), int(r[1]), int(r[2])) in held for r in rows])
     hrows = rows[sel]
-    X = np.stack([bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[3:7].astype(np.int32))
+    X = np.stack([bsmm.bsmm_mlp_features(int(r[0]), int(r[1]), int(r[2]), r[4:8].astype(np.int32), int(r[3]))
                   for r in hrows])
     mean, sd, P = read_weights(WEIGHTS)
     Xn = ((X - mean) / sd).astype(np.float32)
@@ -61,7 +61,8 @@ def test_table_covers_the_shapes(heldout):
     assert len(held) == rep["held_out"] == 100
     assert len(rows) - len(hrows) == rep["train_rows"]
     assert all(4 <= v <= 64 for s in shapes for v in s)
-    assert (rows[:, 7] > 0).all()
+    assert (rows[:, learn.T_US] > 0).all()
+    assert sorted({int(r[3]) for r in rows}) == rep["run_lengths"]
 
 
 def test_heldout_evaluation_reproduces_report(heldout):
@@ -70,7 +71,8 @@ def test_heldout_evaluation_reproduces_report(heldout):
     differently, hence the small tolerance)."""
     learn, rows, hrows, held, pred, rep = heldout
     ratios, speedups = learn.evaluate(hrows, held, pred, learn.read_plain(RANDOM_DB))
-    assert len(ratios) == 100 and len(speedups) == 100
+    n_cases = 100 * len(rep["run_lengths"])
+    assert len(ratios) == n_cases == rep["heldout_cases"] and len(speedups) == n_cases
     assert (ratios <= 1.0).all() and (ratios > 0).all()
     r = rep["heldout_best_over_pick"]
     assert abs(ratios.mean() - r["mean"]) < 0.01
@@ -89,8 +91,8 @@ def test_model_beats_random_choice(heldout):
     learn, rows, hrows, held, pred, rep = heldout
     ratios, _ = learn.evaluate(hrows, held, pred, {})
     rand = []
-    key = [(int(r[0]), int(r[1]), int(r[2])) for r in hrows]
-    for s in sorted(held):
-        t = hrows[[i for i, k in enumerate(key) if k == s], 7]
+    key = [(int(r[0]), int(r[1]), int(r[2]), int(r[3])) for r in hrows]
+    for c in sorted(set(key)):
+        t = hrows[[i for i, k in enumerate(key) if k == c], learn.T_US]
         rand.append(np.mean(t.min() / t))
     assert ratios.mean() > np.mean(rand) + 0.1

@@ -246,6 +246,31 @@ def test_sampled_rows_match_full():
     assert np.array_equal(part.data, full.data[e0:e0 + len(part.data)])
 
 
+def test_pattern_of_row_range_matches_full():
+    """The pattern restricted to a row range (with an old C, beta != 0) is
+    that range of the full pattern and empty elsewhere; the multiply of the
+    range agrees with the full multiply, also for the first and last rows."""
+    rng = rng_of(77)
+    s = np.array([5, 13, 23, 32, 5, 13, 7, 23, 32, 5, 9], np.int32)
+    A = make_matrix(rng, s, s, 0.3)
+    B = make_matrix(rng, s, s, 0.3)
+    Cin = make_matrix(rng, s, s, 0.2)
+    rp, ci = orc.pattern(A, B, Cin)
+    full = orc.multiply(0.5, A, B, -1.0, Cin)
+    for r0, r1 in ((0, 1), (3, 8), (10, 11), (0, 11), (4, 4)):
+        prp, pci = orc.pattern(A, B, Cin, rows=(r0, r1))
+        assert len(prp) == len(rp)
+        assert np.array_equal(np.diff(prp)[r0:r1], np.diff(rp)[r0:r1])
+        assert not np.diff(prp)[:r0].any() and not np.diff(prp)[r1:].any()
+        assert np.array_equal(pci, ci[rp[r0]:rp[r1]])
+        part = orc.multiply(0.5, A, B, -1.0, Cin, rows=(r0, r1))
+        sizes = orc.block_sizes(full.rbs, full.cbs, full.row_ptr, full.col_ind)
+        e0 = int(sizes[:int(full.row_ptr[r0])].sum())
+        e1 = int(sizes[:int(full.row_ptr[r1])].sum())
+        assert np.array_equal(part.col_ind, full.col_ind[full.row_ptr[r0]:full.row_ptr[r1]])
+        assert np.array_equal(part.data[:e1 - e0], full.data[e0:e1])
+
+
 def test_dense_library_on_dense_panels():
     """32-blocks at full occupancy (a small version of the dense workload)."""
     from synth import dense_square
