@@ -271,6 +271,7 @@ def test_stack_row_panels(kernel, panel):
     existing C and the filter run after the last panel."""
     b = lib()
     A, B = banded_uneven(seed=41, occupancy=0.15, target=1100)
+    assert int(np.diff(np.asarray(B.row_ptr))[np.asarray(A.col_ind)].sum()) > 2 * 1500
     rng = rng_of(42)
     Cin = make_matrix(rng, A.rbs, B.cbs, 0.2)
     ref, st0 = gpu_multiply(0.75, A, B, -0.5, Cin, eps=1e-3, kernel=kernel)
@@ -299,7 +300,9 @@ def test_stack_row_panels_no_plan_reuse():
     repeated multiplies into one C still give beta*C + alpha*A*B."""
     b = lib()
     A, B = banded_uneven(seed=43, occupancy=0.2, target=700)
-    b.bsmm_set_option("stack_panel", "3000")
+    nprod = int(np.diff(np.asarray(B.row_ptr))[np.asarray(A.col_ind)].sum())
+    assert nprod > 1000
+    b.bsmm_set_option("stack_panel", str(nprod // 5))
     b.bsmm_set_option("plan_cache", "1")
     set_path("stack", "tuned")
     try:
