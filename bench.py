@@ -150,7 +150,14 @@ def all_configs(bsmm, torch, stream):
 
 
 PAPER_SHAPES = {"square_63360": (63360, 63360, 63360),
-                "rect_1408x1408x1982464": (1408, 1408, 1982464)}
+                "rect_1408x1408x1982464": (1408, 1408, 1982464),
+                # the first tenth of the square product's C rows (every C row
+                # of a dense product costs the same in both modes)
+                "square_63360_rows_6336": (6336, 63360, 63360)}
+# Blocked mode is skipped above this many block products: the stack entries
+# (16 bytes each) are written at about 0.5 TB/s (measured), so 2.4e10
+# products (square, blocks of 22) would take over ten minutes per multiply.
+BLOCKED_MAX_PRODUCTS = 4e9
 
 
 def paper_workloads(bsmm, torch, stream, names, threads):
@@ -181,8 +188,14 @@ def paper_workloads(bsmm, torch, stream, names, threads):
             B = BlockCSR(ks_, ns_, *pattern_full(len(ks_), len(ns_)), b_vals)
             MA, MB = bsmm.Matrix.from_blocks(A), bsmm.Matrix.from_blocks(B)
             r = {"blocks_A": int(A.nnzb), "blocks_B": int(B.nnzb)}
+            products = float(len(ms_)) * len(ks_) * len(ns_)
             for mode, opts in (("densified", dict(path="dense")),
                                ("blocked", dict(path="stack", stack_kernel="tuned", verbose=1))):
+                if mode == "blocked" and products > BLOCKED_MAX_PRODUCTS:
+                    r[mode] = {"skipped": f"{products:.3g} block products ({products * 16 / 1e9:.0f} GB "
+                                          f"of stack entries) exceed {BLOCKED_MAX_PRODUCTS:.0e}"}
+                    log(f"{name} b{bs} blocked skipped: {r[mode]['skipped']}")
+                    continue
                 set_opts(bsmm, **opts)
                 MC = bsmm.Matrix.empty(ms_, ns_)
 
@@ -205,7 +218,8 @@ def paper_workloads(bsmm, torch, stream, names, threads):
                 r[mode]["sampled_block_rows"] = list(rows)
                 log(f"{name} b{bs} {mode}: rel err {r[mode]['rel_err_sampled_rows']:.2e} on block rows {rows}")
                 del X
-            r["t_blocked_over_t_densified"] = round(r["blocked"]["ms"] / r["densified"]["ms"], 3)
+            if "ms" in r["blocked"]:
+                r["t_blocked_over_t_densified"] = round(r["blocked"]["ms"] / r["densified"]["ms"], 3)
             res[f"b{bs}"] = r
             MA.close()
             MB.close()
