@@ -14,8 +14,12 @@
 // LDS double buffered; each wave owns a 64 x 64 sub-tile as 4 x 4 MFMA tiles of
 // v_mfma_f64_16x16x4 (FP64 in, FP64 accumulate).  Workgroup ids are remapped
 // so that the tiles dispatched to one XCD form a contiguous band of
-// 8 tile-rows (shared A panels stay in that XCD's L2).
+// 8 tile-rows (shared A panels stay in that XCD's L2).  When the output
+// has too few tiles to fill the GPU (M = N = 1408 with K in the millions:
+// 121 tiles for 256 CUs), k is split across workgroups; the partial tiles
+// are summed in a fixed order by a second kernel that applies the epilogue.
 #include <algorithm>
+#include <atomic>
 
 #include "dev_util.h"
 #include "internal.h"
@@ -80,6 +84,11 @@ struct GemmArgs {
     int32_t c_nbc;
     const int32_t *c_rbs;
     const int2 *rmap, *cmap;
+    // Split k (few output tiles): workgroup (tile, split) sums k tiles
+    // [split * kt_per, (split + 1) * kt_per) into part[split] (row-major
+    // M_pad x N_pad, unscaled); k_splitk_reduce applies the epilogue.
+    int splits, kt_per;
+    double *part;
 };
 
 // Global -> register loads of one k step of KB: A tile (128 rows x KB k) as
@@ -128,15 +137,24 @@ __device__ __forceinline__ void gemm_lstore(const double2_t (&ra)[KB / 4],
 
 // KB = 16: 64 KB of LDS, two workgroups per CU; KB = 32: 128 KB, one
 // workgroup per CU with twice the prefetch distance and half the barriers.
-template <int KB, int MINB>
+template <int KB, int MINB, bool SPLIT>
 __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
     __shared__ double As[2][KB * BM];  // [k][m]
     __shared__ double Bs[2][BN * KB];  // [n][k ^ swizzle(n)]
 
-    // XCD-aware remap, then grouped row-major order inside the XCD's band.
+    // XCD-aware remap, then grouped row-major order inside the XCD's band
+    // (split k: consecutive logical ids walk the tiles of one split).
     const int nwg = gridDim.x;
     int logical = blockIdx.x;
     if ((nwg & 7) == 0) logical = (blockIdx.x & 7) * (nwg >> 3) + (blockIdx.x >> 3);
+    int split = 0, kt0 = 0, kt1 = g.ktiles;
+    if (SPLIT) {
+        const int tiles = g.tiles_m * g.tiles_n;
+        split = logical / tiles;
+        logical -= split * tiles;
+        kt0 = split * g.kt_per;
+        kt1 = min(g.ktiles, kt0 + g.kt_per);
+    }
     const int per_group = kGroupM * g.tiles_n;
     const int group = logical / per_group;
     const int first_m = group * kGroupM;
@@ -161,12 +179,12 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-    gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, 0, tid);
+    gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt0, tid);
     gemm_lstore<KB>(ra, rb, As[0], Bs[0], tid);
     __syncthreads();
-    for (int kt = 0; kt < g.ktiles; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < g.ktiles) gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
+    for (int kt = kt0; kt < kt1; ++kt) {
+        const int cur = (kt - kt0) & 1;
+        if (kt + 1 < kt1) gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
 #pragma unroll
         for (int ks = 0; ks < KB / 4; ++ks) {
             const int k = ks * 4 + lk;
@@ -184,12 +202,29 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
                 for (int j = 0; j < 4; ++j)
                     acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
         }
-        if (kt + 1 < g.ktiles) gemm_lstore<KB>(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
+        if (kt + 1 < kt1) gemm_lstore<KB>(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
         __syncthreads();
     }
 
     // Epilogue: D(row, col) of a 16x16 FP64 tile sits in lane
     // (col + 16 * (row % 4)), element row / 4.
+    if (SPLIT) {
+        // Partial sums, row-major: 16 lanes store 16 consecutive columns.
+        const int64_t ldp = (int64_t)g.tiles_n * BN;
+        double *P = g.part + (int64_t)split * g.tiles_m * BM * ldp;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + l16;
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + e * 4 + lk;
+                    P[row * ldp + col] = acc[i][j][e];
+                }
+            }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
 #pragma unroll
@@ -213,6 +248,29 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
     }
 }
 
+// Split-k epilogue: C(row, col) = beta C + alpha * (sum of the partials in
+// split order), written into C's blocks like the GEMM epilogue; one thread
+// per element, consecutive threads on consecutive columns.
+__global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
+    const int64_t ldp = (int64_t)g.tiles_n * BN;
+    const int64_t plane = (int64_t)g.tiles_m * BM * ldp;
+    const int64_t n = g.M * g.N;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t row = t / g.N, col = t - row * g.N;
+        const double *p = g.part + row * ldp + col;
+        double v = p[0];
+        for (int sp = 1; sp < g.splits; ++sp) v += p[sp * plane];
+        const int2 rm = g.rmap[row], cm = g.cmap[col];
+        const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
+        const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
+        if (blk < 0) continue;
+        double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
+        const double prod = g.alpha * v;
+        *dst = (g.beta == 0.0) ? prod : fma(g.beta, *dst, prod);
+    }
+}
+
 // c_map[I*nbc + J] = CSR position of block (I,J) in C, or -1.
 __global__ __launch_bounds__(256) void k_block_map(int32_t nbr, int32_t nbc, const int64_t *rp,
                                                    const int32_t *ci, int32_t *map) {
@@ -221,6 +279,24 @@ __global__ __launch_bounds__(256) void k_block_map(int32_t nbr, int32_t nbc, con
     __syncthreads();
     for (int64_t p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x)
         map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
+}
+
+// Compute units of the current device (cached per device).
+int cu_count() {
+    static std::atomic<int> cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    int n = cache[dev].load(std::memory_order_relaxed);
+    if (n > 0) return n;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return 256;
+    }
+    cache[dev].store(n, std::memory_order_relaxed);
+    return n;
 }
 
 }  // namespace
@@ -289,12 +365,39 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     g.c_rbs = C->d_rbs();
     g.rmap = C->d_row_map();
     g.cmap = C->d_col_map();
+    // Split k when the output tiles cannot fill the GPU (tall-and-skinny
+    // products): about two rounds of resident workgroups, each split at
+    // least 16 k tiles deep, partials at most 2 GiB.
+    const int64_t slots = (int64_t)cu_count() * (KB == 32 ? 1 : 2);
+    int64_t splits = 1;
+    if (tiles < slots) {
+        splits = std::min<int64_t>(ceil_div(2 * slots, tiles), g.ktiles / 16);
+        splits = std::min<int64_t>(splits, (int64_t(1) << 31) / (int64_t)(sizeof(double) * Mp * Np));
+        splits = std::max<int64_t>(splits, 1);
+    }
+    DevBuf part;
+    if (splits > 1) {
+        g.kt_per = (int)ceil_div(g.ktiles, splits);
+        splits = ceil_div(g.ktiles, g.kt_per);  // no empty split
+        g.splits = (int)splits;
+        BSMM_TRY(part.reserve(sizeof(double) * splits * Mp * Np, s));
+        g.part = part.as<double>();
+    }
     {
         KernelTimer kt(0, s);
-        if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<32, 1>), dim3((unsigned)tiles), dim3(256), 0, s, g);
-        else hipLaunchKernelGGL((k_dgemm_mfma<16, 2>), dim3((unsigned)tiles), dim3(256), 0, s, g);
+        const dim3 grid((unsigned)(tiles * splits));
+        if (splits > 1) {
+            if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<32, 1, true>), grid, dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_dgemm_mfma<16, 2, true>), grid, dim3(256), 0, s, g);
+        } else {
+            if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<32, 1, false>), grid, dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_dgemm_mfma<16, 2, false>), grid, dim3(256), 0, s, g);
+        }
     }
-    return launch_check("dgemm_mfma");
+    BSMM_TRY(launch_check("dgemm_mfma"));
+    if (splits == 1) return BSMM_OK;
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_of(M * N, 256, 8192)), dim3(256), 0, s, g);
+    return launch_check("splitk_reduce");
 }
 
 }  // namespace bsmm
