@@ -154,10 +154,9 @@ PAPER_SHAPES = {"square_63360": (63360, 63360, 63360),
                 # the first tenth of the square product's C rows (every C row
                 # of a dense product costs the same in both modes)
                 "square_63360_rows_6336": (6336, 63360, 63360)}
-# Blocked mode is skipped above this many block products: the stack entries
-# (16 bytes each) are written at about 0.5 TB/s (measured), so 2.4e10
-# products (square, blocks of 22) would take over ten minutes per multiply.
-BLOCKED_MAX_PRODUCTS = 4e9
+# Blocked mode is skipped above this many block products (the square
+# product in blocks of 22 has 2.4e10; its first tenth of rows took 3.7 s).
+BLOCKED_MAX_PRODUCTS = 3e10
 
 
 def paper_workloads(bsmm, torch, stream, names, threads):

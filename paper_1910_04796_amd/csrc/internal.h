@@ -209,6 +209,7 @@ struct Stacks {
     std::vector<int32_t> row_sizes;   // sorted distinct C block-row sizes
     std::vector<int32_t> col_sizes;   // sorted distinct C block-column sizes
     std::vector<int64_t> class_begin; // run range of class cl: [cb[cl], cb[cl+1])
+    std::vector<int64_t> class_prod_begin;  // first product of class cl (ncl + 1 entries)
     DevBuf run_cblk;   // int64[n_runs]   C block index
     DevBuf run_coff;   // int64[n_runs]   C element offset
     DevBuf run_ptr;    // int64[n_runs+1] first product

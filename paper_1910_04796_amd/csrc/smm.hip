@@ -381,35 +381,17 @@ int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const i
     return launch_check("smm_valu");
 }
 
-namespace {
-// out[i] = run_ptr[idx[i]]: products before the first run of each class.
-__global__ void k_gather_run_ptr(const int64_t *run_ptr, const int64_t *idx, int n, int64_t *out) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) out[i] = run_ptr[idx[i]];
-}
-}  // namespace
-
 // Average products per run of every class (tuned path: the run length is
-// part of the parameter lookup).
-static int class_run_lengths(const Stacks &st, hipStream_t s, std::vector<int> *out) {
-    const int n = st.n_classes + 1;
-    std::vector<int64_t> first(n);
-    DevBuf idx, val;
-    BSMM_TRY(idx.reserve(sizeof(int64_t) * n, s));
-    BSMM_TRY(val.reserve(sizeof(int64_t) * n, s));
-    BSMM_HIP(hipMemcpyAsync(idx.p, st.class_begin.data(), sizeof(int64_t) * n, hipMemcpyHostToDevice, s));
-    hipLaunchKernelGGL(k_gather_run_ptr, dim3(grid_of(n, 256)), dim3(256), 0, s,
-                       (const int64_t *)st.run_ptr.as<int64_t>(), (const int64_t *)idx.as<int64_t>(), n,
-                       val.as<int64_t>());
-    BSMM_TRY(launch_check("gather_run_ptr"));
-    BSMM_HIP(hipMemcpyAsync(first.data(), val.p, sizeof(int64_t) * n, hipMemcpyDeviceToHost, s));
-    BSMM_HIP(hipStreamSynchronize(s));
+// part of the parameter lookup), from the per-class run and product counts
+// the stack builder read back.
+static void class_run_lengths(const Stacks &st, std::vector<int> *out) {
     out->assign(st.n_classes, 1);
+    if ((int)st.class_prod_begin.size() != st.n_classes + 1) return;
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t runs = st.class_begin[cl + 1] - st.class_begin[cl];
-        if (runs > 0) (*out)[cl] = (int)std::max<int64_t>(1, (first[cl + 1] - first[cl] + runs / 2) / runs);
+        const int64_t prods = st.class_prod_begin[cl + 1] - st.class_prod_begin[cl];
+        if (runs > 0) (*out)[cl] = (int)std::max<int64_t>(1, (prods + runs / 2) / runs);
     }
-    return BSMM_OK;
 }
 
 // The k under which tuned parameters are looked up: a run mixes the k of
@@ -451,7 +433,7 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         BSMM_HIP(hipStreamSynchronize(s));
     }
     std::vector<int> rlen;
-    if (tuned) BSMM_TRY(class_run_lengths(st, s, &rlen));
+    if (tuned) class_run_lengths(st, &rlen);
     LaunchList &launches = ex->launches;
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t rb = st.class_begin[cl], re = st.class_begin[cl + 1];

@@ -77,23 +77,37 @@ __device__ __forceinline__ int class_of(int64_t c, const int32_t *c_row, const i
 }
 
 // One wave per tile of kTile C blocks: per-class counts of the blocks that
-// receive products, written class-major (hist[cl * ntiles + tile]).
+// receive products and per-class sums of their products, written
+// class-major (hist[cl * ntiles + tile], hist_p likewise).
 __global__ __launch_bounds__(256) void k_class_hist(int64_t c_base, int64_t nnzb, int64_t ntiles,
                                                     const int64_t *c_count, const int32_t *c_row,
                                                     const int32_t *c_ci, const int32_t *rsi,
                                                     const int32_t *csi, int ncs, int ncl,
-                                                    int64_t *hist) {
-    extern __shared__ int32_t lds[];
+                                                    int64_t *hist, int64_t *hist_p) {
+    extern __shared__ int64_t lds_h[];
     const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    int32_t *cnt = lds + wave_id() * ncl;
+    unsigned long long *psum = (unsigned long long *)lds_h + wave_id() * ncl;
+    int32_t *cnt = (int32_t *)(lds_h + (blockDim.x / kWave) * ncl) + wave_id() * ncl;
     if (tile >= ntiles) return;
-    for (int cl = lane_id(); cl < ncl; cl += kWave) cnt[cl] = 0;
+    for (int cl = lane_id(); cl < ncl; cl += kWave) {
+        cnt[cl] = 0;
+        psum[cl] = 0;
+    }
     wave_lds_sync();
     const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
-    for (int64_t c = c_base + tile * kTile + lane_id(); c < end; c += kWave)
-        if (c_count[c] > 0) atomicAdd(&cnt[class_of(c, c_row, c_ci, rsi, csi, ncs)], 1);
+    for (int64_t c = c_base + tile * kTile + lane_id(); c < end; c += kWave) {
+        const int64_t n = c_count[c];
+        if (n > 0) {
+            const int cl = class_of(c, c_row, c_ci, rsi, csi, ncs);
+            atomicAdd(&cnt[cl], 1);
+            atomicAdd(&psum[cl], (unsigned long long)n);
+        }
+    }
     wave_lds_sync();
-    for (int cl = lane_id(); cl < ncl; cl += kWave) hist[(int64_t)cl * ntiles + tile] = cnt[cl];
+    for (int cl = lane_id(); cl < ncl; cl += kWave) {
+        hist[(int64_t)cl * ntiles + tile] = cnt[cl];
+        hist_p[(int64_t)cl * ntiles + tile] = (int64_t)psum[cl];
+    }
 }
 
 // Stable scatter of the runs into class-major order.
@@ -145,8 +159,13 @@ __global__ void k_gather_rows(const int64_t *scan, const int64_t *rp, int32_t nb
     if (r <= nbr) out[r] = scan[rp[r]];
 }
 
-__global__ void k_gather_class_begin(const int64_t *hoff, int64_t ntiles, int ncl, int64_t *out) {
-    for (int cl = threadIdx.x; cl <= ncl; cl += blockDim.x) out[cl] = hoff[(int64_t)cl * ntiles];
+// out[0..ncl]: first run of every class; out[ncl+1..2 ncl+1]: its first product.
+__global__ void k_gather_class_begin(const int64_t *hoff, const int64_t *hoff_p, int64_t ntiles,
+                                     int ncl, int64_t *out) {
+    for (int cl = threadIdx.x; cl <= ncl; cl += blockDim.x) {
+        out[cl] = hoff[(int64_t)cl * ntiles];
+        out[ncl + 1 + cl] = hoff_p[(int64_t)cl * ntiles];
+    }
 }
 
 // Products of one C block row, K ascending inside every run.  Within one K
@@ -223,6 +242,7 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
         return BSMM_ENOTSUP;
     }
     st.class_begin.assign(ncl + 1, 0);
+    st.class_prod_begin.assign(ncl + 1, 0);
     st.class_active.assign(ncl, 0);
     st.n_runs = 0;
     if (nbr == 0 || nnzb == 0) return BSMM_OK;
@@ -281,16 +301,19 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     const int ncl = st.n_classes;
     const int64_t nblk = c1 - c0;
     st.class_begin.assign(ncl + 1, 0);
+    st.class_prod_begin.assign(ncl + 1, 0);
     st.n_runs = 0;
     st.n_prod = nprod;
     if (r1 <= r0 || nblk <= 0) return BSMM_OK;
 
-    DevBuf hist, hoff, run_cnt, cb;
+    DevBuf hist, hoff, hist_p, hoff_p, run_cnt, cb;
     const int64_t ntiles = ceil_div(nblk, kTile);
     BSMM_TRY(hist.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
     BSMM_TRY(hoff.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    BSMM_TRY(hist_p.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    BSMM_TRY(hoff_p.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
     BSMM_TRY(run_cnt.reserve(sizeof(int64_t) * (nblk + 1), s));
-    BSMM_TRY(cb.reserve(sizeof(int64_t) * (ncl + 1), s));
+    BSMM_TRY(cb.reserve(sizeof(int64_t) * 2 * (ncl + 1), s));
     BSMM_TRY(st.run_of_c.reserve(sizeof(int64_t) * C->nnzb, s));
     BSMM_TRY(st.run_cblk.reserve(sizeof(int64_t) * nblk, s));
     BSMM_TRY(st.run_coff.reserve(sizeof(int64_t) * nblk, s));
@@ -298,13 +321,15 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     BSMM_TRY(st.run_ptr.reserve(sizeof(int64_t) * (nblk + 1), s));
 
     const unsigned tgrid = grid_of(ntiles, 4);
-    hipLaunchKernelGGL(k_class_hist, dim3(tgrid), dim3(256), sizeof(int32_t) * 4 * ncl, s, c0,
-                       nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
+    hipLaunchKernelGGL(k_class_hist, dim3(tgrid), dim3(256), (sizeof(int32_t) + sizeof(int64_t)) * 4 * ncl,
+                       s, c0, nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
                        (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(),
                        (const int32_t *)st.d_rsi.as<int32_t>(),
-                       (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl, hist.as<int64_t>());
+                       (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl, hist.as<int64_t>(),
+                       hist_p.as<int64_t>());
     BSMM_TRY(launch_check("class_hist"));
     BSMM_TRY(scan_exclusive_i64(hist.as<int64_t>(), hoff.as<int64_t>(), ncl * ntiles, s));
+    BSMM_TRY(scan_exclusive_i64(hist_p.as<int64_t>(), hoff_p.as<int64_t>(), ncl * ntiles, s));
     hipLaunchKernelGGL(k_class_scatter, dim3(tgrid), dim3(256), sizeof(int64_t) * 4 * ncl, s, c0,
                        nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
                        (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(), C->d_blk_off(),
@@ -315,14 +340,18 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
                        run_cnt.as<int64_t>(), st.run_of_c.as<int64_t>());
     BSMM_TRY(launch_check("class_scatter"));
     hipLaunchKernelGGL(k_gather_class_begin, dim3(1), dim3(256), 0, s,
-                       (const int64_t *)hoff.as<int64_t>(), ntiles, ncl, cb.as<int64_t>());
+                       (const int64_t *)hoff.as<int64_t>(), (const int64_t *)hoff_p.as<int64_t>(),
+                       ntiles, ncl, cb.as<int64_t>());
     BSMM_TRY(launch_check("gather_class_begin"));
     int32_t miss = 0;
-    BSMM_HIP(hipMemcpyAsync(st.class_begin.data(), cb.p, sizeof(int64_t) * (ncl + 1),
+    std::vector<int64_t> both(2 * (ncl + 1));
+    BSMM_HIP(hipMemcpyAsync(both.data(), cb.p, sizeof(int64_t) * 2 * (ncl + 1),
                             hipMemcpyDeviceToHost, s));
     BSMM_HIP(hipMemcpyAsync(&miss, st.missing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BSMM_HIP(hipStreamSynchronize(s));
     BSMM_TRY(check_missing(miss));
+    st.class_begin.assign(both.begin(), both.begin() + ncl + 1);
+    st.class_prod_begin.assign(both.begin() + ncl + 1, both.end());
     st.n_runs = st.class_begin[ncl];
     for (int cl = 0; cl < ncl; ++cl)
         if (st.class_begin[cl + 1] > st.class_begin[cl]) st.class_active[cl] = 1;
