@@ -220,6 +220,7 @@ struct Stacks {
     DevBuf run_of_c;   // int64[C.nnzb]   run of every C block in its panel, or -1
     DevBuf d_rsi, d_csi, missing;     // size-class index of rows / columns; pattern flag
     std::vector<char> class_active;   // class holds runs (any panel so far)
+    std::vector<int> run_len_hint;    // mean run length per class over every panel (else empty)
 };
 // Whole stacks: stack_count, then stack_rows over every C block row.
 // st.n_prod must hold the product count of the symbolic phase on entry.
@@ -232,6 +233,10 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
 // (host vectors of nbr + 1 entries); EINDEX when C misses a product block.
 int stack_row_bounds(const bsmm_matrix_s *C, const Stacks &st, std::vector<int64_t> *prod_before,
                      std::vector<int64_t> *blk_before, hipStream_t s);
+// After stack_count: the mean run length (products per C block receiving
+// any) of every class over all C block rows.
+int stack_class_run_lengths(const bsmm_matrix_s *C, const Stacks &st, std::vector<int> *out,
+                            hipStream_t s);
 // After stack_count: the runs and products of C block rows [r0, r1) (C
 // blocks [c0, c1), nprod products), replacing the previous panel's.
 int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,

@@ -181,6 +181,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
                      double beta, int64_t cap, Stacks &st, int64_t *n_panels, hipStream_t s) {
     std::vector<int64_t> pb, cb;
     BSMM_TRY(stack_row_bounds(C, st, &pb, &cb, s));
+    if (options().stack_kernel == 1) BSMM_TRY(stack_class_run_lengths(C, st, &st.run_len_hint, s));
     int64_t runs = 0;
     for (int32_t r0 = 0; r0 < C->nbr;) {
         int32_t r1 = r0 + 1;

@@ -433,7 +433,12 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         BSMM_HIP(hipStreamSynchronize(s));
     }
     std::vector<int> rlen;
-    if (tuned) class_run_lengths(st, &rlen);
+    if (tuned) {
+        // Row panels share the whole multiply's run lengths, so every panel
+        // picks the same parameters as one whole stack would.
+        if ((int)st.run_len_hint.size() == st.n_classes) rlen = st.run_len_hint;
+        else class_run_lengths(st, &rlen);
+    }
     LaunchList &launches = ex->launches;
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t rb = st.class_begin[cl], re = st.class_begin[cl + 1];

@@ -244,6 +244,7 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
     st.class_begin.assign(ncl + 1, 0);
     st.class_prod_begin.assign(ncl + 1, 0);
     st.class_active.assign(ncl, 0);
+    st.run_len_hint.clear();
     st.n_runs = 0;
     if (nbr == 0 || nnzb == 0) return BSMM_OK;
 
@@ -294,6 +295,62 @@ int stack_row_bounds(const bsmm_matrix_s *C, const Stacks &st, std::vector<int64
     return check_missing(miss);
 }
 
+namespace {
+struct ClassHist {
+    DevBuf hist, hoff, hist_p, hoff_p, cb;
+    int64_t ntiles = 0;
+};
+
+// Per-class histograms of the C blocks [c0, c0 + nblk) that receive products
+// (blocks and products, per tile), their scans, and the class boundaries
+// gathered into h.cb: first run of every class, then its first product
+// (2 (ncl + 1) values).  Everything is queued on s.
+int class_offsets(const bsmm_matrix_s *C, const Stacks &st, int64_t c0, int64_t nblk, ClassHist &h,
+                  hipStream_t s) {
+    const int ncl = st.n_classes;
+    h.ntiles = ceil_div(nblk, kTile);
+    const int64_t n = ncl * h.ntiles + 1;
+    BSMM_TRY(h.hist.reserve(sizeof(int64_t) * n, s));
+    BSMM_TRY(h.hoff.reserve(sizeof(int64_t) * n, s));
+    BSMM_TRY(h.hist_p.reserve(sizeof(int64_t) * n, s));
+    BSMM_TRY(h.hoff_p.reserve(sizeof(int64_t) * n, s));
+    BSMM_TRY(h.cb.reserve(sizeof(int64_t) * 2 * (ncl + 1), s));
+    hipLaunchKernelGGL(k_class_hist, dim3(grid_of(h.ntiles, 4)), dim3(256),
+                       (sizeof(int32_t) + sizeof(int64_t)) * 4 * ncl, s, c0, nblk, h.ntiles,
+                       (const int64_t *)st.c_count.as<int64_t>(),
+                       (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(),
+                       (const int32_t *)st.d_rsi.as<int32_t>(),
+                       (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl, h.hist.as<int64_t>(),
+                       h.hist_p.as<int64_t>());
+    BSMM_TRY(launch_check("class_hist"));
+    BSMM_TRY(scan_exclusive_i64(h.hist.as<int64_t>(), h.hoff.as<int64_t>(), ncl * h.ntiles, s));
+    BSMM_TRY(scan_exclusive_i64(h.hist_p.as<int64_t>(), h.hoff_p.as<int64_t>(), ncl * h.ntiles, s));
+    hipLaunchKernelGGL(k_gather_class_begin, dim3(1), dim3(256), 0, s,
+                       (const int64_t *)h.hoff.as<int64_t>(), (const int64_t *)h.hoff_p.as<int64_t>(),
+                       h.ntiles, ncl, h.cb.as<int64_t>());
+    return launch_check("gather_class_begin");
+}
+}  // namespace
+
+int stack_class_run_lengths(const bsmm_matrix_s *C, const Stacks &st, std::vector<int> *out,
+                            hipStream_t s) {
+    const int ncl = st.n_classes;
+    out->assign(ncl, 1);
+    if (C->nnzb == 0 || ncl == 0) return BSMM_OK;
+    ClassHist h;
+    BSMM_TRY(class_offsets(C, st, 0, C->nnzb, h, s));
+    std::vector<int64_t> both(2 * (ncl + 1));
+    BSMM_HIP(hipMemcpyAsync(both.data(), h.cb.p, sizeof(int64_t) * 2 * (ncl + 1),
+                            hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    for (int cl = 0; cl < ncl; ++cl) {
+        const int64_t runs = both[cl + 1] - both[cl];
+        const int64_t prods = both[ncl + 2 + cl] - both[ncl + 1 + cl];
+        if (runs > 0) (*out)[cl] = (int)std::max<int64_t>(1, (prods + runs / 2) / runs);
+    }
+    return BSMM_OK;
+}
+
 int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
                Stacks &st, int32_t r0, int32_t r1, int64_t c0, int64_t c1, int64_t nprod,
                hipStream_t s) {
@@ -306,46 +363,27 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     st.n_prod = nprod;
     if (r1 <= r0 || nblk <= 0) return BSMM_OK;
 
-    DevBuf hist, hoff, hist_p, hoff_p, run_cnt, cb;
-    const int64_t ntiles = ceil_div(nblk, kTile);
-    BSMM_TRY(hist.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
-    BSMM_TRY(hoff.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
-    BSMM_TRY(hist_p.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
-    BSMM_TRY(hoff_p.reserve(sizeof(int64_t) * (ncl * ntiles + 1), s));
+    DevBuf run_cnt;
+    ClassHist h;
     BSMM_TRY(run_cnt.reserve(sizeof(int64_t) * (nblk + 1), s));
-    BSMM_TRY(cb.reserve(sizeof(int64_t) * 2 * (ncl + 1), s));
     BSMM_TRY(st.run_of_c.reserve(sizeof(int64_t) * C->nnzb, s));
     BSMM_TRY(st.run_cblk.reserve(sizeof(int64_t) * nblk, s));
     BSMM_TRY(st.run_coff.reserve(sizeof(int64_t) * nblk, s));
     BSMM_TRY(st.run_class.reserve(sizeof(int32_t) * nblk, s));
     BSMM_TRY(st.run_ptr.reserve(sizeof(int64_t) * (nblk + 1), s));
-
-    const unsigned tgrid = grid_of(ntiles, 4);
-    hipLaunchKernelGGL(k_class_hist, dim3(tgrid), dim3(256), (sizeof(int32_t) + sizeof(int64_t)) * 4 * ncl,
-                       s, c0, nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
-                       (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(),
-                       (const int32_t *)st.d_rsi.as<int32_t>(),
-                       (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl, hist.as<int64_t>(),
-                       hist_p.as<int64_t>());
-    BSMM_TRY(launch_check("class_hist"));
-    BSMM_TRY(scan_exclusive_i64(hist.as<int64_t>(), hoff.as<int64_t>(), ncl * ntiles, s));
-    BSMM_TRY(scan_exclusive_i64(hist_p.as<int64_t>(), hoff_p.as<int64_t>(), ncl * ntiles, s));
-    hipLaunchKernelGGL(k_class_scatter, dim3(tgrid), dim3(256), sizeof(int64_t) * 4 * ncl, s, c0,
-                       nblk, ntiles, (const int64_t *)st.c_count.as<int64_t>(),
+    BSMM_TRY(class_offsets(C, st, c0, nblk, h, s));
+    hipLaunchKernelGGL(k_class_scatter, dim3(grid_of(h.ntiles, 4)), dim3(256), sizeof(int64_t) * 4 * ncl,
+                       s, c0, nblk, h.ntiles, (const int64_t *)st.c_count.as<int64_t>(),
                        (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(), C->d_blk_off(),
                        (const int32_t *)st.d_rsi.as<int32_t>(),
                        (const int32_t *)st.d_csi.as<int32_t>(), st.ncs, ncl,
-                       (const int64_t *)hoff.as<int64_t>(), st.run_cblk.as<int64_t>(),
+                       (const int64_t *)h.hoff.as<int64_t>(), st.run_cblk.as<int64_t>(),
                        st.run_class.as<int32_t>(), st.run_coff.as<int64_t>(),
                        run_cnt.as<int64_t>(), st.run_of_c.as<int64_t>());
     BSMM_TRY(launch_check("class_scatter"));
-    hipLaunchKernelGGL(k_gather_class_begin, dim3(1), dim3(256), 0, s,
-                       (const int64_t *)hoff.as<int64_t>(), (const int64_t *)hoff_p.as<int64_t>(),
-                       ntiles, ncl, cb.as<int64_t>());
-    BSMM_TRY(launch_check("gather_class_begin"));
     int32_t miss = 0;
     std::vector<int64_t> both(2 * (ncl + 1));
-    BSMM_HIP(hipMemcpyAsync(both.data(), cb.p, sizeof(int64_t) * 2 * (ncl + 1),
+    BSMM_HIP(hipMemcpyAsync(both.data(), h.cb.p, sizeof(int64_t) * 2 * (ncl + 1),
                             hipMemcpyDeviceToHost, s));
     BSMM_HIP(hipMemcpyAsync(&miss, st.missing.p, sizeof(int32_t), hipMemcpyDeviceToHost, s));
     BSMM_HIP(hipStreamSynchronize(s));
