@@ -156,8 +156,11 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
         for (int i = 0; i < MT; ++i)
 #pragma unroll
             for (int j = 0; j < NT; ++j) acc[i][j] = (v4d_t){0.0, 0.0, 0.0, 0.0};
+        // The next product's descriptor is loaded one product ahead.
+        ulonglong2 nxt = q0 < q1 ? p.prods[q0] : make_ulonglong2(0ull, 0ull);
         for (int64_t q = q0; q < q1; ++q) {
-            const ulonglong2 pr = p.prods[q];
+            const ulonglong2 pr = nxt;
+            if (q + 1 < q1) nxt = p.prods[q + 1];
             const double *a = p.A + (int64_t)(pr.x & ((1ull << 48) - 1));
             const int k = (int)(pr.x >> 48);
             const double *b = p.B + (int64_t)pr.y;
