@@ -265,7 +265,8 @@ int bsmm_kernel_times(double *gemm_ms, int64_t *gemm_launches, double *stack_ms,
  * bsmm_select_params: the parameters the tuned path uses for (m, n, k) in
  *   runs of about run_len products: the database entry of that shape timed
  *   at the run length nearest to run_len (log scale), else the learned
- *   model's choice, else the plain rule.  Database lines are
+ *   model's choice for min(run_len, 32) (32: the longest run length the
+ *   tuner times and the model is trained on), else the plain rule.  Database lines are
  *   "m n k R tm tn kc waves [best_us plain_us]"; lines without R
  *   ("m n k tm tn kc waves [best_us plain_us]") count as R = 8; lines of
  *   any other length are skipped.  run_len < 1: BSMM_EINVAL.

@@ -255,6 +255,9 @@ struct SmmParams {
 constexpr int kMfmaTile = 16;
 // Length of the learned model's feature vector (mlp_features).
 constexpr int kMlpFeatures = 11;
+// Longest run length the tuner times (and the model is trained on); longer
+// runs are presented to the model as runs of this length.
+constexpr int kMlpMaxRunLen = 32;
 // Kernel arguments of one small-block launch.
 struct SmmArgs {
     const double *A;

@@ -118,8 +118,10 @@ SmmParams select_params(int m, int n, int k, int run_len) {
         SmmParams p;
         if (db_lookup_locked(m, n, k, run_len, &p)) return p;
     }
+    // The model is only asked within the run lengths it was trained on: its
+    // run-length feature is not extrapolated past the tuner's longest runs.
     SmmParams p;
-    if (mlp_select(m, n, k, run_len, &p)) return p;
+    if (mlp_select(m, n, k, std::min(run_len, kMlpMaxRunLen), &p)) return p;
     return plain_params(m, n);
 }
 

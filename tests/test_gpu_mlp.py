@@ -117,3 +117,14 @@ def test_model_with_other_feature_count_is_ignored(tmp_path):
         assert b.bsmm_select_params(17, 29, 11) == plain
     finally:
         b.bsmm_set_option("mlp_weights", "")
+
+
+def test_model_not_extrapolated_past_trained_run_lengths():
+    """Runs far longer than the tuner's (a tall-and-skinny product gives
+    C blocks tens of thousands of products) are presented to the committed
+    model as runs of 32, the longest it was trained on; (22, 22, 22) is not
+    in the database, so the model decides."""
+    b = lib()
+    b.use_default_tuning()
+    assert b.bsmm_select_params(22, 22, 22, 90112) == b.bsmm_select_params(22, 22, 22, 32)
+    assert b.bsmm_select_params(22, 22, 22, 33) == b.bsmm_select_params(22, 22, 22, 32)
