@@ -281,6 +281,8 @@ __global__ __launch_bounds__(256) void k_block_map(int32_t nbr, int32_t nbc, con
         map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
 }
 
+}  // namespace
+
 // Compute units of the current device (cached per device).
 int cu_count() {
     static std::atomic<int> cache[64];
@@ -299,7 +301,6 @@ int cu_count() {
     return n;
 }
 
-}  // namespace
 
 int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                    double alpha, double beta, hipStream_t s) {

@@ -255,6 +255,8 @@ struct SmmParams {
 constexpr int kMfmaTile = 16;
 // Length of the learned model's feature vector (mlp_features).
 constexpr int kMlpFeatures = 11;
+// Compute units of the current device (cached per device; 256 if unknown).
+int cu_count();
 // Longest run length the tuner times (and the model is trained on); longer
 // runs are presented to the model as runs of this length.
 constexpr int kMlpMaxRunLen = 32;
@@ -275,6 +277,12 @@ struct SmmArgs {
     int region;             // doubles of LDS per group
     int kc_max;             // largest k chunk that fits the region
     double alpha, beta;
+    // MFMA kernel only: each run's products are cut into `split` segments
+    // handled by different waves; split > 1 writes unscaled partial blocks
+    // to part[((r - run_begin) * split + segment) * m * n] (column-major)
+    // and k_smm_split_reduce applies the epilogue.
+    int split;
+    double *part;
 };
 // A planned launch: kernel, shape-dependent arguments, block size, LDS.
 struct SmmLaunch {
@@ -297,6 +305,7 @@ using LaunchList = std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>
 void retire_graph(hipGraphExec_t exec, hipEvent_t done);
 struct StackExec {
     LaunchList launches;
+    std::vector<DevBuf> parts;  // partial blocks of split launches
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after every launch of exec
     StackExec() = default;

@@ -149,8 +149,15 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     const int m = p.m, n = p.n;
     const int lr = lane & 15, lk = lane >> 4;
-    for (int64_t r = p.run_begin + wid; r < p.run_end; r += waves) {
-        const int64_t q0 = p.run_ptr[r], q1 = p.run_ptr[r + 1];
+    const int S = p.split > 1 ? p.split : 1;
+    const int64_t items = (p.run_end - p.run_begin) * S;
+    for (int64_t it = wid; it < items; it += waves) {
+        // Item = (run, segment): segment sg of S takes products
+        // [len sg / S, len (sg + 1) / S) of the run.
+        const int64_t r = p.run_begin + it / S;
+        const int sg = (int)(it % S);
+        const int64_t rq0 = p.run_ptr[r], len = p.run_ptr[r + 1] - rq0;
+        const int64_t q0 = rq0 + len * sg / S, q1 = rq0 + len * (sg + 1) / S;
         v4d_t acc[MT][NT];
 #pragma unroll
         for (int i = 0; i < MT; ++i)
@@ -207,6 +214,19 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
                                                                              0, 0, 0);
             }
         }
+        if (S > 1) {
+            double *w = p.part + it * (int64_t)m * n;
+#pragma unroll
+            for (int i = 0; i < MT; ++i)
+#pragma unroll
+                for (int j = 0; j < NT; ++j)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        const int row = 16 * i + 4 * e + lk, col = 16 * j + lr;
+                        if (row < m && col < n) w[(int64_t)col * m + row] = acc[i][j][e];
+                    }
+            continue;
+        }
         double *c = p.C + p.run_coff[r];
 #pragma unroll
         for (int i = 0; i < MT; ++i)
@@ -221,6 +241,23 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
                         *dst = (p.beta == 0.0) ? prod : fma(p.beta, *dst, prod);
                     }
                 }
+    }
+}
+
+// Epilogue of split runs: C block of run r = beta C + alpha * (sum of its
+// segments' partial blocks in segment order); one thread per element.
+__global__ __launch_bounds__(256) void k_smm_split_reduce(SmmArgs p) {
+    const int64_t mn = (int64_t)p.m * p.n;
+    const int64_t total = (p.run_end - p.run_begin) * mn;
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t rl = t / mn, e = t - rl * mn;
+        const double *w = p.part + rl * p.split * mn + e;
+        double v = w[0];
+        for (int sg = 1; sg < p.split; ++sg) v += w[sg * mn];
+        double *dst = p.C + p.run_coff[p.run_begin + rl] + e;
+        const double prod = p.alpha * v;
+        *dst = (p.beta == 0.0) ? prod : fma(p.beta, *dst, prod);
     }
 }
 
@@ -358,8 +395,12 @@ int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
     return BSMM_OK;
 }
 
+static unsigned split_reduce_grid(const SmmArgs &a) {
+    return grid_of((a.run_end - a.run_begin) * (int64_t)a.m * a.n, 256, 8192);
+}
+
 unsigned smm_grid(const SmmLaunch &L, int64_t nruns) {
-    const int64_t waves_needed = ceil_div(nruns, L.args.G);
+    const int64_t waves_needed = ceil_div(nruns * std::max(L.args.split, 1), L.args.G);
     const int64_t wg_cap = 256 * 8;  // enough resident work for 256 CUs
     return grid_of(waves_needed, L.waves, wg_cap);
 }
@@ -378,10 +419,15 @@ int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const i
     a.run_end = re;
     a.alpha = alpha;
     a.beta = beta;
-    KernelTimer kt(1, s);
-    hipLaunchKernelGGL((SmmKernel)L.fn, dim3(smm_grid(L, re - rb)), dim3(64 * L.waves), L.lds, s,
-                       a);
-    return launch_check("smm_valu");
+    {
+        KernelTimer kt(1, s);
+        hipLaunchKernelGGL((SmmKernel)L.fn, dim3(smm_grid(L, re - rb)), dim3(64 * L.waves), L.lds, s,
+                           a);
+    }
+    BSMM_TRY(launch_check("smm_valu"));
+    if (a.split <= 1) return BSMM_OK;
+    hipLaunchKernelGGL(k_smm_split_reduce, dim3(split_reduce_grid(a)), dim3(256), 0, s, a);
+    return launch_check("smm_split_reduce");
 }
 
 // Average products per run of every class (tuned path: the run length is
@@ -420,9 +466,24 @@ static int representative_k(const bsmm_matrix_s *A) {
     return best;
 }
 
+// Segments per run for a class of `runs` runs holding `prods` products on
+// the one-wave-per-run MFMA kernel: enough (run, segment) items for about
+// 16 waves per CU when the runs alone are fewer, each segment at least 16
+// products long, at most 64 segments and 1 GiB of partial blocks.
+static int split_for(int64_t runs, int64_t prods, int m, int n) {
+    const int64_t target = (int64_t)cu_count() * 16;
+    if (runs <= 0 || runs >= target) return 1;
+    int64_t S = ceil_div(target, runs);
+    S = std::min<int64_t>(S, prods / runs / 16);
+    S = std::min<int64_t>(S, 64);
+    S = std::min<int64_t>(S, (int64_t(1) << 30) / (runs * (int64_t)m * n * (int64_t)sizeof(double)));
+    return (int)std::max<int64_t>(S, 1);
+}
+
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                const Stacks &st, double alpha, double beta, hipStream_t s, StackExec *ex) {
     ex->launches.clear();
+    ex->parts.clear();
     if (st.n_runs == 0) return BSMM_OK;
     const int kmax = std::max(1, A->max_cbs);
     const int64_t chunk = options().stack_chunk;
@@ -450,6 +511,16 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         SmmParams prm = tuned ? select_params(m, n, krep, rlen[cl]) : plain_params(m, n);
         SmmLaunch L;
         BSMM_TRY(plan_smm(prm, m, n, kmax, &L));
+        if (chunk <= 0 && prm.tm == kMfmaTile && (int)st.class_prod_begin.size() == st.n_classes + 1) {
+            const int S = split_for(re - rb, st.class_prod_begin[cl + 1] - st.class_prod_begin[cl], m, n);
+            if (S > 1) {
+                DevBuf part;
+                BSMM_TRY(part.reserve(sizeof(double) * (size_t)(re - rb) * S * m * n, s));
+                L.args.split = S;
+                L.args.part = part.as<double>();
+                ex->parts.push_back(std::move(part));
+            }
+        }
         if (chunk <= 0) {
             launches.push_back({L, {rb, re}});
             continue;
@@ -554,6 +625,20 @@ int build_graph(const LaunchList &launches, const bsmm_matrix_s *A, const bsmm_m
         if (hipGraphAddKernelNode(&node, graph, nullptr, 0, &kp) != hipSuccess) {
             set_error(BSMM_EDEVICE, "hipGraphAddKernelNode failed");
             status = BSMM_EDEVICE;
+        } else if (a.split > 1) {
+            // The class's split-run epilogue runs after its kernel.
+            hipKernelNodeParams rp{};
+            rp.func = (void *)k_smm_split_reduce;
+            rp.gridDim = dim3(split_reduce_grid(a));
+            rp.blockDim = dim3(256);
+            rp.sharedMemBytes = 0;
+            rp.kernelParams = &argp;
+            rp.extra = nullptr;
+            hipGraphNode_t rnode;
+            if (hipGraphAddKernelNode(&rnode, graph, &node, 1, &rp) != hipSuccess) {
+                set_error(BSMM_EDEVICE, "hipGraphAddKernelNode failed");
+                status = BSMM_EDEVICE;
+            }
         }
     }
     if (status == BSMM_OK && hipGraphInstantiate(out, graph, nullptr, nullptr, 0) != hipSuccess) {

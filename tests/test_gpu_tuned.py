@@ -9,7 +9,7 @@ import pytest
 from oracle import oracle as orc
 from synth import banded_uneven, make_matrix, rng_of
 
-from tests.helpers import check_against_oracle, gpu_multiply, lib
+from tests.helpers import check_against_oracle, gpu_multiply, lib, set_path
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -174,3 +174,59 @@ def test_plan_cache_replay_matches(kernel):
     # beta = 0 then three times beta = 0.5: C = (1 + 0.5 + 0.25 + 0.125) A B
     R = orc.multiply(1.875, A, B, 0.0)
     check_against_oracle(outs[1], R, TOL)
+
+
+@pytest.mark.parametrize("bs,nk", [(32, 400), (23, 300), (13, 500)])
+def test_few_long_runs_split(bs, nk):
+    """A tall-and-skinny product has few C blocks, each receiving hundreds
+    of products: on the MFMA kernel every run is cut into segments on
+    different waves, and a second kernel sums the segments' partial blocks
+    in a fixed order.  Integer entries give the exact result (beta != 0
+    into an existing C), random ones the reference within the tolerance;
+    repeated multiplies are bitwise equal."""
+    rng = rng_of(900 + bs)
+    ms = np.full(2, bs, np.int32)
+    ks = np.full(nk, bs, np.int32)
+    for values in ("int", "uniform"):
+        A = make_matrix(rng, ms, ks, 1.0, values=values)
+        B = make_matrix(rng, ks, ms, 1.0, values=values)
+        Cin = make_matrix(rng, ms, ms, 1.0, values=values)
+        R = orc.multiply(1.0, A, B, -2.0, Cin)
+        X, st = _tuned(A, B, "16 16 0 1", beta=-2.0, Cin=Cin)
+        X2, _ = _tuned(A, B, "16 16 0 1", beta=-2.0, Cin=Cin)
+        assert st["path"] == 1 and st["n_runs"] == 4 and st["n_products"] == 4 * nk
+        assert np.array_equal(X.data, X2.data)
+        check_against_oracle(X, R, 0.0 if values == "int" else TOL)
+
+
+def test_few_long_runs_split_in_graph():
+    """Split runs of several shape classes in one hipGraph (each class's
+    reduction node depends on its kernel node); plan-cache replays give the
+    same bits."""
+    b = lib()
+    rng = rng_of(955)
+    ms = np.array([32, 13], np.int32)
+    ks = np.array([23, 32, 5, 13] * 100, np.int32)
+    A = make_matrix(rng, ms, ks, 1.0)
+    B = make_matrix(rng, ks, ms, 1.0)
+    R = orc.multiply(1.0, A, B, 0.0)
+    X, st = _tuned(A, B, "16 16 0 2")
+    assert st["n_classes"] == 4 and st["n_runs"] == 4
+    check_against_oracle(X, R, TOL)
+    b.bsmm_set_option("plan_cache", "1")
+    b.bsmm_set_option("stack_params", "16 16 0 2")
+    set_path("stack", "tuned")
+    try:
+        MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
+        MC = b.Matrix.empty(A.rbs, B.cbs)
+        outs = []
+        for _ in range(3):
+            b.multiply(1.0, MA, MB, 0.0, MC)
+            outs.append(MC.to_host().data.copy())
+        for M in (MA, MB, MC):
+            M.close()
+    finally:
+        b.bsmm_set_option("plan_cache", "0")
+        b.bsmm_set_option("stack_params", "")
+        set_path()
+    assert all(np.array_equal(o, X.data) for o in outs)
