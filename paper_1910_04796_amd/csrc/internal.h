@@ -219,6 +219,8 @@ struct Stacks {
     DevBuf c_row;      // int32[C.nnzb]   block row of every C block
     DevBuf run_of_c;   // int64[C.nnzb]   run of every C block in its panel, or -1
     DevBuf d_rsi, d_csi, missing;     // size-class index of rows / columns; pattern flag
+    int kparts = 1;                   // parts per A block row in count and fill
+    DevBuf pcount;                    // int64[C.nnzb * kparts]: first position of each part (kparts > 1)
     std::vector<char> class_active;   // class holds runs (any panel so far)
     std::vector<int> run_len_hint;    // mean run length per class over every panel (else empty)
 };

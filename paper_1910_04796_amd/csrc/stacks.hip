@@ -37,15 +37,28 @@ constexpr int kMapMaxCols = 8192;   // LDS map + counters: 64 KB
 constexpr int kTile = 1024;         // C blocks per classification tile
 constexpr int kMaxClasses = 1024;   // distinct (m, n) shapes
 
+// A block range [pa0, pa1) of part `part` of P of A's block row `row`.
+__device__ __forceinline__ void a_part(const int64_t *a_rp, int32_t row, int part, int P, int64_t *pa0,
+                                       int64_t *pa1) {
+    const int64_t b = a_rp[row], len = a_rp[row + 1] - b;
+    *pa0 = b + len * part / P;
+    *pa1 = b + len * (part + 1) / P;
+}
+
+// Workgroup (row, part): products per C block of the row from the part's
+// share of A's block row (P > 1 splits long A rows of few-row products;
+// the part counts go to pcount[c * P + part], else straight to c_count).
 __global__ __launch_bounds__(256) void k_stack_count(int32_t nbc, const int64_t *a_rp,
                                                      const int32_t *a_ci, const int64_t *b_rp,
                                                      const int32_t *b_ci, const int64_t *c_rp,
                                                      const int32_t *c_ci, int64_t *c_count,
-                                                     int32_t *c_row, int32_t *missing) {
+                                                     int32_t *c_row, int32_t *missing, int P,
+                                                     int64_t *pcount) {
     extern __shared__ int32_t lds[];
     int32_t *map = lds;          // nbc entries: column -> slot in the C row, or -1
     int32_t *cnt = lds + nbc;    // row length entries
     const int32_t row = blockIdx.x;
+    const int part = blockIdx.y;
     const int64_t p0 = c_rp[row];
     const int32_t len = (int32_t)(c_rp[row + 1] - p0);
     for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
@@ -56,7 +69,9 @@ __global__ __launch_bounds__(256) void k_stack_count(int32_t nbc, const int64_t 
     }
     __syncthreads();
     const int nw = blockDim.x / kWave;
-    for (int64_t pa = a_rp[row] + wave_id(); pa < a_rp[row + 1]; pa += nw) {
+    int64_t pa0, pa1;
+    a_part(a_rp, row, part, P, &pa0, &pa1);
+    for (int64_t pa = pa0 + wave_id(); pa < pa1; pa += nw) {
         const int32_t kb = a_ci[pa];
         for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
             const int32_t s = map[b_ci[q]];
@@ -66,8 +81,25 @@ __global__ __launch_bounds__(256) void k_stack_count(int32_t nbc, const int64_t 
     }
     __syncthreads();
     for (int s = threadIdx.x; s < len; s += blockDim.x) {
-        c_count[p0 + s] = cnt[s];
-        c_row[p0 + s] = row;
+        if (P == 1) c_count[p0 + s] = cnt[s];
+        else pcount[(p0 + s) * P + part] = cnt[s];
+        c_row[p0 + s] = row;  // every part writes the same value
+    }
+}
+
+// P > 1: per C block, the part counts become the part's first position in
+// the run (exclusive prefix in part order) and c_count their total.
+__global__ __launch_bounds__(256) void k_part_offsets(int64_t nnzb, int P, int64_t *pcount,
+                                                      int64_t *c_count) {
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < nnzb;
+         c += (int64_t)gridDim.x * blockDim.x) {
+        int64_t run = 0;
+        for (int p = 0; p < P; ++p) {
+            const int64_t v = pcount[c * P + p];
+            pcount[c * P + p] = run;
+            run += v;
+        }
+        c_count[c] = run;
     }
 }
 
@@ -171,7 +203,8 @@ __global__ void k_gather_class_begin(const int64_t *hoff, const int64_t *hoff_p,
 // Products of one C block row, K ascending inside every run.  Within one K
 // every C slot is hit at most once, so the per-slot cursors need no atomics;
 // a barrier separates consecutive K.
-__global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int32_t nbc, const int64_t *a_rp,
+__global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const int64_t *poff,
+                                                    int32_t nbc, const int64_t *a_rp,
                                                     const int32_t *a_ci, const int64_t *a_off,
                                                     const int64_t *b_rp, const int32_t *b_ci,
                                                     const int64_t *b_off, const int32_t *kbs,
@@ -182,16 +215,19 @@ __global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int32_t nbc, c
     int32_t *map = lds;
     int32_t *cur = lds + nbc;
     const int32_t row = row0 + (int32_t)blockIdx.x;
+    const int part = blockIdx.y;
     const int64_t p0 = c_rp[row];
     const int32_t len = (int32_t)(c_rp[row + 1] - p0);
     for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
     __syncthreads();
     for (int s = threadIdx.x; s < len; s += blockDim.x) {
         map[c_ci[p0 + s]] = s;
-        cur[s] = 0;
+        cur[s] = P == 1 ? 0 : (int32_t)poff[(p0 + s) * P + part];
     }
     __syncthreads();
-    for (int64_t pa = a_rp[row]; pa < a_rp[row + 1]; ++pa) {
+    int64_t pa0, pa1;
+    a_part(a_rp, row, part, P, &pa0, &pa1);
+    for (int64_t pa = pa0; pa < pa1; ++pa) {
         const int32_t kb = a_ci[pa];
         const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
         for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
@@ -253,16 +289,29 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
     BSMM_TRY(st.c_row.reserve(sizeof(int32_t) * nnzb, s));
     BSMM_TRY(st.c_count.reserve(sizeof(int64_t) * nnzb, s));
     BSMM_TRY(st.missing.reserve(sizeof(int32_t), s));
+    // Few C block rows with long A rows (tall-and-skinny products): split
+    // every A row into P parts so that about 1024 workgroups count and fill.
+    st.kparts = 1;
+    if (nbr < 256 && A->nnzb > 0) {
+        const int64_t per_row = A->nnzb / nbr;
+        st.kparts = (int)std::min<int64_t>(ceil_div(1024, nbr), std::max<int64_t>(1, per_row / 64));
+    }
+    if (st.kparts > 1) BSMM_TRY(st.pcount.reserve(sizeof(int64_t) * nnzb * st.kparts, s));
     BSMM_HIP(hipMemcpyAsync(st.d_rsi.p, rsi.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice, s));
     BSMM_HIP(hipMemcpyAsync(st.d_csi.p, csi.data(), sizeof(int32_t) * nbc, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, st.missing.as<int32_t>());
     BSMM_TRY(launch_check("zero_i32"));
     const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
-    hipLaunchKernelGGL(k_stack_count, dim3(nbr), dim3(256), map_lds, s, nbc, A->d_row_ptr(),
-                       A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(), C->d_row_ptr(),
-                       C->d_col_ind(), st.c_count.as<int64_t>(), st.c_row.as<int32_t>(),
-                       st.missing.as<int32_t>());
-    return launch_check("stack_count");
+    hipLaunchKernelGGL(k_stack_count, dim3(nbr, st.kparts), dim3(256), map_lds, s, nbc,
+                       A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
+                       C->d_row_ptr(), C->d_col_ind(), st.c_count.as<int64_t>(),
+                       st.c_row.as<int32_t>(), st.missing.as<int32_t>(), st.kparts,
+                       st.pcount.as<int64_t>());
+    BSMM_TRY(launch_check("stack_count"));
+    if (st.kparts == 1) return BSMM_OK;
+    hipLaunchKernelGGL(k_part_offsets, dim3(grid_of(nnzb, 256)), dim3(256), 0, s, nnzb, st.kparts,
+                       st.pcount.as<int64_t>(), st.c_count.as<int64_t>());
+    return launch_check("part_offsets");
 }
 
 // The flag of k_stack_count, read after a host synchronisation.
@@ -397,7 +446,8 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     if (nprod > 0) {
         BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
         const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
-        hipLaunchKernelGGL(k_stack_fill, dim3(r1 - r0), dim3(256), map_lds, s, r0, nbc,
+        hipLaunchKernelGGL(k_stack_fill, dim3(r1 - r0, st.kparts), dim3(256), map_lds, s, r0,
+                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), nbc,
                            A->d_row_ptr(), A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(),
                            B->d_col_ind(), B->d_blk_off(), B->d_rbs(), C->d_row_ptr(),
                            C->d_col_ind(), (const int64_t *)st.run_of_c.as<int64_t>(),

@@ -257,11 +257,27 @@ def test_empty_and_degenerate():
     assert len(X.row_ptr) == 1
 
 
-def test_stack_contents_exact():
+def _tall_skinny_sparse(seed):
+    """3 block rows of A against 700 block columns (half occupied) and B with
+    4 block columns: few C rows, long A rows, so the stack builder splits
+    every A row over several workgroups."""
+    rng = rng_of(seed)
+    ms = np.array([5, 13, 5], np.int32)
+    ks = rng.choice(np.array([5, 13, 23], np.int32), size=700)
+    ns = np.array([13, 5, 23, 5], np.int32)
+    return make_matrix(rng, ms, ks, 0.5), make_matrix(rng, ks, ns, 0.5)
+
+
+@pytest.mark.parametrize("workload", ["banded", "tall_skinny"])
+def test_stack_contents_exact(workload):
     """The stacks hold exactly the (I,K,J) products of the block patterns,
-    runs ordered by class then C block, K ascending inside a run."""
+    runs ordered by class then C block, K ascending inside a run (also when
+    long A rows are counted and filled in parts by several workgroups)."""
     b = lib()
-    A, B = banded_uneven(seed=9, occupancy=0.1, target=600)
+    if workload == "banded":
+        A, B = banded_uneven(seed=9, occupancy=0.1, target=600)
+    else:
+        A, B = _tall_skinny_sparse(seed=19)
     R = orc.multiply(1.0, A, B, 0.0)
     MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
     MC = b.Matrix.from_blocks(R)
@@ -290,6 +306,21 @@ def test_stack_contents_exact():
     assert key == sorted(key)
     for M in (MA, MB, MC):
         M.close()
+
+
+def test_tall_skinny_parts_match_reference():
+    """The split count and fill of long A rows: plain and tuned stacks reach
+    the reference result; integer entries exactly."""
+    for kernel in ("plain", "tuned"):
+        rng = rng_of(23)
+        ms = np.array([5, 13, 5], np.int32)
+        ks = rng.choice(np.array([5, 13, 23], np.int32), size=700)
+        ns = np.array([13, 5, 23, 5], np.int32)
+        A = make_matrix(rng, ms, ks, 0.5, values="int")
+        B = make_matrix(rng, ks, ns, 0.5, values="int")
+        Cin = make_matrix(rng, ms, ns, 0.5, values="int")
+        X, st = gpu_multiply(1.0, A, B, 3.0, Cin, path="stack", kernel=kernel)
+        check_against_oracle(X, orc.multiply(1.0, A, B, 3.0, Cin), 0.0)
 
 
 def test_stack_chunk_bitwise():
