@@ -472,8 +472,9 @@ def main():
         c0 = time.perf_counter()
         orc.multiply(1.0, A, B, 0.0, rows=(2, 6), nthreads=threads)
         t_row = (time.perf_counter() - c0) / 4
-        r0 = 6
-        nrows = int(max(1, min(N // BS - r0, 15.0 / max(t_row, 1e-3))))
+        # The whole C when it takes at most 30 s, else about 15 s of rows.
+        r0 = 0
+        nrows = N // BS if t_row * (N // BS) <= 30.0 else int(max(1, 15.0 / max(t_row, 1e-3)))
         c0 = time.perf_counter()
         R = orc.multiply(1.0, A, B, 0.0, rows=(r0, r0 + nrows), nthreads=threads)
         t_cpu = time.perf_counter() - c0
