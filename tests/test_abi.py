@@ -62,6 +62,7 @@ def test_options_round_trip():
                  ("stack_kernel", "tuned"),
                  ("stack_kernel", "plain"), ("stack_chunk", "30000"), ("stack_chunk", "0"),
                  ("stack_panel", "1000"), ("stack_panel", "0"), ("stack_panel", "1073741824"),
+                 ("verbose", "1"), ("verbose", "0"),
                  ("emul_kernel", "t64"), ("emul_kernel", "t128"), ("emul_kernel", "t128w8"), ("emul_kernel", "t128k32"), ("dense_kb", "32"), ("dense_kb", "16")]:
         b.bsmm_set_option(k, v)
         assert b.bsmm_get_option(k) == v
@@ -70,6 +71,7 @@ def test_options_round_trip():
     assert _err(b.bsmm_set_option, "stack_chunk", "-4") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "stack_panel", "-1") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "stack_panel", "1e9") == b.BSMM_EINVAL
+    assert _err(b.bsmm_set_option, "verbose", "yes") == b.BSMM_EINVAL
     assert _err(b.bsmm_set_option, "emul_kernel", "t96") == b.BSMM_EINVAL
 
 
