@@ -401,7 +401,9 @@ static unsigned split_reduce_grid(const SmmArgs &a) {
 
 unsigned smm_grid(const SmmLaunch &L, int64_t nruns) {
     const int64_t waves_needed = ceil_div(nruns * std::max(L.args.split, 1), L.args.G);
-    const int64_t wg_cap = 256 * 8;  // enough resident work for 256 CUs
+    // At most 32 waves per CU (256 CUs) in the grid, whatever the waves per
+    // workgroup; the kernels stride over the remaining runs.
+    const int64_t wg_cap = 256 * 32 / std::max(L.waves, 1);
     return grid_of(waves_needed, L.waves, wg_cap);
 }
 
