@@ -211,6 +211,35 @@ static int validate_pattern(int32_t nbr, int32_t nbc, int64_t nnzb, const int64_
 static thread_local bsmm_multiply_stats t_stats;
 bsmm_multiply_stats &stats() { return t_stats; }
 
+// Every device buffer of a matrix belongs to the stream that last used it.
+// Before work on stream s touches the matrix, s waits for the work queued
+// on the buffers' current streams, and the buffers pass to s: a buffer
+// released later (replaced by a grown or filtered pattern, or destroyed)
+// returns to the pool under the last stream that used it, so the pool never
+// hands it out while that work may still run.
+int adopt_stream(bsmm_matrix_s *M, hipStream_t s) {
+    DevBuf *bufs[] = {&M->b_rbs, &M->b_cbs, &M->b_row_off, &M->b_col_off, &M->b_row_map,
+                      &M->b_col_map, &M->b_row_ptr, &M->b_col_ind, &M->b_blk_off, &M->b_data};
+    std::vector<hipStream_t> waited;
+    for (DevBuf *b : bufs) {
+        if (!b->p || b->s == s) continue;
+        if (std::find(waited.begin(), waited.end(), b->s) == waited.end()) {
+            hipEvent_t ev;
+            BSMM_HIP(hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+            const hipError_t e1 = hipEventRecord(ev, b->s);
+            const hipError_t e2 = e1 == hipSuccess ? hipStreamWaitEvent(s, ev, 0) : e1;
+            (void)hipEventDestroy(ev);
+            if (e2 != hipSuccess) {
+                set_error(BSMM_EDEVICE, "stream hand-over failed: %s", hipGetErrorString(e2));
+                return BSMM_EDEVICE;
+            }
+            waited.push_back(b->s);
+        }
+        b->s = s;
+    }
+    return BSMM_OK;
+}
+
 }  // namespace bsmm
 
 using namespace bsmm;
@@ -374,6 +403,7 @@ extern "C" int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_c
         return BSMM_EINVAL;
     }
     hipStream_t s = (hipStream_t)stream;
+    BSMM_TRY(adopt_stream(m, s));
     if (blk_row_ptr)
         BSMM_HIP(hipMemcpyAsync(blk_row_ptr, m->d_row_ptr(), sizeof(int64_t) * (m->nbr + 1),
                                 hipMemcpyDeviceToHost, s));

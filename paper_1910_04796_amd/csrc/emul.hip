@@ -10,10 +10,12 @@
 //      r <- 128 r - d_s (all exact in FP64), d_s in [-127, 127] stored as int8;
 //   3. one INT8 MFMA GEMM over every digit pair with s + t <= S + 1,
 //      accumulating G_d = sum_{s+t=d} A_s B_t exactly in INT32 (K chunks keep
-//      K * 127^2 * S below 2^31);
-//   4. FP64 recombination in the epilogue: Horner h = G_{S+1}, h <- h 2^-7 + G_d
-//      down to d = 2, value = h * 2^(e_i + e_j - 14) (exact scaling); chunk
-//      values summed in FP64 in chunk order; C = beta C + alpha value with
+//      K * 127^2 * S below 2^31; when K needs several chunks, each chunk adds
+//      its INT32 sums into exact int64 partial sums, so G_d is the exact sum
+//      over the whole K whatever the chunking);
+//   4. FP64 recombination in the epilogue of the last chunk: Horner
+//      h = G_{S+1}, h <- h 2^-7 + G_d down to d = 2, value =
+//      h * 2^(e_i + e_j - 14) (exact scaling); C = beta C + alpha value with
 //      separately rounded products (native FP64 for the recombination and
 //      beta * C).
 //
@@ -34,6 +36,7 @@
 // tiles resident on one XCD form a compact group of tile rows and columns
 // (their slices stay in that XCD's L2).
 #include <algorithm>
+#include <climits>
 
 #include "dev_util.h"
 #include "internal.h"
@@ -85,18 +88,29 @@ __device__ __forceinline__ void emul_tile_of(int tiles_m, int tiles_n, int gm, i
     tn = in_group / gsz;
 }
 
+// Exponent of a row holding an infinity or a NaN: digit slices cannot carry
+// such values, so the row is sliced as zeros and every output element it
+// touches becomes NaN.
+constexpr int kNonFiniteExp = INT_MIN;
+
 // Row exponents of a k-contiguous matrix (rows x ld): one wave per row.
 __global__ __launch_bounds__(256) void k_row_exp(const double *X, int64_t rows, int64_t K,
                                                  int64_t ld, int *e) {
     const int64_t r = (int64_t)blockIdx.x * 4 + wave_id();
     if (r >= rows) return;
     double mx = 0.0;
-    for (int64_t k = lane_id(); k < K; k += kWave) mx = fmax(mx, fabs(X[r * ld + k]));
+    bool bad = false;
+    for (int64_t k = lane_id(); k < K; k += kWave) {
+        const double x = X[r * ld + k];
+        bad |= !isfinite(x);
+        mx = fmax(mx, fabs(x));
+    }
     mx = wave_max(mx);
+    const bool any_bad = __ballot(bad) != 0;
     if (lane_id() == 0) {
         int ex = 0;
         if (mx > 0.0) (void)frexp(mx, &ex);
-        e[r] = ex;
+        e[r] = any_bad ? kNonFiniteExp : ex;
     }
 }
 
@@ -114,10 +128,12 @@ __global__ __launch_bounds__(256) void k_slice(const double *X, int64_t rows, in
     const int64_t rp = idx >> 2;
     const int64_t p = rp / rows, r = rp - p * rows;
     const int64_t k = 32 * p + 8 * q;
-    const double sc = ldexp(1.0, -e[r]);
+    // Scaling by 2^-e in one step is exact also for subnormal rows (e below
+    // -1022, where 2^-e itself would overflow).
+    const int er = e[r];
     double v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = X[r * ld + k + j] * sc;
+    for (int j = 0; j < 8; ++j) v[j] = er == kNonFiniteExp ? 0.0 : ldexp(X[r * ld + k + j], -er);
     for (int s = 0; s < S; ++s) {
         unsigned long long w = 0;
 #pragma unroll
@@ -139,7 +155,7 @@ struct EmulArgs {
     int64_t k0, k1;         // k range of this chunk
     const int *ea, *eb;
     int mode;               // 1 first chunk, 2 later chunk, 4 last chunk (bit flags)
-    double *V;              // FP64 partial values (Mp x Np, column-major), multi-chunk only
+    long long *V;           // exact partial sums, S planes of Mp x Np (column-major), multi-chunk only
     int64_t M, N;
     double alpha, beta;
     double *C;
@@ -150,22 +166,33 @@ struct EmulArgs {
     const int2 *rmap, *cmap;
 };
 
-// FP64 recombination of one output element from its S weight sums (Horner
-// in 2^-7, exact power-of-two scaling), chunk accumulation, and the store
+// One output element from its S weight sums of this K chunk: exact int64
+// accumulation over the chunks, then (last chunk) the FP64 recombination
+// (Horner in 2^-7, exact power-of-two scaling) and the store
 // C = beta C + alpha value into C's block (every operation rounded on its
-// own: this file is compiled without contraction).
+// own: this file is compiled without contraction).  The int64 sums are
+// exact (|G_d| <= S K 127^2 < 2^53), so converting them to FP64 is exact and
+// the result does not depend on where K was split.
 template <int S>
 __device__ __forceinline__ void emul_out(const EmulArgs &g, const int (&vals)[S], int64_t row,
                                          int64_t col) {
-    double h = (double)vals[S - 1];
+    long long tot[S];
+    const int64_t plane = g.Mp * g.Np, at = col * g.Mp + row;
 #pragma unroll
-    for (int d = S - 2; d >= 0; --d) h = h * (1.0 / 128.0) + (double)vals[d];
-    double v = ldexp(h, g.ea[row] + g.eb[col] - 14);
-    if (!(g.mode & 1)) v = g.V[col * g.Mp + row] + v;
+    for (int d = 0; d < S; ++d) tot[d] = (g.mode & 1) ? (long long)vals[d] : g.V[d * plane + at] + vals[d];
     if (!(g.mode & 4)) {
-        g.V[col * g.Mp + row] = v;
+#pragma unroll
+        for (int d = 0; d < S; ++d) g.V[d * plane + at] = tot[d];
         return;
     }
+    double h = (double)tot[S - 1];
+#pragma unroll
+    for (int d = S - 2; d >= 0; --d) h = h * (1.0 / 128.0) + (double)tot[d];
+    // One power-of-two scaling (exponents lie in [-1073, 1024], so their sum
+    // fits an int): the value is rounded at most once, on under- or overflow.
+    const int ea = g.ea[row], eb = g.eb[col];
+    const double v = (ea == kNonFiniteExp || eb == kNonFiniteExp) ? __builtin_nan("")
+                                                                  : ldexp(h, ea + eb - 14);
     if (row >= g.M || col >= g.N) return;
     const int2 rm = g.rmap[row], cm = g.cmap[col];
     const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
@@ -784,7 +811,7 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
     }
     const int64_t chunk = emul_chunk(S);
     const int64_t nchunks = ceil_div(Kp, chunk);
-    if (nchunks > 1) BSMM_TRY(V.reserve(sizeof(double) * Mp * Np, s));
+    if (nchunks > 1) BSMM_TRY(V.reserve(sizeof(long long) * S * Mp * Np, s));
     const int64_t tiles = (Mp / tile_m) * (Np / tile_n);
     if (tiles > INT32_MAX) {
         set_error(BSMM_ERANGE, "emulated product too large");
@@ -802,7 +829,7 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
         g.ea = ea.as<int>();
         g.eb = eb.as<int>();
         g.mode = (c == 0 ? 1 : 2) | (c == nchunks - 1 ? 4 : 0);
-        g.V = V.as<double>();
+        g.V = V.as<long long>();
         g.M = M;
         g.N = N;
         g.alpha = alpha;

@@ -201,6 +201,10 @@ int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hi
 int fill_zero(double *p, int64_t n, hipStream_t s);
 
 // ---------------------------------------------------------------- stacks
+// A product entry keeps A's element offset in 48 bits and k in 16 bits.
+constexpr int kMaxStackK = 0xFFFF;
+// Block columns of C the count and fill phases map in LDS (64 KB).
+constexpr int kMaxStackCols = 8192;
 // Product stacks of C += A*B, grouped by shape class (m, n).
 struct Stacks {
     int64_t n_runs = 0, n_prod = 0;

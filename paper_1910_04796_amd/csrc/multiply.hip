@@ -16,6 +16,7 @@
 
 namespace bsmm {
 int validate_multiply(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, double eps);
+int adopt_stream(bsmm_matrix_s *M, hipStream_t s);
 bsmm_multiply_stats &stats();
 
 namespace {
@@ -69,6 +70,11 @@ int symbolic(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, SymbolicTotal
         tot->nelems = A->rows() * B->cols();
         tot->nprod = (int64_t)nbr * nbk * nbc;
         tot->flops = 2.0 * M * N * K;
+        if (tot->nnzb > (int64_t)INT32_MAX || tot->nelems >= (int64_t(1) << 47)) {
+            set_error(BSMM_ERANGE, "result too large (%lld blocks, %lld elements)",
+                      (long long)tot->nnzb, (long long)tot->nelems);
+            return BSMM_ERANGE;
+        }
         if (tot->nnzb == C->nnzb) return BSMM_OK;
         *changed = true;
         BSMM_TRY(np.rp.reserve(sizeof(int64_t) * (nbr + 1), s));
@@ -236,6 +242,26 @@ int numeric(int path, bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doub
     }
 }
 
+// Limits of the stack path, checked on the host before any work is queued:
+// a product entry carries k in 16 bits and the count and fill phases map
+// C's block columns in LDS.
+int check_stack_limits(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                       const Options &o) {
+    const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
+    if (o.path == 3 || dense) return BSMM_OK;
+    if (A->max_cbs > kMaxStackK) {
+        set_error(BSMM_ENOTSUP, "stack path: block columns of A hold at most %d columns (found %d)",
+                  kMaxStackK, A->max_cbs);
+        return BSMM_ENOTSUP;
+    }
+    if (C->nbc > kMaxStackCols) {
+        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns (found %d)",
+                  kMaxStackCols, C->nbc);
+        return BSMM_ENOTSUP;
+    }
+    return BSMM_OK;
+}
+
 int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
                   bsmm_matrix_s *C, double eps, hipStream_t s) {
     bsmm_multiply_stats &stt = stats();
@@ -313,7 +339,11 @@ extern "C" int bsmm_multiply(double alpha, bsmm_matrix A, bsmm_matrix B, double 
                              bsmm_matrix C, double filter_eps, void *stream) {
     clear_error();
     BSMM_TRY(validate_multiply(A, B, C, filter_eps));
+    BSMM_TRY(check_stack_limits(A, B, C, options()));
     hipStream_t s = (hipStream_t)stream;
+    BSMM_TRY(adopt_stream(A, s));
+    if (B != A) BSMM_TRY(adopt_stream(B, s));
+    BSMM_TRY(adopt_stream(C, s));
     const int st = multiply_impl(alpha, A, B, beta, C, filter_eps, s);
     A->last_stream = B->last_stream = C->last_stream = s;
     return st;

@@ -33,7 +33,6 @@ namespace bsmm {
 
 namespace {
 
-constexpr int kMapMaxCols = 8192;   // LDS map + counters: 64 KB
 constexpr int kTile = 1024;         // C blocks per classification tile
 constexpr int kMaxClasses = 1024;   // distinct (m, n) shapes
 
@@ -262,8 +261,8 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
                 Stacks &st, hipStream_t s) {
     const int32_t nbr = C->nbr, nbc = C->nbc;
     const int64_t nnzb = C->nnzb;
-    if (nbc > kMapMaxCols) {
-        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns", kMapMaxCols);
+    if (nbc > kMaxStackCols) {
+        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns", kMaxStackCols);
         return BSMM_ENOTSUP;
     }
     std::vector<int32_t> rsi, csi;

@@ -56,3 +56,17 @@ def check_against_oracle(X, R, tol):
     err = orc.rel_err(np.asarray(X.data), np.asarray(R.data))
     assert err <= tol, f"relative error {err:.3e} > {tol:.1e}"
     return err
+
+
+def from_dense(D, rbs, cbs):
+    """Block-CSR (every block stored) of a dense matrix: blocks in CSR order,
+    column-major inside a block."""
+    from synth import BlockCSR, pattern_full
+    rbs = np.asarray(rbs, np.int32)
+    cbs = np.asarray(cbs, np.int32)
+    ro = np.concatenate([[0], np.cumsum(rbs)])
+    co = np.concatenate([[0], np.cumsum(cbs)])
+    rp, ci = pattern_full(len(rbs), len(cbs))
+    data = [np.asarray(D[ro[i]:ro[i + 1], co[j]:co[j + 1]], np.float64).ravel(order="F")
+            for i in range(len(rbs)) for j in range(len(cbs))]
+    return BlockCSR(rbs, cbs, rp, ci, np.concatenate(data))

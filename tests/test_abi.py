@@ -125,3 +125,27 @@ def test_model_features_of_run_length():
     assert b.bsmm_mlp_features(23, 13, 7, np.array([2, 2, 0, 0], np.int32), 8)[9] == 0.0
     # lanes cover m x n; the matrix-core tile also pads k to a multiple of 4
     assert np.isclose(f1[8], (23 * 13) / (2 * 1 * 256) * 7 / 8)
+
+
+def test_create_range_errors_before_any_device_call():
+    """ERANGE is decided from the index alone, before any HIP call (so also
+    on a machine without a GPU): 2^47 or more elements, more than 2^31 - 1
+    blocks."""
+    from paper_1910_04796_amd import bsmm as b
+    c = b.bsmm_create_matrix
+    assert _err(c, 1, [1 << 24], 1, [1 << 23], 1, [0, 1], [0], None) == b.BSMM_ERANGE
+    big = (1 << 31)
+    assert _err(c, 1, [1], 1, [1], big, [0, big], [0], None) == b.BSMM_ERANGE
+    assert "2^47" in b.bsmm_last_error() or "too many" in b.bsmm_last_error()
+
+
+def test_create_and_multiply_argument_errors():
+    """EINVAL on null arguments and bad option values of the allocator:
+    a deallocator is required with an allocator."""
+    import ctypes
+    from paper_1910_04796_amd import bsmm as b
+    st = b._lib.bsmm_create_matrix(1, None, 1, None, 0, None, None, None, 0, None, None)
+    assert st == b.BSMM_EINVAL
+    st = b._lib.bsmm_set_allocator(b.ALLOC_FN(lambda n, s, c: None), b.DEALLOC_FN(), None)
+    assert st == b.BSMM_EINVAL
+    assert _err(b.bsmm_multiply, 1.0, None, None, 0.0, None, float("nan"), 0) == b.BSMM_EINVAL

@@ -7,7 +7,7 @@ from oracle import emul_ref as er
 from oracle import oracle as orc
 from synth import make_matrix, rng_of, wide_range_sparse
 
-from tests.helpers import check_against_oracle, gpu_multiply, lib
+from tests.helpers import check_against_oracle, from_dense, gpu_multiply, lib
 
 pytestmark = pytest.mark.gpu
 
@@ -40,19 +40,66 @@ def test_bit_exact_against_reference(S):
 
 
 def test_multi_chunk_k():
-    """K above the INT32-exact chunk (8 slices: 16640) is summed in FP64 per
-    chunk, in chunk order, exactly as the reference does."""
+    """K above the INT32-exact chunk of the device (8 slices: 16,640): the
+    chunks add their weight sums into exact int64 partials, so the result
+    equals the reference, whose weight sums run over the whole K, bit for
+    bit (for 7 and 8 slices, with beta * C)."""
     rng = rng_of(7)
-    S = 8
-    rbs = np.array([20, 12], np.int32)
-    kbs = np.full(170, 100, np.int32)
-    cbs = np.array([16, 9], np.int32)
+    for S in (7, 8):
+        rbs = np.array([20, 12], np.int32)
+        kbs = np.full(200, 100, np.int32)
+        cbs = np.array([16, 9], np.int32)
+        A = make_matrix(rng, rbs, kbs, 1.0, values="wide")
+        B = make_matrix(rng, kbs, cbs, 1.0, values="wide")
+        Cin = make_matrix(rng, rbs, cbs, 1.0)
+        assert 20000 > (2 ** 31 - 1) // (127 * 127 * S)
+        X, _ = _emul(A, B, 0.5, -1.0, Cin, S)
+        R = er.emulate(orc.to_dense(A), orc.to_dense(B), S, 0.5, -1.0, orc.to_dense(Cin))
+        D = orc.to_dense(X)
+        bad = np.argwhere(D != R)
+        assert len(bad) == 0, f"S={S}: {len(bad)} mismatches, first {bad[:3].tolist()}"
+
+
+def test_multi_chunk_k_beyond_int32_closed_form():
+    """Every digit 127 (entries 1 - 2^-49) at K = 20,000: the heaviest weight
+    sum, 7 K 127^2, exceeds 2^31, so the chunked INT32 sums must be carried
+    exactly; the device result equals the reference bit for bit."""
+    S = 7
+    x = 1.0 - 2.0 ** -49
+    rbs = np.array([16], np.int32)
+    kbs = np.full(625, 32, np.int32)
+    cbs = np.array([8], np.int32)
+    A = make_matrix(rng_of(0), rbs, kbs, 1.0, values=lambda r, n: np.full(n, x))
+    B = make_matrix(rng_of(0), kbs, cbs, 1.0, values=lambda r, n: np.full(n, x))
+    X, _ = _emul(A, B, 1.0, 0.0, None, S)
+    R = er.emulate(orc.to_dense(A), orc.to_dense(B), S)
+    assert np.array_equal(orc.to_dense(X), R)
+
+
+def test_subnormal_and_non_finite_rows():
+    """A row of A whose largest entry is subnormal is scaled exactly; a row
+    of A holding Inf and a column of B holding NaN give NaN in their row and
+    column of the product; everything else equals the reference."""
+    rng = rng_of(8)
+    rbs = np.array([8, 8], np.int32)
+    kbs = np.array([16, 16], np.int32)
+    cbs = np.array([8, 8], np.int32)
     A = make_matrix(rng, rbs, kbs, 1.0, values="wide")
     B = make_matrix(rng, kbs, cbs, 1.0, values="wide")
-    X, _ = _emul(A, B, 1.0, 0.0, None, S)
-    R = er.emulate(orc.to_dense(A), orc.to_dense(B), S, kchunk=er.int32_chunk(S))
-    assert er.int32_chunk(S) < 17000
-    assert np.array_equal(orc.to_dense(X), R)
+    Ad = orc.to_dense(A)
+    Bd = orc.to_dense(B)
+    Ad[2, :] = np.ldexp(rng.integers(-127, 128, 32).astype(np.float64), -1074)
+    Ad[11, 5] = np.inf
+    Bd[20, 13] = np.nan
+    A2 = from_dense(Ad, rbs, kbs)
+    B2 = from_dense(Bd, kbs, cbs)
+    X, _ = _emul(A2, B2, 1.0, 0.0, None, 7)
+    R = er.emulate(Ad, Bd, 7)
+    D = orc.to_dense(X)
+    same = (D == R) | (np.isnan(D) & np.isnan(R))
+    assert np.all(same), np.argwhere(~same)[:4].tolist()
+    assert np.all(np.isnan(D[11, :])) and np.all(np.isnan(D[:, 13]))
+    assert np.all(np.isfinite(D[2, :8])) and np.any(D[2, :] != 0)
 
 
 def test_integer_inputs_exact_with_one_slice():

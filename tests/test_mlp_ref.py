@@ -46,3 +46,34 @@ def test_training_learns_a_smooth_target():
             G, _ = ref.grad(P, X[b:b + 64], T[b:b + 64])
             P, M, V = ref.adam_step(P, G, M, V, step, lr=3e-3)
     assert ref.loss(P, X, T) < 0.05 * l0
+
+
+def _adam_constant_gradient_pin(step_fn, steps=12, lr=0.01):
+    """A constant gradient g gives moments m_t = (1 - b1^t) g and
+    v_t = (1 - b2^t) g^2, so the bias-corrected estimates are exactly g and
+    g^2 at every step and t steps move the parameters by t lr g / (|g| + eps)."""
+    g = np.array([3.0, -0.5, 1e-3, -40.0])
+    P = np.zeros(4)
+    M = np.zeros(4)
+    V = np.zeros(4)
+    for t in range(1, steps + 1):
+        P, M, V = step_fn(P, g, M, V, t, lr=lr)
+        want = -t * lr * g / (np.abs(g) + 1e-8)
+        if not np.allclose(P, want, rtol=1e-12, atol=0):
+            return False
+    return True
+
+
+def test_adam_later_steps_closed_form():
+    assert _adam_constant_gradient_pin(ref.adam_step)
+
+
+def test_adam_pin_catches_stale_bias_correction():
+    """Planted mistake: bias correction with the first step's powers at every
+    step (right at step 1, wrong from step 2 on)."""
+    def stale(P, G, M, V, step, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+        M = b1 * M + (1 - b1) * G
+        V = b2 * V + (1 - b2) * G * G
+        return P - lr * (M / (1 - b1)) / (np.sqrt(V / (1 - b2)) + eps), M, V
+
+    assert not _adam_constant_gradient_pin(stale)
