@@ -100,6 +100,30 @@ int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes,
 int bsmm_multiply(double alpha, bsmm_matrix A, bsmm_matrix B, double beta,
                   bsmm_matrix C, double filter_eps, void *stream);
 
+/*
+ * C <- beta*C + alpha*A*B without allocating device memory, for callers
+ * that cannot allocate: code under stream capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arithmetic, paths and options as
+ * bsmm_multiply, with these differences:
+ *   - C's pattern must already contain every product block (e.g. C is the
+ *     output of an earlier bsmm_multiply of the same patterns); C keeps its
+ *     pattern and buffers.  Otherwise BSMM_EINDEX, C untouched.
+ *   - No filter (filter_eps = 0) and no plan is kept for "plan_cache".
+ *   - Every temporary (symbolic counts, product stacks, split-run partial
+ *     blocks, dense panels, emulation slices) is carved from a fixed
+ *     scratch array of 64 MiB in device memory, one per device, held from
+ *     the first call on a device until the process ends.  A multiply whose
+ *     temporaries exceed it fails with BSMM_ERANGE before C is written.
+ *   - Stack classes are launched one by one (no hipGraph is instantiated).
+ * The scratch array keeps the last call's contents and is shared by every
+ * call on the device: calls that overlap on one device (two host threads,
+ * or two streams not ordered with each other) race on it.  The call blocks
+ * the host once to read the product counts, like bsmm_multiply.
+ * Errors: as bsmm_multiply, plus EINDEX (pattern) and ERANGE (scratch).
+ */
+int bsmm_multiply_noalloc(double alpha, bsmm_matrix A, bsmm_matrix B, double beta,
+                          bsmm_matrix C, void *stream);
+
 /* Frees a matrix and its device memory (after synchronising the stream it
  * was last used on).  NULL is accepted and ignored. */
 int bsmm_destroy_matrix(bsmm_matrix m);

@@ -61,6 +61,7 @@ class bsmm_multiply_stats(ctypes.Structure):
 _lib.bsmm_create_matrix.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _vp, ctypes.c_int,
                                     _vp, ctypes.POINTER(_vp)]
 _lib.bsmm_multiply.argtypes = [ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp]
+_lib.bsmm_multiply_noalloc.argtypes = [ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp]
 _lib.bsmm_destroy_matrix.argtypes = [_vp]
 _lib.bsmm_matrix_info.argtypes = [_vp, _i32p, _i32p, _i64p, _i64p]
 _lib.bsmm_copy_out.argtypes = [_vp, _i64p, _i32p, _vp, ctypes.c_int, _vp]
@@ -85,12 +86,12 @@ _lib.bsmm_mlp_adam_step.argtypes = [_i32, _f32p, _f32p, _f32p, _f32p, _i32, ctyp
 _lib.bsmm_mlp_train.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _i32, _i32, ctypes.c_float,
                                 ctypes.c_uint64, _f32p]
 for _f in ("bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
-           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
-           "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
+           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix",
+           "bsmm_matrix_info", "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
            "bsmm_last_stats", "bsmm_inspect_stacks"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("bsmm_create_matrix", "bsmm_multiply", "bsmm_destroy_matrix", "bsmm_matrix_info",
+EXPORTED = ("bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix", "bsmm_matrix_info",
             "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
             "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times",
             "bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params",
@@ -167,6 +168,10 @@ def bsmm_create_matrix(nbr, row_blk_sizes, nbc, col_blk_sizes, nnzb, blk_row_ptr
 
 def bsmm_multiply(alpha, A, B, beta, C, filter_eps=0.0, stream=None):
     _check(_lib.bsmm_multiply(float(alpha), A, B, float(beta), C, float(filter_eps), _stream(stream)))
+
+
+def bsmm_multiply_noalloc(alpha, A, B, beta, C, stream=None):
+    _check(_lib.bsmm_multiply_noalloc(float(alpha), A, B, float(beta), C, _stream(stream)))
 
 
 def bsmm_destroy_matrix(m):

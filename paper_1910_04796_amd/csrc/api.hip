@@ -211,6 +211,9 @@ static int validate_pattern(int32_t nbr, int32_t nbc, int64_t nnzb, const int64_
 static thread_local bsmm_multiply_stats t_stats;
 bsmm_multiply_stats &stats() { return t_stats; }
 
+static thread_local ScratchArena *t_arena = nullptr;
+ScratchArena *&scratch_arena() { return t_arena; }
+
 // Every device buffer of a matrix belongs to the stream that last used it.
 // Before work on stream s touches the matrix, s waits for the work queued
 // on the buffers' current streams, and the buffers pass to s: a buffer

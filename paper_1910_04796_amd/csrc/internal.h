@@ -83,11 +83,23 @@ void *dev_alloc(size_t bytes, hipStream_t s);
 void dev_free(void *p, hipStream_t s);
 int pool_release_all();
 
-// A device buffer owned by RAII (freed back to the pool).
+// A fixed region of device memory that temporaries are carved from (bump
+// order, 256-byte aligned, never returned) while an allocation-free multiply
+// runs on the calling thread.
+struct ScratchArena {
+    char *base = nullptr;
+    size_t cap = 0, used = 0;
+};
+// The calling thread's active arena, or null (temporaries from the pool).
+ScratchArena *&scratch_arena();
+
+// A device buffer owned by RAII (freed back to the pool; a buffer carved
+// from a scratch arena is only forgotten).
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
     hipStream_t s = nullptr;
+    bool borrowed = false;  // carved from a scratch arena
     DevBuf() = default;
     DevBuf(const DevBuf &) = delete;
     DevBuf &operator=(const DevBuf &) = delete;
@@ -95,16 +107,17 @@ struct DevBuf {
     DevBuf &operator=(DevBuf &&o) noexcept {
         if (this != &o) {
             reset();
-            p = o.p; bytes = o.bytes; s = o.s;
-            o.p = nullptr; o.bytes = 0;
+            p = o.p; bytes = o.bytes; s = o.s; borrowed = o.borrowed;
+            o.p = nullptr; o.bytes = 0; o.borrowed = false;
         }
         return *this;
     }
     ~DevBuf() { reset(); }
     void reset() {
-        if (p) dev_free(p, s);
+        if (p && !borrowed) dev_free(p, s);
         p = nullptr;
         bytes = 0;
+        borrowed = false;
     }
     // Ensures capacity >= n bytes (contents are not preserved).
     int reserve(size_t n, hipStream_t st) {
@@ -112,6 +125,19 @@ struct DevBuf {
         if (n <= bytes && p) return BSMM_OK;
         reset();
         size_t want = n ? n : 1;
+        if (ScratchArena *ar = scratch_arena()) {
+            const size_t at = (ar->used + 255) & ~size_t(255);
+            if (at > ar->cap || want > ar->cap - at) {
+                set_error(BSMM_ERANGE, "temporaries exceed the %zu-byte scratch region (%zu more bytes)",
+                          ar->cap, want);
+                return BSMM_ERANGE;
+            }
+            p = ar->base + at;
+            ar->used = at + want;
+            bytes = want;
+            borrowed = true;
+            return BSMM_OK;
+        }
         p = dev_alloc(want, st);
         if (!p) {
             set_error(BSMM_ENOMEM, "device allocation of %zu bytes failed", want);
@@ -352,6 +378,14 @@ int64_t emul_chunk(int S);
 
 // ---------------------------------------------------------------- filter
 int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s);
+
+// ------------------------------------------------------- fixed pattern
+// C <- beta*C + alpha*A*B into C's existing pattern and buffers, with every
+// temporary carved from the active scratch arena (no filter, no plan kept,
+// stack classes launched one by one instead of through a hipGraph).
+// EINDEX when C's pattern misses a product block (C untouched).
+int multiply_fixed_pattern(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
+                           bsmm_matrix_s *C, hipStream_t s);
 
 // --------------------------------------------------------------- helpers
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }

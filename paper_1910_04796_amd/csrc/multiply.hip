@@ -178,6 +178,26 @@ struct Plan {
 };
 void free_plan(Plan *p) { delete p; }
 
+// Limits of the stack path, checked on the host before any work is queued:
+// a product entry carries k in 16 bits and the count and fill phases map
+// C's block columns in LDS.
+int check_stack_limits(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                       const Options &o) {
+    const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
+    if (o.path == 3 || dense) return BSMM_OK;
+    if (A->max_cbs > kMaxStackK) {
+        set_error(BSMM_ENOTSUP, "stack path: block columns of A hold at most %d columns (found %d)",
+                  kMaxStackK, A->max_cbs);
+        return BSMM_ENOTSUP;
+    }
+    if (C->nbc > kMaxStackCols) {
+        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns (found %d)",
+                  kMaxStackCols, C->nbc);
+        return BSMM_ENOTSUP;
+    }
+    return BSMM_OK;
+}
+
 namespace {
 
 // Stack path over panels of consecutive C block rows whose products fit
@@ -240,26 +260,6 @@ int numeric(int path, bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doub
             BSMM_TRY(scale_blocks(C, st.c_count.as<int64_t>(), beta, s));
         return BSMM_OK;
     }
-}
-
-// Limits of the stack path, checked on the host before any work is queued:
-// a product entry carries k in 16 bits and the count and fill phases map
-// C's block columns in LDS.
-int check_stack_limits(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
-                       const Options &o) {
-    const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
-    if (o.path == 3 || dense) return BSMM_OK;
-    if (A->max_cbs > kMaxStackK) {
-        set_error(BSMM_ENOTSUP, "stack path: block columns of A hold at most %d columns (found %d)",
-                  kMaxStackK, A->max_cbs);
-        return BSMM_ENOTSUP;
-    }
-    if (C->nbc > kMaxStackCols) {
-        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns (found %d)",
-                  kMaxStackCols, C->nbc);
-        return BSMM_ENOTSUP;
-    }
-    return BSMM_OK;
 }
 
 int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
@@ -331,6 +331,40 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
 }
 
 }  // namespace
+
+int multiply_fixed_pattern(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
+                           bsmm_matrix_s *C, hipStream_t s) {
+    bsmm_multiply_stats &stt = stats();
+    stt = bsmm_multiply_stats{};
+    Options o = options();
+    SymbolicTotals tot;
+    bool changed = false;
+    NewPattern np;
+    DevBuf row_elems;
+    BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s));
+    if (changed) {
+        set_error(BSMM_EINDEX, "C's pattern misses product blocks (%lld blocks needed, %lld stored)",
+                  (long long)tot.nnzb, (long long)C->nnzb);
+        return BSMM_EINDEX;
+    }
+    const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
+    const int path = (alpha == 0.0 || tot.nprod == 0) ? 0 : o.path == 3 ? 3 : dense ? 2 : 1;
+    // Whole stacks in one piece: row panels would reserve again per panel,
+    // after earlier panels have already written C.
+    o.stack_panel = 0;
+    Stacks st;
+    st.n_prod = tot.nprod;
+    StackExec ex;
+    BSMM_TRY(numeric(path, A, B, C, alpha, beta, o, st, ex, false, &stt.n_row_panels, s));
+    stt.path = path;
+    stt.c_nnzb_before = stt.c_nnzb_after = C->nnzb;
+    stt.n_products = tot.nprod;
+    stt.flops = tot.flops;
+    stt.n_runs = st.n_runs;
+    stt.n_classes = active_classes(st);
+    return BSMM_OK;
+}
+
 }  // namespace bsmm
 
 using namespace bsmm;

@@ -536,7 +536,9 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
             b0 = b1;
         }
     }
-    if (tuned && chunk <= 0 && launches.size() > 1) {
+    // Instantiating a graph may allocate device memory: a multiply running
+    // on a scratch arena launches its classes one by one instead.
+    if (tuned && chunk <= 0 && launches.size() > 1 && !scratch_arena()) {
         BSMM_TRY(build_graph(launches, A, B, C, st, alpha, beta, &ex->exec));
         BSMM_HIP(hipEventCreateWithFlags(&ex->done, hipEventDisableTiming));
     }
