@@ -2,19 +2,21 @@
 """Benchmark of the local block-sparse FP64 multiply on one MI355X.
 
 Headline workload (one step = one full bsmm_multiply, inputs resident in HBM):
-dense square product N = 8192 stored as a 256 x 256 grid of 32 x 32 blocks,
-every block present, values U[-1, 1], C = 1.0 * A * B + 0.0 * C.  The
-library densifies (merge into panels, one FP64 MFMA GEMM with the split back
-into blocks fused into its epilogue).  `value` is that path's FP64-equivalent
-GFLOP/s (sum of 2 m n k over the block products per second).
+the banded product of uneven blocks, N ~ 50,000 with block-row and
+block-column sizes drawn from {5, 13, 23, 32}, 30 % of the block positions
+stored, magnitudes decaying as exp(-|I-J|/50), blocks whose magnitude
+envelope falls below 1e-10 not stored, C = 1.0 * A * B with the result
+filtered at eps = 1e-10.  `value` is the FP64-equivalent GFLOP/s (sum of
+2 m n k over the block products per second) of the tuned stack path; the
+plain stack path on the same inputs is reported beside it.
 
-Comparison legs on the same workload (extra JSON fields): the blocked path
-with the plain and the tuned small-block kernels (the paper's
-T_blocked / T_densified), and the split-precision FP64 emulation on INT8
-matrix cores.  Further legs: the banded uneven workload (block sizes from
-{5,13,23,32}, N ~ 50,000, 1 % and 10 % occupancy) plain vs tuned, and the
-460 x 460 sparse case's latency.  The CPU reference is timed on a bounded
-sample of the headline workload and checks the GPU results on those rows.
+Further legs (extra JSON fields, each with a warm-up and median/min over
+repeated multiplies): the dense N = 8192 product in 32-blocks (densified
+GEMM, blocked plain and tuned, INT8 split-precision emulation), the
+split-precision workload N = 16384 (native vs emulated), the banded product
+at 1 % and 10 %, and the 460 x 460 sparse case's latency.  The CPU
+reference is timed on a bounded sample of the headline workload and checks
+the GPU results on those rows.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -31,28 +33,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "FP64-equiv GFLOP/s of local C+=A·B, tuned/emulated vs plain, rel err≤1e-12"
-N, BS = 8192, 32
-PEAK_FP64_MFMA_TFLOPS = 78.6
+PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 matrix and vector peak
+HEADLINE_OCC = 0.30
+HEADLINE_EPS = 1e-10
+HEADLINE_NAME = "banded_uneven_n50000_b5-13-23-32_occ30_eps1e-10"
+SAMPLE_ROWS = 64              # CPU baseline: contiguous block rows of the headline C
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def traffic_from_profile():
-    """HBM bytes per GEMM launch from the committed counter summary, valid
-    only while the GEMM source is unchanged since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", "dgemm_dense_square_8192_traffic.json")
-    src = os.path.join(ROOT, "paper_1910_04796_amd", "csrc", "dense.hip")
-    try:
-        with open(path) as f:
-            t = json.load(f)
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if t.get("source_sha256") != sha:
-            return None
-        return t.get("bytes_per_launch")
-    except (OSError, ValueError):
-        return None
+def set_opts(bsmm, **kw):
+    for k, v in kw.items():
+        bsmm.bsmm_set_option(k, str(v))
 
 
 def timed(torch, fn, reps):
@@ -65,9 +59,92 @@ def timed(torch, fn, reps):
     return (time.perf_counter() - t0) * 1e3 / reps
 
 
-def sampled_err(orc, X, A, B, rows, threads, eps=0.0):
-    """Largest relative error of the host copy X against the reference on
-    the given block rows (inf if a row's pattern differs)."""
+def timed_calls(torch, fn, warmup, reps):
+    """Each call bracketed by device syncs: median, min, max and mean (ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t0) * 1e3)
+    return {"median_ms": round(float(np.median(ts)), 4), "min_ms": round(min(ts), 4),
+            "max_ms": round(max(ts), 4), "mean_ms": round(float(np.mean(ts)), 4),
+            "reps": reps, "warmup": warmup}
+
+
+def gflops(F, ms):
+    return round(F / (ms * 1e-3) / 1e9, 1)
+
+
+def profile_json(name, src):
+    """A committed counter summary, valid only while the kernel source is
+    unchanged since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", name)
+    try:
+        with open(path) as f:
+            t = json.load(f)
+        sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        return t if t.get("source_sha256") == sha else None
+    except (OSError, ValueError):
+        return None
+
+
+def mfma_padding(A, B):
+    """Algorithmic flops F = sum 2 m n k over the block products, and the
+    flops the small-block MFMA kernels issue for them: m and n rounded up to
+    16-row / 16-column tiles, k to 16-deep steps.  Both sums factor over K:
+    sum_K f(k_K) * (sum over A's blocks in column K of g(m_I)) * (sum over
+    B's blocks in row K of h(n_J))."""
+    rbs, kbs, cbs = (np.asarray(x, np.int64) for x in (A.rbs, A.cbs, B.cbs))
+    a_rows = np.repeat(np.arange(len(rbs)), np.diff(A.row_ptr))
+    a_m = np.bincount(A.col_ind, weights=rbs[a_rows], minlength=len(kbs))
+    a_mp = np.bincount(A.col_ind, weights=16 * np.ceil(rbs[a_rows] / 16), minlength=len(kbs))
+    b_rows = np.repeat(np.arange(len(kbs)), np.diff(B.row_ptr))
+    b_n = np.bincount(b_rows, weights=cbs[B.col_ind], minlength=len(kbs))
+    b_np = np.bincount(b_rows, weights=16 * np.ceil(cbs[B.col_ind] / 16), minlength=len(kbs))
+    F = 2.0 * float(np.sum(kbs * a_m * b_n))
+    issued = 2.0 * float(np.sum(16 * np.ceil(kbs / 16) * a_mp * b_np))
+    return F, issued
+
+
+def rows_slice(torch, M, r0, r1):
+    """Block rows [r0, r1) of a matrix on the device as a host block-CSR
+    (the data go through a device buffer, only the rows reach the host)."""
+    from paper_1910_04796_amd import bsmm
+    from synth import BlockCSR, block_elems
+    nbr, nbc, nnzb, ne = M.info()
+    dev = torch.empty(max(ne, 1), dtype=torch.float64, device="cuda")
+    rp, ci, _ = bsmm.bsmm_copy_out(M.handle, device_out=dev)
+    sizes = block_elems(M.rbs, M.cbs, rp, ci)
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    a0, a1 = int(rp[r0]), int(rp[r1])
+    data = dev[int(start[a0]):int(start[a1])].cpu().numpy()
+    del dev
+    return BlockCSR(M.rbs[r0:r1], M.cbs, rp[r0:r1 + 1] - rp[r0], ci[a0:a1].astype(np.int32), data)
+
+
+def rel_err_same_pattern(orc, X, R):
+    """Relative error of X against R (inf if the block patterns differ)."""
+    if not (np.array_equal(X.row_ptr, R.row_ptr) and np.array_equal(X.col_ind, R.col_ind)):
+        return float("inf")
+    return orc.rel_err(X.data, R.data)
+
+
+def sampled_err(orc, torch, M, A, B, rows, threads, eps=0.0):
+    """Largest relative error of the device matrix M against the reference
+    on the given block rows (inf if a row's pattern differs)."""
+    errs = []
+    for r in rows:
+        R = orc.multiply(1.0, A, B, 0.0, filter_eps=eps, rows=(r, r + 1), nthreads=threads)
+        errs.append(rel_err_same_pattern(orc, rows_slice(torch, M, r, r + 1), R))
+    return max(errs)
+
+
+def sampled_err_host(orc, X, A, B, rows, threads, eps=0.0):
+    """As sampled_err, for a host copy X of the whole result."""
     sizes = orc.block_sizes(X.rbs, X.cbs, X.row_ptr, X.col_ind)
     start = np.concatenate([[0], np.cumsum(sizes)])
     errs = []
@@ -81,68 +158,279 @@ def sampled_err(orc, X, A, B, rows, threads, eps=0.0):
     return max(errs)
 
 
-def all_configs(bsmm, torch, stream):
-    """The remaining workloads of the method's evaluation set: rectangular
-    dense (4096 x 65536 times 65536 x 4096), banded uneven blocks at 30 %,
-    and the sparse split-precision case (1,424^2 blocks of 23, 20 %, entries
-    sign * 10^U(-6,2)).  Returns the timings and, for the reference check,
-    host copies of the results with their inputs."""
-    from synth import banded_uneven, dense_rect, wide_range_sparse
+def headline(bsmm, torch, stream, args):
+    """The banded 30 % product: tuned stacks (timed as the contract says),
+    plain stacks beside them, the stack kernels' device time, and the
+    MFMA padding of the small-block kernels."""
+    from synth import banded_uneven
+    t0 = time.perf_counter()
+    A, B = banded_uneven(seed=0, occupancy=HEADLINE_OCC, target=50000)
+    log(f"headline inputs: {A.nnzb} + {B.nnzb} blocks ({time.perf_counter() - t0:.1f} s)")
+    F, issued = mfma_padding(A, B)
+    MA, MB = bsmm.Matrix.from_blocks(A), bsmm.Matrix.from_blocks(B)
+    res = {}
+    set_opts(bsmm, path="stack", stack_kernel="tuned")
+    MC = bsmm.Matrix.empty(A.rbs, B.cbs)
+
+    def step():
+        bsmm.multiply(1.0, MA, MB, 0.0, MC, HEADLINE_EPS, stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"warmup done ({args.warmup} steps)")
+    bsmm.bsmm_set_option("time_kernels", "1")
+    bsmm.bsmm_kernel_times(reset=True)
+    ms_per_step = timed(torch, step, args.steps)
+    _, _, stack_ms, stack_n = bsmm.bsmm_kernel_times(reset=True)
+    bsmm.bsmm_set_option("time_kernels", "0")
+    st = bsmm.bsmm_last_stats()
+    assert abs(st["flops"] - F) <= 1e-9 * F, (st["flops"], F)
+    log(f"tuned: {ms_per_step:.3f} ms/step, {gflops(F, ms_per_step)} GFLOP/s")
+    res["tuned"] = {"ms_per_step": round(ms_per_step, 4), "gflops": gflops(F, ms_per_step),
+                    "stack_kernel_ms": round(stack_ms / max(stack_n, 1), 4),
+                    "stack_launches": stack_n}
+    res["stats"] = st
+    res["C_tuned"] = MC
+    set_opts(bsmm, stack_kernel="plain")
+    MP = bsmm.Matrix.empty(A.rbs, B.cbs)
+    t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MP, HEADLINE_EPS, stream), 1,
+                    args.plain_reps)
+    res["plain"] = dict(t, gflops=gflops(F, t["median_ms"]))
+    log(f"plain: {t['median_ms']:.3f} ms (median of {args.plain_reps})")
+    res["C_plain"] = MP
+    set_opts(bsmm, path="auto", stack_kernel="plain")
+    MA.close()
+    MB.close()
+    res["F"], res["issued"] = F, issued
+    res["A"], res["B"] = A, B
+    return res
+
+
+def cpu_baseline(orc, torch, res, threads_all):
+    """The reference on SAMPLE_ROWS contiguous block rows of the headline C
+    (seeded start) on every core the process may use, and on fewer rows
+    with one thread; the tuned and plain GPU results are checked on the
+    sampled rows."""
+    A, B = res["A"], res["B"]
+    nbr = len(A.rbs)
+    r0 = int(np.random.default_rng(12345).integers(0, nbr - SAMPLE_ROWS))
+    r1 = r0 + SAMPLE_ROWS
+    a_rows = np.repeat(np.arange(nbr), np.diff(A.row_ptr))
+    flops_rows = None
+    orc.multiply(1.0, A, B, 0.0, filter_eps=HEADLINE_EPS, rows=(r0, r0 + 2), nthreads=threads_all)
+    c0 = time.perf_counter()
+    R = orc.multiply(1.0, A, B, 0.0, filter_eps=HEADLINE_EPS, rows=(r0, r1), nthreads=threads_all)
+    t_all = time.perf_counter() - c0
+    # flops of the sampled rows: per A block (I, K) in the rows, 2 m k times
+    # the columns of B's row K
+    kbs = np.asarray(A.cbs, np.int64)
+    cb = np.asarray(B.cbs, np.int64)
+    b_rows = np.repeat(np.arange(len(kbs)), np.diff(B.row_ptr))
+    b_n = np.bincount(b_rows, weights=cb[B.col_ind], minlength=len(kbs))
+    sel = (a_rows >= r0) & (a_rows < r1)
+    m = np.asarray(A.rbs, np.int64)[a_rows[sel]]
+    k = kbs[A.col_ind[sel]]
+    flops_rows = 2.0 * float(np.sum(m * k * b_n[A.col_ind[sel]]))
+    one_rows = 4
+    c0 = time.perf_counter()
+    orc.multiply(1.0, A, B, 0.0, filter_eps=HEADLINE_EPS, rows=(r0, r0 + one_rows), nthreads=1)
+    t_one = time.perf_counter() - c0
+    sel1 = (a_rows >= r0) & (a_rows < r0 + one_rows)
+    m1 = np.asarray(A.rbs, np.int64)[a_rows[sel1]]
+    k1 = kbs[A.col_ind[sel1]]
+    flops_one = 2.0 * float(np.sum(m1 * k1 * b_n[A.col_ind[sel1]]))
+    cpu = {"value": round(flops_rows / t_all / 1e9, 3), "unit": "GFLOP/s", "cores": threads_all,
+           "kind": "oracle",
+           "sample": f"block rows {r0}..{r1 - 1} of {nbr} of the headline product "
+                     f"({flops_rows:.3e} flop, {t_all:.1f} s on {threads_all} threads)",
+           "value_1thread": round(flops_one / t_one / 1e9, 3),
+           "sample_1thread": f"block rows {r0}..{r0 + one_rows - 1} ({flops_one:.3e} flop, {t_one:.1f} s)",
+           "full_product_estimate_s": round(t_all * res["F"] / flops_rows, 1)}
+    errs = {"tuned": rel_err_same_pattern(orc, rows_slice(torch, res["C_tuned"], r0, r1), R),
+            "plain": rel_err_same_pattern(orc, rows_slice(torch, res["C_plain"], r0, r1), R)}
+    return cpu, errs, (r0, r1)
+
+
+def extras_dense(bsmm, torch, stream, args):
+    """Dense N = 8192 in 32-blocks: densified GEMM (with the GEMM kernel's
+    own roofline), blocked plain and tuned stacks, INT8 emulation."""
+    from synth import dense_square
+    N, BS = 8192, 32
+    A, B = dense_square(seed=0, n=N, bs=BS)
+    MA, MB = bsmm.Matrix.from_blocks(A), bsmm.Matrix.from_blocks(B)
+    F = 2.0 * N ** 3
+    out = {"N": N, "block": BS, "flops_per_multiply": F}
+    keep = {}
+
+    def leg(name, reps, **opts):
+        set_opts(bsmm, **opts)
+        MC = bsmm.Matrix.empty(A.rbs, B.cbs)
+        bsmm.bsmm_set_option("time_kernels", "1")
+        bsmm.bsmm_kernel_times(reset=True)
+        t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream), 2, reps)
+        g_ms, g_n, s_ms, s_n = bsmm.bsmm_kernel_times(reset=True)
+        bsmm.bsmm_set_option("time_kernels", "0")
+        r = dict(t, gflops=gflops(F, t["median_ms"]))
+        if g_n:
+            r["gemm_kernel_ms"] = round(g_ms / g_n, 4)
+        if s_n:
+            r["stack_kernel_ms"] = round(s_ms / s_n, 4)
+        out[name] = r
+        log(f"dense 8192 {name}: {t['median_ms']:.3f} ms")
+        set_opts(bsmm, path="auto", stack_kernel="plain", dense_kb=16)
+        return MC
+
+    keep["densified"] = leg("densified", args.reps * 2, path="dense")
+    g = out["densified"]["gemm_kernel_ms"]
+    out["densified"]["gemm_roofline"] = {
+        "kernel": "k_dgemm_mfma", "achieved": round(F / (g * 1e-3) / 1e12, 3), "peak": PEAK_FP64_TFLOPS,
+        "unit": "TFLOP/s", "frac": round(F / (g * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+    tr = profile_json("dgemm_dense_square_8192_traffic.json", "paper_1910_04796_amd/csrc/dense.hip")
+    out["densified"]["gemm_roofline"]["traffic"] = tr.get("bytes_per_launch") if tr else None
+    leg("densified_k32", args.reps, path="dense", dense_kb=32).close()
+    for kern in ("plain", "tuned"):
+        leg(f"blocked_{kern}", args.reps, path="stack", stack_kernel=kern).close()
+        out[f"blocked_{kern}"]["t_blocked_over_t_densified"] = round(
+            out[f"blocked_{kern}"]["median_ms"] / out["densified"]["median_ms"], 3)
+    keep["emulated_int8_s7"] = leg("emulated_int8_s7", args.reps, path="emul", emul_slices=7)
+    e = out["emulated_int8_s7"]
+    e["speedup_vs_densified_fp64"] = round(out["densified"]["median_ms"] / e["median_ms"], 3)
+    e["int8_tops_achieved"] = round(28 * F / (e["gemm_kernel_ms"] * 1e-3) / 1e12, 1)
+    e["int8_peak_tops"] = 5000.0
+    MA.close()
+    MB.close()
+    return out, keep, A, B
+
+
+def extras_wide(bsmm, torch, stream, args, orc, threads):
+    """Split-precision workload: N = 16384 in 32-blocks, entries
+    sign * 10^U(-6, 2); native FP64 dense vs INT8 emulation (7 slices)."""
+    from synth import wide_range_dense
+    W1, W2 = wide_range_dense(seed=0, n=16384, bs=32)
+    MW1, MW2 = bsmm.Matrix.from_blocks(W1), bsmm.Matrix.from_blocks(W2)
+    F = 2.0 * 16384 ** 3
+    out = {"N": 16384, "values": "sign * 10^U(-6,2)", "slices": 7, "flops_per_multiply": F}
+    Xs = {}
+    for name, opts in (("native_fp64", dict(path="dense")), ("emulated_int8", dict(path="emul", emul_slices=7))):
+        set_opts(bsmm, **opts)
+        MC = bsmm.Matrix.empty(W1.rbs, W2.cbs)
+        t = timed_calls(torch, lambda: bsmm.multiply(1.0, MW1, MW2, 0.0, MC, 0.0, stream), 1, args.reps)
+        out[name] = dict(t, gflops_fp64_equiv=gflops(F, t["median_ms"]))
+        Xs[name] = MC.to_host()
+        MC.close()
+        log(f"wide-range 16384 {name}: {t['median_ms']:.3f} ms")
+    set_opts(bsmm, path="auto")
+    out["speedup_emulated_vs_native"] = round(out["native_fp64"]["median_ms"] /
+                                              out["emulated_int8"]["median_ms"], 3)
+    Xn, Xe = Xs["native_fp64"].data, Xs["emulated_int8"].data
+    out["rel_err_emulated_vs_native"] = float(np.linalg.norm(Xe - Xn) / np.linalg.norm(Xn))
+    if orc is not None:
+        out["rel_err_emulated_rows_5_200_511"] = sampled_err_host(orc, Xs["emulated_int8"], W1, W2,
+                                                                  (5, 200, 511), threads)
+        out["rel_err_native_rows_5_200_511"] = sampled_err_host(orc, Xs["native_fp64"], W1, W2,
+                                                                (5, 200, 511), threads)
+    MW1.close()
+    MW2.close()
+    return out
+
+
+def extras_banded(bsmm, torch, stream, args, orc, threads):
+    """Banded uneven blocks at 1 % and 10 %: plain vs tuned stacks."""
+    from synth import banded_uneven
+    out = {}
+    for occ in (0.01, 0.10):
+        U, V = banded_uneven(seed=0, occupancy=occ, target=50000)
+        MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
+        r = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
+        for kern in ("plain", "tuned"):
+            set_opts(bsmm, path="stack", stack_kernel=kern)
+            MW = bsmm.Matrix.empty(U.rbs, V.cbs)
+            t = timed_calls(torch, lambda: bsmm.multiply(1.0, MU, MV, 0.0, MW, HEADLINE_EPS, stream), 2,
+                            args.reps)
+            st = bsmm.bsmm_last_stats()
+            r[kern] = dict(t, gflops=gflops(st["flops"], t["median_ms"]))
+            r["flops_per_multiply"] = st["flops"]
+            r["products"] = st["n_products"]
+            r["classes"] = st["n_classes"]
+            if orc is not None and kern == "tuned":
+                nb = len(U.rbs)
+                r["tuned"]["rel_err_sampled_rows"] = sampled_err(orc, torch, MW, U, V,
+                                                                 (3, nb // 2, nb - 4), threads, HEADLINE_EPS)
+            MW.close()
+        r["tuned_speedup"] = round(r["plain"]["median_ms"] / r["tuned"]["median_ms"], 3)
+        out[f"banded_uneven_{int(round(occ * 100))}pct"] = r
+        log(f"banded {occ}: plain {r['plain']['median_ms']} ms, tuned {r['tuned']['median_ms']} ms")
+        MU.close()
+        MV.close()
+    set_opts(bsmm, path="auto", stack_kernel="plain")
+    return out
+
+
+def extras_tiny(bsmm, torch, stream, args):
+    """460 x 460 in 23-blocks, 10 %: latency of one multiply."""
+    from synth import sparse_uniform
+    S1, S2 = sparse_uniform(seed=0)
+    M1, M2 = bsmm.Matrix.from_blocks(S1), bsmm.Matrix.from_blocks(S2)
+    tiny = {}
+    for kern in ("plain", "tuned"):
+        set_opts(bsmm, path="stack", stack_kernel=kern)
+        M3 = bsmm.Matrix.empty(S1.rbs, S2.cbs)
+        run3 = lambda: bsmm.multiply(1.0, M1, M2, 0.0, M3, 0.0, stream)
+        tiny[kern + "_us"] = round(1e3 * timed_calls(torch, run3, 3, 20)["median_ms"], 1)
+        if kern == "tuned":
+            # Repeated multiply into the same C with the plan cache: the
+            # symbolic phase and stack build are skipped and the planned
+            # hipGraph is replayed (same result, see the plan-cache tests).
+            bsmm.bsmm_set_option("plan_cache", "1")
+            tiny["tuned_plan_cache_us"] = round(1e3 * timed_calls(torch, run3, 3, 20)["median_ms"], 1)
+            bsmm.bsmm_set_option("plan_cache", "0")
+        M3.close()
+    set_opts(bsmm, path="auto", stack_kernel="plain")
+    M1.close()
+    M2.close()
+    return tiny
+
+
+def all_configs(bsmm, torch, stream, args):
+    """The remaining workloads of the evaluation set: rectangular dense
+    (4096 x 65536 times 65536 x 4096) and the sparse split-precision case
+    (1,424^2 blocks of 23, 20 %, entries sign * 10^U(-6,2)).  Returns the
+    timings and, for the reference check, host copies of the results with
+    their inputs."""
+    from synth import dense_rect, wide_range_sparse
     res, keep = {}, {}
 
     def time_path(MA, MB, rbs, cbs, eps, reps, **opts):
         set_opts(bsmm, **opts)
         MC = bsmm.Matrix.empty(rbs, cbs)
-
-        def run():
-            bsmm.multiply(1.0, MA, MB, 0.0, MC, eps, stream)
-
-        run()
+        t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MC, eps, stream), 1, reps)
         st = bsmm.bsmm_last_stats()
-        ms = timed(torch, run, reps)
         set_opts(bsmm, path="auto", stack_kernel="plain")
-        return MC, ms, st
+        return MC, t, st
 
     A, B = dense_rect(seed=0)
     MA, MB = bsmm.Matrix.from_blocks(A), bsmm.Matrix.from_blocks(B)
-    MC, ms, st = time_path(MA, MB, A.rbs, B.cbs, 0.0, 3, path="auto")
+    MC, t, st = time_path(MA, MB, A.rbs, B.cbs, 0.0, args.reps, path="auto")
     Fr = 2.0 * 4096 * 4096 * 65536
-    res["dense_rect_4096x4096x65536"] = {"path": st["path"], "ms_per_step": round(ms, 3),
-                                         "gflops": round(Fr / (ms * 1e-3) / 1e9, 1)}
+    res["dense_rect_4096x4096x65536"] = dict(t, path=st["path"], gflops=gflops(Fr, t["median_ms"]))
     keep["rect"] = (MC.to_host(), A, B, 0.0, (0, 61, 127))
-    log(f"dense rect: {ms:.3f} ms")
+    log(f"dense rect: {t['median_ms']:.3f} ms")
     for M in (MA, MB, MC):
         M.close()
-
-    U, V = banded_uneven(seed=0, occupancy=0.30, target=50000)
-    MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
-    b30 = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
-    for kern in ("plain", "tuned"):
-        MW, ms, st = time_path(MU, MV, U.rbs, V.cbs, 1e-10, 2, path="stack", stack_kernel=kern)
-        b30[kern] = {"ms_per_step": round(ms, 3), "gflops": round(st["flops"] / (ms * 1e-3) / 1e9, 1)}
-        b30["flops_per_step"] = st["flops"]
-        b30["products"] = st["n_products"]
-        if kern == "tuned":
-            keep["banded30"] = (MW.to_host(), U, V, 1e-10, (3, len(U.rbs) // 2, len(U.rbs) - 4))
-        MW.close()
-        log(f"banded 0.3 {kern}: {ms:.3f} ms")
-    b30["tuned_speedup"] = round(b30["plain"]["ms_per_step"] / b30["tuned"]["ms_per_step"], 3)
-    res["banded_uneven_30pct"] = b30
-    MU.close()
-    MV.close()
-    del U, V
 
     S1, S2 = wide_range_sparse(seed=0)
     M1, M2 = bsmm.Matrix.from_blocks(S1), bsmm.Matrix.from_blocks(S2)
     sp = {"N": int(np.sum(S1.rbs)), "block": 23, "occupancy": 0.2, "values": "sign * 10^U(-6,2)"}
-    for name, opts in (("native_fp64_stack_tuned", dict(path="stack", stack_kernel="tuned")),
+    for name, opts in (("native_fp64_stack_plain", dict(path="stack", stack_kernel="plain")),
+                       ("native_fp64_stack_tuned", dict(path="stack", stack_kernel="tuned")),
                        ("emulated_int8_densified", dict(path="emul", emul_slices=7))):
-        MS, ms, st = time_path(M1, M2, S1.rbs, S2.cbs, 0.0, 2, **opts)
-        sp[name] = {"ms_per_step": round(ms, 3), "gflops_fp64_equiv": round(st["flops"] / (ms * 1e-3) / 1e9, 1)}
-        sp["flops_per_step"] = st["flops"]
+        MS, t, st = time_path(M1, M2, S1.rbs, S2.cbs, 0.0, args.reps, **opts)
+        sp[name] = dict(t, gflops_fp64_equiv=gflops(st["flops"], t["median_ms"]))
+        sp["flops_per_multiply"] = st["flops"]
         keep["sparse_" + name] = (MS.to_host(), S1, S2, 0.0, (3, 700, 1420))
         MS.close()
-        log(f"sparse split-precision workload {name}: {ms:.3f} ms")
+        log(f"sparse split-precision workload {name}: {t['median_ms']:.3f} ms")
     res["sparse_wide_range_32752_b23"] = sp
     M1.close()
     M2.close()
@@ -213,7 +501,7 @@ def paper_workloads(bsmm, torch, stream, names, threads):
                 X = MC.to_host()
                 MC.close()
                 rows = (0, len(ms_) - 1)
-                r[mode]["rel_err_sampled_rows"] = sampled_err(orc, X, A, B, rows, threads)
+                r[mode]["rel_err_sampled_rows"] = sampled_err_host(orc, X, A, B, rows, threads)
                 r[mode]["sampled_block_rows"] = list(rows)
                 log(f"{name} b{bs} {mode}: rel err {r[mode]['rel_err_sampled_rows']:.2e} on block rows {rows}")
                 del X
@@ -229,21 +517,17 @@ def paper_workloads(bsmm, torch, stream, names, threads):
     return out
 
 
-def set_opts(bsmm, **kw):
-    for k, v in kw.items():
-        bsmm.bsmm_set_option(k, str(v))
-
-
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--reps", type=int, default=5, help="repetitions of every extra leg")
+    ap.add_argument("--plain-reps", type=int, default=3, help="repetitions of the plain headline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-blocked", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the emulation, uneven and tiny legs")
+    ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--all-configs", action="store_true",
-                    help="also run the rectangular dense, 30 %% banded and sparse split-precision workloads")
+                    help="also run the rectangular dense and sparse split-precision workloads")
     ap.add_argument("--paper-workloads", default="",
                     help="only run the paper's products: comma list of " + ", ".join(PAPER_SHAPES))
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -258,9 +542,9 @@ def main():
     import torch
 
     from paper_1910_04796_amd import bsmm
-    from synth import banded_uneven, dense_square, sparse_uniform, wide_range_dense
 
     torch.cuda.set_device(0)
+    threads = len(os.sched_getaffinity(0))
     if args.calibrate_copy:
         # A plain copy of known size: 1 GiB read + 1 GiB written per launch.
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")
@@ -279,266 +563,88 @@ def main():
         bad = [x for x in names if x not in PAPER_SHAPES]
         if bad:
             sys.exit(f"bench.py: unknown paper workload(s) {bad}")
-        threads = min(len(os.sched_getaffinity(0)), 16)
         res = paper_workloads(bsmm, torch, stream, names, threads)
         print(json.dumps({"paper_workloads": res, "dtype": "f64", "data": "synthetic", "n_gpus": 1}),
               flush=True)
         bsmm.bsmm_set_allocator()
         return
-    log("generating inputs")
-    A, B = dense_square(seed=0, n=N, bs=BS)
-    MA = bsmm.Matrix.from_blocks(A)
-    MB = bsmm.Matrix.from_blocks(B)
-    MC = bsmm.Matrix.empty(A.rbs, B.cbs)
-    F = 2.0 * N ** 3
 
-    def step(C=MC):
-        bsmm.multiply(1.0, MA, MB, 0.0, C, 0.0, stream)
+    res = headline(bsmm, torch, stream, args)
+    F = res["F"]
+    st = res["stats"]
+    tuned = res["tuned"]
+    k_ms = tuned["stack_kernel_ms"]
+    achieved = F / (k_ms * 1e-3) / 1e12
+    tr = profile_json("smm_sched_banded30_traffic.json", "paper_1910_04796_amd/csrc/smm.hip")
+    roofline = {"bound": "mfma", "kernel": "k_smm_mfma_sched (tuned stack launch)",
+                "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "kernel_ms": k_ms,
+                "launches": tuned["stack_launches"],
+                "traffic": tr.get("bytes_per_launch") if tr else None,
+                "mfma_issued_over_algorithmic": round(res["issued"] / F, 4),
+                "mfma_issue_frac": round(res["issued"] / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"warmup done ({args.warmup} steps)")
-
-    bsmm.bsmm_set_option("time_kernels", "1")
-    bsmm.bsmm_kernel_times(reset=True)
-    ms_per_step = timed(torch, step, args.steps)
-    gemm_ms, gemm_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
-    bsmm.bsmm_set_option("time_kernels", "0")
-    stats = bsmm.bsmm_last_stats()
-    value = F / (ms_per_step * 1e-3) / 1e9
-    log(f"dense path: {ms_per_step:.3f} ms/step, {value:.1f} GFLOP/s, path={stats['path']}")
-
-    gemm_avg_ms = gemm_ms / max(gemm_n, 1)
-    achieved = F / (gemm_avg_ms * 1e-3) / 1e12
-    roofline = {"bound": "mfma", "kernel": "k_dgemm_mfma", "achieved": round(achieved, 3),
-                "peak": PEAK_FP64_MFMA_TFLOPS, "unit": "TFLOP/s",
-                "frac": round(achieved / PEAK_FP64_MFMA_TFLOPS, 4),
-                "kernel_ms": round(gemm_avg_ms, 4), "launches": gemm_n,
-                "traffic": traffic_from_profile()}
-
-    # The 32-deep k-step variant of the same GEMM, for comparison.
-    bsmm.bsmm_set_option("dense_kb", "32")
-    step()
-    bsmm.bsmm_set_option("time_kernels", "1")
-    bsmm.bsmm_kernel_times(reset=True)
-    kb32_ms = timed(torch, step, 3)
-    g32_ms, g32_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
-    bsmm.bsmm_set_option("time_kernels", "0")
-    bsmm.bsmm_set_option("dense_kb", "16")
-    dense_kb32 = {"ms_per_step": round(kb32_ms, 3), "gemm_kernel_ms": round(g32_ms / max(g32_n, 1), 3),
-                  "gemm_tflops": round(F / (g32_ms / max(g32_n, 1) * 1e-3) / 1e12, 2)}
-    log(f"dense path, k step 32: {kb32_ms:.3f} ms/step")
-
-    blocked = None
-    if not args.no_blocked:
-        blocked = {}
-        for kern in ("plain", "tuned"):
-            set_opts(bsmm, path="stack", stack_kernel=kern)
-            MC2 = bsmm.Matrix.empty(A.rbs, B.cbs)
-            step(MC2)
-            bms = timed(torch, lambda: step(MC2), 3)
-            MC2.close()
-            blocked[kern] = {"ms_per_step": round(bms, 3), "gflops": round(F / (bms * 1e-3) / 1e9, 1),
-                             "t_blocked_over_t_densified": round(bms / ms_per_step, 3),
-                             "params_32x32x32": list(bsmm.bsmm_select_params(32, 32, 32))
-                             if kern == "tuned" else None}
-            log(f"blocked path ({kern}): {bms:.3f} ms/step")
-        set_opts(bsmm, path="auto", stack_kernel="plain")
-
-    extras = {}
-    MCe = None
-    MWe = None
-    if not args.no_extras:
-        # Split-precision emulation of the same product (7 slices).
-        set_opts(bsmm, path="emul", emul_slices=7)
-        MCe = bsmm.Matrix.empty(A.rbs, B.cbs)
-        step(MCe)
-        bsmm.bsmm_set_option("time_kernels", "1")
-        bsmm.bsmm_kernel_times(reset=True)
-        ems = timed(torch, lambda: step(MCe), 3)
-        eg_ms, eg_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
-        bsmm.bsmm_set_option("time_kernels", "0")
-        set_opts(bsmm, path="auto")
-        pairs = 7 * 8 // 2
-        ek = eg_ms / max(eg_n, 1)
-        extras["emulated_int8_s7"] = {
-            "ms_per_step": round(ems, 3), "gflops_fp64_equiv": round(F / (ems * 1e-3) / 1e9, 1),
-            "speedup_vs_dense_fp64": round(ms_per_step / ems, 3),
-            "gemm_kernel_ms": round(ek, 3),
-            "int8_tops_achieved": round(pairs * F / (ek * 1e-3) / 1e12, 1), "int8_peak_tops": 5000.0}
-        log(f"emulated path: {ems:.3f} ms/step (INT8 GEMM {ek:.3f} ms)")
-
-        # Split-precision configuration of the paper's sizes: N = 16384 in
-        # 32-blocks, entries sign * 10^U(-6, 2); native FP64 dense path vs
-        # the emulation with 7 slices.
-        W1, W2 = wide_range_dense(seed=0, n=16384, bs=BS)
-        MW1, MW2 = bsmm.Matrix.from_blocks(W1), bsmm.Matrix.from_blocks(W2)
-        Fw = 2.0 * 16384 ** 3
-        wres = {"N": 16384, "values": "sign * 10^U(-6,2)", "slices": 7}
-        outs = {}
-        for name, opts in (("native_fp64", dict(path="dense")), ("emulated_int8", dict(path="emul", emul_slices=7))):
-            set_opts(bsmm, **opts)
-            MWc = bsmm.Matrix.empty(W1.rbs, W2.cbs)
-
-            def runw(MWc=MWc):
-                bsmm.multiply(1.0, MW1, MW2, 0.0, MWc, 0.0, stream)
-
-            wms = timed(torch, runw, 3)
-            wres[name] = {"ms_per_step": round(wms, 3), "gflops_fp64_equiv": round(Fw / (wms * 1e-3) / 1e9, 1)}
-            outs[name] = MWc
-            log(f"wide-range 16384 {name}: {wms:.3f} ms")
-        set_opts(bsmm, path="auto")
-        wres["speedup_emulated_vs_native"] = round(wres["native_fp64"]["ms_per_step"] /
-                                                   wres["emulated_int8"]["ms_per_step"], 3)
-        Xn = outs["native_fp64"].to_host().data
-        Xe = outs["emulated_int8"].to_host().data
-        wres["rel_err_emulated_vs_native"] = float(np.linalg.norm(Xe - Xn) / np.linalg.norm(Xn))
-        del Xn, Xe
-        outs["native_fp64"].close()
-        MWe = outs["emulated_int8"]
-        MW1.close()
-        MW2.close()
-        extras["emulated_wide_dense_16384"] = wres
-
-        # Banded uneven blocks {5,13,23,32}, N ~ 50,000: plain vs tuned stacks.
-        for occ in (0.01, 0.10):
-            U, V = banded_uneven(seed=0, occupancy=occ, target=50000)
-            MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
-            res = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
-            for kern in ("plain", "tuned"):
-                set_opts(bsmm, path="stack", stack_kernel=kern)
-                MW = bsmm.Matrix.empty(U.rbs, V.cbs)
-
-                def run(MW=MW):
-                    bsmm.multiply(1.0, MU, MV, 0.0, MW, 1e-10, stream)
-
-                run()
-                st = bsmm.bsmm_last_stats()
-                ums = timed(torch, run, 3)
-                res[kern] = {"ms_per_step": round(ums, 3),
-                             "gflops": round(st["flops"] / (ums * 1e-3) / 1e9, 1)}
-                res["flops_per_step"] = st["flops"]
-                res["products"] = st["n_products"]
-                res["classes"] = st["n_classes"]
-                MW.close()
-            res["tuned_speedup"] = round(res["plain"]["ms_per_step"] / res["tuned"]["ms_per_step"], 3)
-            extras[f"banded_uneven_{int(round(occ * 100))}pct"] = res
-            log(f"banded {occ}: plain {res['plain']['ms_per_step']} ms, tuned {res['tuned']['ms_per_step']} ms")
-            MU.close()
-            MV.close()
-            del U, V
-
-        # 460 x 460 in 23-blocks, 10 %: latency of one multiply.
-        S1, S2 = sparse_uniform(seed=0)
-        M1, M2 = bsmm.Matrix.from_blocks(S1), bsmm.Matrix.from_blocks(S2)
-        tiny = {}
-        for kern in ("plain", "tuned"):
-            set_opts(bsmm, path="stack", stack_kernel=kern)
-            M3 = bsmm.Matrix.empty(S1.rbs, S2.cbs)
-
-            def run3(M3=M3):
-                bsmm.multiply(1.0, M1, M2, 0.0, M3, 0.0, stream)
-
-            run3()
-            tiny[kern + "_us"] = round(1e3 * timed(torch, run3, 20), 1)
-            if kern == "tuned":
-                # Repeated multiply into the same C with the plan cache: the
-                # symbolic phase and stack build are skipped and the planned
-                # hipGraph is replayed (same result, see the plan-cache tests).
-                bsmm.bsmm_set_option("plan_cache", "1")
-                run3()
-                tiny["tuned_plan_cache_us"] = round(1e3 * timed(torch, run3, 20), 1)
-                bsmm.bsmm_set_option("plan_cache", "0")
-            M3.close()
-        extras["sparse_460_b23_latency"] = tiny
-        set_opts(bsmm, path="auto", stack_kernel="plain")
-        M1.close()
-        M2.close()
-
-    keep = {}
-    if args.all_configs:
-        extras["all_configs"], keep = all_configs(bsmm, torch, stream)
-
+    orc = None
     cpu = None
-    rel_err = None
+    rel_errs = None
+    sample = None
     if not args.no_cpu_baseline:
-        # CPU baseline leg: the reference on a bounded sample of block rows,
-        # also used to check the GPU results on those rows.
         from oracle import oracle as orc
-        threads = min(len(os.sched_getaffinity(0)), 16)
-        row_flops = 2.0 * BS * N * N  # one block row of C: 32 x 8192 x 8192
-        orc.multiply(1.0, A, B, 0.0, rows=(0, 2), nthreads=threads)  # warm-up (threads, pages)
-        c0 = time.perf_counter()
-        orc.multiply(1.0, A, B, 0.0, rows=(2, 6), nthreads=threads)
-        t_row = (time.perf_counter() - c0) / 4
-        # The whole C when it takes at most 30 s, else about 15 s of rows.
-        r0 = 0
-        nrows = N // BS if t_row * (N // BS) <= 30.0 else int(max(1, 15.0 / max(t_row, 1e-3)))
-        c0 = time.perf_counter()
-        R = orc.multiply(1.0, A, B, 0.0, rows=(r0, r0 + nrows), nthreads=threads)
-        t_cpu = time.perf_counter() - c0
-        cpu = {"value": round(row_flops * nrows / t_cpu / 1e9, 3), "unit": "GFLOP/s",
-               "cores": threads, "kind": "oracle",
-               "sample": f"block rows {r0}..{r0 + nrows - 1} of 256 ({nrows * 32} of {N} rows of C), "
-                         f"{t_cpu:.1f} s"}
+        cpu, rel_errs, sample = cpu_baseline(orc, torch, res, threads)
+        log(f"cpu baseline: {cpu['value']} GFLOP/s on {threads} threads, {cpu['value_1thread']} on 1; "
+            f"rel err tuned {rel_errs['tuned']:.2e} plain {rel_errs['plain']:.2e}")
 
-        def rows_err(M):
-            X = M.to_host()
-            sizes = orc.block_sizes(X.rbs, X.cbs, X.row_ptr, X.col_ind)
-            start = np.concatenate([[0], np.cumsum(sizes)])
-            e0 = int(start[int(X.row_ptr[r0])])
-            e1 = int(start[int(X.row_ptr[r0 + nrows])])
-            assert np.array_equal(X.col_ind[int(X.row_ptr[r0]):int(X.row_ptr[r0 + nrows])], R.col_ind)
-            return orc.rel_err(X.data[e0:e1], R.data)
+    res["C_tuned"].close()
+    res["C_plain"].close()
+    extras = {}
+    if not args.no_extras:
+        extras["dense_square_8192_b32"], keep, A2, B2 = extras_dense(bsmm, torch, stream, args)
+        if orc is not None:
+            for name, M in keep.items():
+                extras["dense_square_8192_b32"][name]["rel_err_rows_0_127_255"] = sampled_err(
+                    orc, torch, M, A2, B2, (0, 127, 255), threads)
+        for M in keep.values():
+            M.close()
+        del A2, B2
+        extras["emulated_wide_dense_16384"] = extras_wide(bsmm, torch, stream, args, orc, threads)
+        extras.update(extras_banded(bsmm, torch, stream, args, orc, threads))
+        extras["sparse_460_b23_latency"] = extras_tiny(bsmm, torch, stream, args)
+    if args.all_configs:
+        extras["all_configs"], keep = all_configs(bsmm, torch, stream, args)
+        if orc is not None:
+            for name, (X, Aref, Bref, eps, rows) in keep.items():
+                e = sampled_err_host(orc, X, Aref, Bref, rows, threads, eps)
+                d = extras["all_configs"]
+                if name == "rect":
+                    d = d["dense_rect_4096x4096x65536"]
+                else:
+                    d = d["sparse_wide_range_32752_b23"][name[len("sparse_"):]]
+                d["rel_err_sampled_rows"] = e
+                d["sampled_block_rows"] = list(rows)
 
-        rel_err = rows_err(MC)
-        if MCe is not None:
-            extras["emulated_int8_s7"]["rel_err"] = rows_err(MCe)
-        if MWe is not None:
-            # Emulated wide-range product against the reference on three
-            # sampled block rows.
-            Xw = MWe.to_host()
-            sizes = orc.block_sizes(Xw.rbs, Xw.cbs, Xw.row_ptr, Xw.col_ind)
-            start = np.concatenate([[0], np.cumsum(sizes)])
-            errs = []
-            for r in (5, 200, 511):
-                Rw = orc.multiply(1.0, W1, W2, 0.0, rows=(r, r + 1), nthreads=threads)
-                a0, a1 = int(Xw.row_ptr[r]), int(Xw.row_ptr[r + 1])
-                errs.append(orc.rel_err(Xw.data[int(start[a0]):int(start[a1])], Rw.data))
-            extras["emulated_wide_dense_16384"]["rel_err_rows_5_200_511"] = max(errs)
-            del Xw
-        for name, (X, Aref, Bref, eps, rows) in keep.items():
-            e = sampled_err(orc, X, Aref, Bref, rows, threads, eps)
-            key = {"rect": ("dense_rect_4096x4096x65536",), "banded30": ("banded_uneven_30pct", "tuned"),
-                   "sparse_native_fp64_stack_tuned": ("sparse_wide_range_32752_b23", "native_fp64_stack_tuned"),
-                   "sparse_emulated_int8_densified": ("sparse_wide_range_32752_b23", "emulated_int8_densified")}[name]
-            d = extras["all_configs"]
-            for k in key:
-                d = d[k]
-            d["rel_err_sampled_rows"] = e
-            d["sampled_block_rows"] = list(rows)
-        log(f"cpu baseline: {cpu['value']} GFLOP/s on {threads} threads; rel_err {rel_err:.2e}")
-
+    ms = tuned["ms_per_step"]
     out = {
-        "metric": METRIC, "value": round(value, 2), "unit": "GFLOP/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "metric": METRIC, "value": tuned["gflops"], "unit": "GFLOP/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "dense_square_n8192_b32", "N": N, "block": BS, "occupancy": 1.0,
-                   "alpha": 1.0, "beta": 0.0, "path": "dense: merged panels + FP64 MFMA GEMM",
-                   "flops_per_step": F},
+        "config": {"workload": HEADLINE_NAME, "N": int(np.sum(res["A"].rbs)),
+                   "block_sizes": [5, 13, 23, 32], "occupancy": HEADLINE_OCC,
+                   "filter_eps": HEADLINE_EPS, "alpha": 1.0, "beta": 0.0,
+                   "path": "tuned stacks: tuning database parameters, classes on the scheduled FP64 MFMA "
+                           "small-block kernel in one hipGraph",
+                   "flops_per_step": F, "products": st["n_products"], "runs": st["n_runs"],
+                   "classes": st["n_classes"], "c_blocks_before_filter": st["c_nnzb_before"],
+                   "c_blocks_after_filter": st["c_nnzb_after"]},
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "rel_err": rel_err,
-        "blocked": blocked,
-        "dense_kb32": dense_kb32,
+        "rel_err": rel_errs["tuned"] if rel_errs else None,
+        "rel_err_mode": f"sampled: block rows {sample[0]}..{sample[1] - 1}" if sample else None,
+        "plain": dict(res["plain"], rel_err=rel_errs["plain"] if rel_errs else None),
+        "tuned_speedup_vs_plain": round(res["plain"]["median_ms"] / ms, 3),
         "extras": extras,
     }
     print(json.dumps(out), flush=True)
-    for M in (MA, MB, MC, MCe, MWe):
-        if M is not None:
-            M.close()
     bsmm.bsmm_set_allocator()
 
 

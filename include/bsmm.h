@@ -1,5 +1,6 @@
 /*
- * bsmm.h -- block-sparse FP64 matrix multiply on one AMD MI355X (gfx950).
+ * bsmm.h -- block-sparse FP64 / FP32 matrix multiply on one AMD MI355X
+ * (gfx950).
  *
  * One rank's local step of a distributed block-CSR multiplication:
  *
@@ -22,8 +23,9 @@
  *  - blk_row_ptr is int64[nbr+1] with blk_row_ptr[0] = 0 and
  *    blk_row_ptr[nbr] = nnzb, non-decreasing; blk_col_ind is int32[nnzb]
  *    with column indices in [0, nbc), strictly ascending inside each row.
- *  - Block data are FP64, packed in CSR order; every block is column-major
- *    with leading dimension equal to its number of rows.
+ *  - Block data are FP64 (or FP32 for matrices created with
+ *    bsmm_create_matrix_typed), packed in CSR order; every block is
+ *    column-major with leading dimension equal to its number of rows.
  *  - "stream" is a hipStream_t (NULL = the legacy default stream).  All
  *    device work is ordered on that stream.
  *  - Every function returns a status code (below) and never throws across
@@ -44,6 +46,13 @@ extern "C" {
 #endif
 
 typedef struct bsmm_matrix_s *bsmm_matrix; /* opaque; owns its device memory */
+
+/* Element type of a matrix's block data (paper, Sec. II: the library takes
+ * single- and double-precision numbers). */
+enum bsmm_dtype {
+    BSMM_F64 = 0,  /* double */
+    BSMM_F32 = 1   /* float  */
+};
 
 enum bsmm_status {
     BSMM_OK = 0,
@@ -80,6 +89,26 @@ int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes,
                        int data_on_device, void *stream, bsmm_matrix *out);
 
 /*
+ * As bsmm_create_matrix, for block data of element type dtype (BSMM_F64 or
+ * BSMM_F32; paper, Sec. II: the library takes single- and double-precision
+ * numbers).  data points to dtype values (host or device, or NULL for
+ * zeros).  A multiply takes A, B and C of one element type and computes in
+ * it: FP32 matrices run the same stacks and kernels in FP32 (FP32 MFMA where
+ * FP64 uses FP64 MFMA), with alpha, beta rounded to FP32 and the filter's
+ * squared norms summed in FP64.  The split-precision emulation is FP64
+ * only.  Errors: as bsmm_create_matrix, plus EINVAL for an unknown dtype.
+ */
+int bsmm_create_matrix_typed(int32_t nbr, const int32_t *row_blk_sizes,
+                             int32_t nbc, const int32_t *col_blk_sizes,
+                             int64_t nnzb, const int64_t *blk_row_ptr,
+                             const int32_t *blk_col_ind, int32_t dtype,
+                             const void *data, int data_on_device, void *stream,
+                             bsmm_matrix *out);
+
+/* Element type of a matrix (BSMM_F64 or BSMM_F32). */
+int bsmm_matrix_dtype(bsmm_matrix m, int32_t *dtype);
+
+/*
  * C <- filter_eps(beta*C + alpha*A*B) (paper, Sec. II local multiplication;
  * Sec. III densification for fully occupied inputs).
  *   A: nbr x nbk blocks, B: nbk x nbc blocks, C: nbr x nbc blocks; the
@@ -94,8 +123,9 @@ int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes,
  *   A == B is allowed; C must differ from both.
  * The call blocks the host once to read the size of the new C pattern and
  * once more when the filter removes blocks; the rest is stream-ordered.
- * Errors: EINVAL (nulls, C aliasing A or B, filter_eps < 0 or NaN), ESHAPE,
- * ERANGE, ENOMEM, ENOTSUP, EDEVICE.  On EINVAL/ESHAPE nothing is modified.
+ * Errors: EINVAL (nulls, C aliasing A or B, filter_eps < 0 or NaN, element
+ * types that differ), ESHAPE, ERANGE, ENOMEM, ENOTSUP (incl. option "path"
+ * "emul" on FP32 matrices), EDEVICE.  On EINVAL/ESHAPE nothing is modified.
  */
 int bsmm_multiply(double alpha, bsmm_matrix A, bsmm_matrix B, double beta,
                   bsmm_matrix C, double filter_eps, void *stream);
@@ -128,7 +158,7 @@ int bsmm_multiply_noalloc(double alpha, bsmm_matrix A, bsmm_matrix B, double bet
  * was last used on).  NULL is accepted and ignored. */
 int bsmm_destroy_matrix(bsmm_matrix m);
 
-/* Sizes of a matrix: block rows/columns, stored blocks, stored FP64
+/* Sizes of a matrix: block rows/columns, stored blocks, stored
  * elements.  Any output pointer may be NULL. */
 int bsmm_matrix_info(bsmm_matrix m, int32_t *nbr, int32_t *nbc, int64_t *nnzb,
                      int64_t *nelems);
@@ -141,6 +171,11 @@ int bsmm_matrix_info(bsmm_matrix m, int32_t *nbr, int32_t *nbc, int64_t *nnzb,
  */
 int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
                   double *data, int data_on_device, void *stream);
+
+/* As bsmm_copy_out, with data in the matrix's own element type (the only
+ * copy-out of FP32 matrices; bsmm_copy_out returns EINVAL for them). */
+int bsmm_copy_out_typed(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
+                        void *data, int data_on_device, void *stream);
 
 /*
  * Device memory provider.  alloc(bytes, stream, ctx) returns device memory
@@ -178,7 +213,15 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
  *                 classes launched together as nodes of one hipGraph
  *   "stack_chunk" maximum products per stack launch, "0" = unlimited
  *                 (paper, Sec. II: batches of at most 30000 products)
- *   "stack_panel" maximum products held in the stacks at once (default
+ *   "stack_tile"  tuned path: "T" > 0 (default "32") runs every FP64 MFMA
+                 class of blocks up to 32 x 32 whose runs need no splitting
+                 in one launch, its runs ordered by tiles of T x T C blocks
+                 (when those classes hold at least 4096 runs); "0" launches
+                 every class on its own.  Results are the same bits.
+   "stack_sched" order in which the scheduled launch's waves take runs:
+                 "dynamic" (default; a run counter, several short runs per
+                 update) or "static" (fixed strides, numbered XCD by XCD)
+   "stack_panel" maximum products held in the stacks at once (default
  *                 "1073741824", 16 GiB of product entries; "0" = no
  *                 limit): a multiply with more products builds and runs
  *                 its stacks over panels of consecutive C block rows, one
@@ -231,6 +274,8 @@ typedef struct bsmm_multiply_stats {
     int64_t n_row_panels;  /* stack path: C block-row panels the stacks were
                               built and run in (option "stack_panel"); 0 on
                               the other paths                               */
+    int64_t n_sched_runs;  /* runs executed by the scheduled small-block
+                              launch (tuned path, option "stack_tile")      */
 } bsmm_multiply_stats;
 int bsmm_last_stats(bsmm_multiply_stats *out);
 

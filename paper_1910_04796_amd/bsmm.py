@@ -37,6 +37,9 @@ DEFAULT_MLP = os.path.join(_HERE, "tune_db", "gfx950_mlp.txt")
 
 BSMM_OK, BSMM_EINVAL, BSMM_ESHAPE, BSMM_EINDEX = 0, -1, -2, -3
 BSMM_ENOMEM, BSMM_EDEVICE, BSMM_ERANGE, BSMM_ENOTSUP = -4, -5, -6, -7
+BSMM_F64, BSMM_F32 = 0, 1
+DTYPES = {"f64": BSMM_F64, "f32": BSMM_F32}
+NP_DTYPES = {BSMM_F64: np.float64, BSMM_F32: np.float32}
 STATUS_NAMES = {0: "OK", -1: "EINVAL", -2: "ESHAPE", -3: "EINDEX", -4: "ENOMEM",
                 -5: "EDEVICE", -6: "ERANGE", -7: "ENOTSUP"}
 
@@ -55,11 +58,16 @@ class bsmm_multiply_stats(ctypes.Structure):
     _fields_ = [("path", ctypes.c_int32), ("n_classes", ctypes.c_int32),
                 ("n_products", ctypes.c_int64), ("n_runs", ctypes.c_int64),
                 ("c_nnzb_before", ctypes.c_int64), ("c_nnzb_after", ctypes.c_int64),
-                ("flops", ctypes.c_double), ("n_row_panels", ctypes.c_int64)]
+                ("flops", ctypes.c_double), ("n_row_panels", ctypes.c_int64),
+                ("n_sched_runs", ctypes.c_int64)]
 
 
 _lib.bsmm_create_matrix.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _vp, ctypes.c_int,
                                     _vp, ctypes.POINTER(_vp)]
+_lib.bsmm_create_matrix_typed.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _i32, _vp,
+                                          ctypes.c_int, _vp, ctypes.POINTER(_vp)]
+_lib.bsmm_matrix_dtype.argtypes = [_vp, _i32p]
+_lib.bsmm_copy_out_typed.argtypes = [_vp, _i64p, _i32p, _vp, ctypes.c_int, _vp]
 _lib.bsmm_multiply.argtypes = [ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp]
 _lib.bsmm_multiply_noalloc.argtypes = [ctypes.c_double, _vp, _vp, ctypes.c_double, _vp, _vp]
 _lib.bsmm_destroy_matrix.argtypes = [_vp]
@@ -87,11 +95,13 @@ _lib.bsmm_mlp_train.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _i32, _i32, cty
                                 ctypes.c_uint64, _f32p]
 for _f in ("bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
            "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix",
-           "bsmm_matrix_info", "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
+           "bsmm_matrix_info", "bsmm_copy_out", "bsmm_create_matrix_typed", "bsmm_matrix_dtype",
+           "bsmm_copy_out_typed", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
            "bsmm_last_stats", "bsmm_inspect_stacks"):
     getattr(_lib, _f).restype = ctypes.c_int
 
-EXPORTED = ("bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix", "bsmm_matrix_info",
+EXPORTED = ("bsmm_create_matrix", "bsmm_create_matrix_typed", "bsmm_matrix_dtype", "bsmm_copy_out_typed",
+            "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix", "bsmm_matrix_info",
             "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
             "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times",
             "bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params",
@@ -137,9 +147,12 @@ def bsmm_last_error():
 
 
 def bsmm_create_matrix(nbr, row_blk_sizes, nbc, col_blk_sizes, nnzb, blk_row_ptr, blk_col_ind,
-                       data=None, data_on_device=None, stream=None):
+                       data=None, data_on_device=None, stream=None, dtype="f64"):
     """Returns an opaque handle (int).  ``data`` is a numpy array (host), a
-    torch CUDA tensor (device), or None for zeros."""
+    torch CUDA tensor (device), or None for zeros; ``dtype`` "f64" or "f32"
+    (host data are converted to it, device data must already be of it)."""
+    code = DTYPES[dtype]
+    npt = NP_DTYPES[code]
     rbs = _arr(row_blk_sizes, np.int32)
     cbs = _arr(col_blk_sizes, np.int32)
     rp = _arr(blk_row_ptr, np.int64)
@@ -151,17 +164,17 @@ def bsmm_create_matrix(nbr, row_blk_sizes, nbc, col_blk_sizes, nnzb, blk_row_ptr
         keep = data.contiguous()
         dptr, on_dev = keep.data_ptr(), 1 if keep.is_cuda else 0
         if not on_dev:
-            keep = keep.numpy().astype(np.float64, copy=False)
+            keep = keep.numpy().astype(npt, copy=False)
             dptr = keep.ctypes.data
     else:
-        keep = _arr(data, np.float64)
+        keep = _arr(data, npt)
         dptr, on_dev = (keep.ctypes.data if keep.size else None), 0
     if data_on_device is not None:
         on_dev = int(bool(data_on_device))
     h = ctypes.c_void_p()
-    st = _lib.bsmm_create_matrix(int(nbr), _ptr(rbs, _i32p), int(nbc), _ptr(cbs, _i32p), int(nnzb),
-                                 rp.ctypes.data_as(_i64p), _ptr(ci, _i32p), dptr, on_dev,
-                                 _stream(stream), ctypes.byref(h))
+    st = _lib.bsmm_create_matrix_typed(int(nbr), _ptr(rbs, _i32p), int(nbc), _ptr(cbs, _i32p), int(nnzb),
+                                       rp.ctypes.data_as(_i64p), _ptr(ci, _i32p), code, dptr, on_dev,
+                                       _stream(stream), ctypes.byref(h))
     _check(st)
     return h.value
 
@@ -185,19 +198,26 @@ def bsmm_matrix_info(m):
     return nbr.value, nbc.value, nnzb.value, ne.value
 
 
+def bsmm_matrix_dtype(m):
+    d = _i32()
+    _check(_lib.bsmm_matrix_dtype(m, ctypes.byref(d)))
+    return d.value
+
+
 def bsmm_copy_out(m, stream=None, device_out=None):
-    """Returns (row_ptr, col_ind, data) as numpy arrays; with ``device_out``
-    (a float64 CUDA tensor of nelems) the data go there instead."""
+    """Returns (row_ptr, col_ind, data) as numpy arrays, data in the matrix's
+    element type; with ``device_out`` (a CUDA tensor of nelems elements of
+    that type) the data go there instead."""
     nbr, nbc, nnzb, ne = bsmm_matrix_info(m)
     rp = np.zeros(nbr + 1, dtype=np.int64)
     ci = np.zeros(max(nnzb, 1), dtype=np.int32)
     if device_out is not None:
-        _check(_lib.bsmm_copy_out(m, rp.ctypes.data_as(_i64p), ci.ctypes.data_as(_i32p),
-                                  ctypes.c_void_p(device_out.data_ptr()), 1, _stream(stream)))
+        _check(_lib.bsmm_copy_out_typed(m, rp.ctypes.data_as(_i64p), ci.ctypes.data_as(_i32p),
+                                        ctypes.c_void_p(device_out.data_ptr()), 1, _stream(stream)))
         return rp, ci[:nnzb], device_out
-    data = np.zeros(max(ne, 1), dtype=np.float64)
-    _check(_lib.bsmm_copy_out(m, rp.ctypes.data_as(_i64p), ci.ctypes.data_as(_i32p),
-                              ctypes.c_void_p(data.ctypes.data), 0, _stream(stream)))
+    data = np.zeros(max(ne, 1), dtype=NP_DTYPES[bsmm_matrix_dtype(m)])
+    _check(_lib.bsmm_copy_out_typed(m, rp.ctypes.data_as(_i64p), ci.ctypes.data_as(_i32p),
+                                    ctypes.c_void_p(data.ctypes.data), 0, _stream(stream)))
     return rp, ci[:nnzb], data[:ne]
 
 
@@ -389,26 +409,27 @@ class HostBlockCSR:
 class Matrix:
     """Owning wrapper of a bsmm handle."""
 
-    def __init__(self, handle, rbs, cbs):
+    def __init__(self, handle, rbs, cbs, dtype="f64"):
         self.handle = handle
         self.rbs = np.asarray(rbs, dtype=np.int32)
         self.cbs = np.asarray(cbs, dtype=np.int32)
+        self.dtype = dtype
 
     @classmethod
-    def from_blocks(cls, M, stream=None, data=None):
+    def from_blocks(cls, M, stream=None, data=None, dtype="f64"):
         """From any object with rbs, cbs, row_ptr, col_ind, data attributes."""
         d = M.data if data is None else data
         h = bsmm_create_matrix(len(M.rbs), M.rbs, len(M.cbs), M.cbs, int(np.asarray(M.row_ptr)[-1]),
-                               M.row_ptr, M.col_ind, d, stream=stream)
-        return cls(h, M.rbs, M.cbs)
+                               M.row_ptr, M.col_ind, d, stream=stream, dtype=dtype)
+        return cls(h, M.rbs, M.cbs, dtype)
 
     @classmethod
-    def empty(cls, rbs, cbs, stream=None):
+    def empty(cls, rbs, cbs, stream=None, dtype="f64"):
         """A matrix with no stored blocks."""
         rp = np.zeros(len(rbs) + 1, dtype=np.int64)
         h = bsmm_create_matrix(len(rbs), rbs, len(cbs), cbs, 0, rp, np.zeros(0, np.int32), None,
-                               stream=stream)
-        return cls(h, rbs, cbs)
+                               stream=stream, dtype=dtype)
+        return cls(h, rbs, cbs, dtype)
 
     def info(self):
         return bsmm_matrix_info(self.handle)

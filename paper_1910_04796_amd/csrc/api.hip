@@ -248,16 +248,21 @@ int adopt_stream(bsmm_matrix_s *M, hipStream_t s) {
 using namespace bsmm;
 
 // ------------------------------------------------------------------- C-ABI
-extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int32_t nbc,
-                                  const int32_t *col_blk_sizes, int64_t nnzb,
-                                  const int64_t *blk_row_ptr, const int32_t *blk_col_ind,
-                                  const double *data, int data_on_device, void *stream,
-                                  bsmm_matrix *out) {
+extern "C" int bsmm_create_matrix_typed(int32_t nbr, const int32_t *row_blk_sizes, int32_t nbc,
+                                        const int32_t *col_blk_sizes, int64_t nnzb,
+                                        const int64_t *blk_row_ptr, const int32_t *blk_col_ind,
+                                        int32_t dtype, const void *data, int data_on_device,
+                                        void *stream, bsmm_matrix *out) {
     clear_error();
     if (!out) {
         set_error(BSMM_EINVAL, "out is NULL");
         return BSMM_EINVAL;
     }
+    if (dtype != BSMM_F64 && dtype != BSMM_F32) {
+        set_error(BSMM_EINVAL, "unknown element type %d", dtype);
+        return BSMM_EINVAL;
+    }
+    const size_t esize = dtype == BSMM_F32 ? sizeof(float) : sizeof(double);
     BSMM_TRY(validate_sizes("row_blk_sizes", nbr, row_blk_sizes));
     BSMM_TRY(validate_sizes("col_blk_sizes", nbc, col_blk_sizes));
     BSMM_TRY(validate_pattern(nbr, nbc, nnzb, blk_row_ptr, blk_col_ind));
@@ -290,6 +295,7 @@ extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int
     }
     M->nbr = nbr;
     M->nbc = nbc;
+    M->dtype = dtype;
     M->rbs.assign(row_blk_sizes, row_blk_sizes + nbr);
     M->cbs.assign(col_blk_sizes, col_blk_sizes + nbc);
     M->row_off = row_off;
@@ -333,7 +339,7 @@ extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int
         (st = M->b_row_ptr.reserve(sizeof(int64_t) * (nbr + 1), s)) ||
         (st = M->b_col_ind.reserve(sizeof(int32_t) * (nnzb + 1), s)) ||
         (st = M->b_blk_off.reserve(sizeof(int64_t) * (nnzb + 1), s)) ||
-        (st = M->b_data.reserve(sizeof(double) * (acc + 1), s)))
+        (st = M->b_data.reserve(esize * (acc + 1), s)))
         return fail(st);
 
 #define CP(dst, src, bytes)                                                                  \
@@ -359,10 +365,11 @@ extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int
     if (acc > 0) {
         hipError_t e;
         if (data)
-            e = hipMemcpyAsync(M->d_data(), data, sizeof(double) * acc,
+            e = hipMemcpyAsync(M->d_raw(), data, esize * acc,
                                data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, s);
         else
-            e = (hipError_t)(fill_zero(M->d_data(), acc, s) == BSMM_OK ? hipSuccess : hipErrorUnknown);
+            e = (hipError_t)(fill_zero_bytes(M->d_raw(), esize * acc, s) == BSMM_OK ? hipSuccess
+                                                                                   : hipErrorUnknown);
         if (e != hipSuccess) {
             set_error(BSMM_EDEVICE, "data upload failed: %s", hipGetErrorString(e));
             return fail(BSMM_EDEVICE);
@@ -373,6 +380,25 @@ extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int
         return fail(BSMM_EDEVICE);
     }
     *out = M;
+    return BSMM_OK;
+}
+
+extern "C" int bsmm_create_matrix(int32_t nbr, const int32_t *row_blk_sizes, int32_t nbc,
+                                  const int32_t *col_blk_sizes, int64_t nnzb,
+                                  const int64_t *blk_row_ptr, const int32_t *blk_col_ind,
+                                  const double *data, int data_on_device, void *stream,
+                                  bsmm_matrix *out) {
+    return bsmm_create_matrix_typed(nbr, row_blk_sizes, nbc, col_blk_sizes, nnzb, blk_row_ptr,
+                                    blk_col_ind, BSMM_F64, data, data_on_device, stream, out);
+}
+
+extern "C" int bsmm_matrix_dtype(bsmm_matrix m, int32_t *dtype) {
+    clear_error();
+    if (!m || !dtype) {
+        set_error(BSMM_EINVAL, "matrix or output is NULL");
+        return BSMM_EINVAL;
+    }
+    *dtype = m->dtype;
     return BSMM_OK;
 }
 
@@ -398,8 +424,8 @@ extern "C" int bsmm_matrix_info(bsmm_matrix m, int32_t *nbr, int32_t *nbc, int64
     return BSMM_OK;
 }
 
-extern "C" int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
-                             double *data, int data_on_device, void *stream) {
+extern "C" int bsmm_copy_out_typed(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
+                                   void *data, int data_on_device, void *stream) {
     clear_error();
     if (!m) {
         set_error(BSMM_EINVAL, "matrix is NULL");
@@ -414,11 +440,21 @@ extern "C" int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_c
         BSMM_HIP(hipMemcpyAsync(blk_col_ind, m->d_col_ind(), sizeof(int32_t) * m->nnzb,
                                 hipMemcpyDeviceToHost, s));
     if (data && m->nelems > 0)
-        BSMM_HIP(hipMemcpyAsync(data, m->d_data(), sizeof(double) * m->nelems,
+        BSMM_HIP(hipMemcpyAsync(data, m->d_raw(), m->esize() * m->nelems,
                                 data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
     BSMM_HIP(hipStreamSynchronize(s));
     m->last_stream = s;
     return BSMM_OK;
+}
+
+extern "C" int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
+                             double *data, int data_on_device, void *stream) {
+    clear_error();
+    if (m && m->dtype != BSMM_F64) {
+        set_error(BSMM_EINVAL, "matrix holds FP32 data (bsmm_copy_out_typed copies it)");
+        return BSMM_EINVAL;
+    }
+    return bsmm_copy_out_typed(m, blk_row_ptr, blk_col_ind, data, data_on_device, stream);
 }
 
 extern "C" int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx) {
@@ -458,6 +494,15 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         long long x = strtoll(value, &end, 10);
         if (!end || *end || x < 0) goto bad;
         o.stack_panel = x;
+    } else if (k == "stack_tile") {
+        char *end = nullptr;
+        long x = strtol(value, &end, 10);
+        if (!end || *end || x < 0 || x > 65536) goto bad;
+        o.stack_tile = (int)x;
+    } else if (k == "stack_sched") {
+        if (v == "static") o.stack_sched = 0;
+        else if (v == "dynamic") o.stack_sched = 1;
+        else goto bad;
     } else if (k == "tune_db") {
         o.tune_db = v;
     } else if (k == "emul_slices") {
@@ -517,6 +562,8 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     else if (k == "stack_kernel") v = o.stack_kernel ? "tuned" : "plain";
     else if (k == "stack_chunk") v = std::to_string(o.stack_chunk);
     else if (k == "stack_panel") v = std::to_string(o.stack_panel);
+    else if (k == "stack_tile") v = std::to_string(o.stack_tile);
+    else if (k == "stack_sched") v = o.stack_sched ? "dynamic" : "static";
     else if (k == "tune_db") v = o.tune_db;
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
     else if (k == "verbose") v = std::to_string(o.verbose);
@@ -559,6 +606,10 @@ int validate_multiply(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doub
     }
     if (C == A || C == B) {
         set_error(BSMM_EINVAL, "C must not alias A or B");
+        return BSMM_EINVAL;
+    }
+    if (A->dtype != C->dtype || B->dtype != C->dtype) {
+        set_error(BSMM_EINVAL, "A, B and C hold different element types");
         return BSMM_EINVAL;
     }
     if (!(eps >= 0.0)) {

@@ -1,5 +1,6 @@
-// dense.hip -- densification path: merge blocks into panels, one FP64 MFMA
-// GEMM, split the result back into the blocks of C.
+// dense.hip -- densification path: merge blocks into panels, one MFMA GEMM
+// (FP64, or FP32 for single-precision matrices), split the result back into
+// the blocks of C.
 //
 // Paper, Sec. III: when the inputs are dense, all blocks handled by a worker
 // are coalesced into one large block by copying them into new buffers, the
@@ -23,13 +24,15 @@
 
 #include "dev_util.h"
 #include "internal.h"
+#include "mfma_util.h"
 
 namespace bsmm {
 
 namespace {
 
-typedef double double4_t __attribute__((ext_vector_type(4)));
-typedef double double2_t __attribute__((ext_vector_type(2)));
+template <class T> struct Vec2;
+template <> struct Vec2<double> { typedef double __attribute__((ext_vector_type(2))) t; };
+template <> struct Vec2<float> { typedef float __attribute__((ext_vector_type(2))) t; };
 
 constexpr int BM = 128, BN = 128;
 constexpr int kGroupM = 8;
@@ -37,11 +40,12 @@ constexpr int kGroupM = 8;
 // Merge: one wave per block (block row found by binary search in the row
 // pointer), copying the column-major block into the column-major panel
 // (ld = panel rows); consecutive lanes write consecutive rows of a column.
+template <class T>
 __global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const int32_t *rbs,
                                                const int32_t *cbs, const int64_t *row_off,
                                                const int64_t *col_off, const int64_t *rp,
                                                const int32_t *ci, const int64_t *blk_off,
-                                               const double *data, double *panel, int64_t ld) {
+                                               const T *data, T *panel, int64_t ld) {
     const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (p >= nnzb) return;
     int32_t lo = 0, hi = nbr;  // row = last lo with rp[lo] <= p
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const 
     const int32_t j = ci[p];
     const int n = cbs[j];
     const int64_t c0 = col_off[j];
-    const double *src = data + blk_off[p];
+    const T *src = data + blk_off[p];
     const int64_t len = (int64_t)m * n;
     if (len < (1 << 20) && m < 4096) {
         const float rcp = 1.0f / (float)m;
@@ -72,13 +76,13 @@ __global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const 
 }
 
 struct GemmArgs {
-    const double *Ap;   // M_pad x K_pad, column-major, ld = lda
-    const double *Bp;   // K_pad x N_pad, column-major, ld = ldb
+    const void *Ap;     // M_pad x K_pad, column-major, ld = lda (element type of the matrices)
+    const void *Bp;     // K_pad x N_pad, column-major, ld = ldb
     int64_t lda, ldb;
     int tiles_m, tiles_n, ktiles;
     int64_t M, N;       // true sizes (rows/cols of C)
     double alpha, beta;
-    double *C;          // C block data
+    void *C;            // C block data
     const int64_t *c_blk_off;
     const int32_t *c_map;   // nbr*nbc block index map, or null when C is full
     int32_t c_nbc;
@@ -88,41 +92,43 @@ struct GemmArgs {
     // [split * kt_per, (split + 1) * kt_per) into part[split] (row-major
     // M_pad x N_pad, unscaled); k_splitk_reduce applies the epilogue.
     int splits, kt_per;
-    double *part;
+    void *part;
 };
 
 // Global -> register loads of one k step of KB: A tile (128 rows x KB k) as
 // KB * 64 double2 along the rows, B tile (KB k x 128 cols) along k.
-template <int KB>
-__device__ __forceinline__ void gemm_gload(double2_t (&ra)[KB / 4], double2_t (&rb)[KB / 4],
-                                           const double *Ablk, const double *Bblk, int64_t lda,
-                                           int64_t ldb, int kt, int tid) {
+template <class T, int KB>
+__device__ __forceinline__ void gemm_gload(typename Vec2<T>::t (&ra)[KB / 4],
+                                           typename Vec2<T>::t (&rb)[KB / 4], const T *Ablk,
+                                           const T *Bblk, int64_t lda, int64_t ldb, int kt, int tid) {
+    typedef typename Vec2<T>::t V2;
     const int64_t k0 = (int64_t)kt * KB;
 #pragma unroll
     for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
         const int kk = e >> 6, r2 = e & 63;
-        ra[i] = *reinterpret_cast<const double2_t *>(Ablk + (k0 + kk) * lda + 2 * r2);
+        ra[i] = *reinterpret_cast<const V2 *>(Ablk + (k0 + kk) * lda + 2 * r2);
     }
 #pragma unroll
     for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
         const int col = e / (KB / 2), k2 = e % (KB / 2);
-        rb[i] = *reinterpret_cast<const double2_t *>(Bblk + (int64_t)col * ldb + k0 + 2 * k2);
+        rb[i] = *reinterpret_cast<const V2 *>(Bblk + (int64_t)col * ldb + k0 + 2 * k2);
     }
 }
 
 // Register -> LDS stores: As[k][m]; Bs[n][k ^ (n & 15)] (XOR swizzle keeps
 // the 16 lanes that read one k of 16 consecutive columns on distinct banks).
-template <int KB>
-__device__ __forceinline__ void gemm_lstore(const double2_t (&ra)[KB / 4],
-                                            const double2_t (&rb)[KB / 4], double *As, double *Bs,
+template <class T, int KB>
+__device__ __forceinline__ void gemm_lstore(const typename Vec2<T>::t (&ra)[KB / 4],
+                                            const typename Vec2<T>::t (&rb)[KB / 4], T *As, T *Bs,
                                             int tid) {
+    typedef typename Vec2<T>::t V2;
 #pragma unroll
     for (int i = 0; i < KB / 4; ++i) {
         const int e = tid + 256 * i;
         const int kk = e >> 6, r2 = e & 63;
-        *reinterpret_cast<double2_t *>(&As[kk * BM + 2 * r2]) = ra[i];
+        *reinterpret_cast<V2 *>(&As[kk * BM + 2 * r2]) = ra[i];
     }
 #pragma unroll
     for (int i = 0; i < KB / 4; ++i) {
@@ -130,17 +136,17 @@ __device__ __forceinline__ void gemm_lstore(const double2_t (&ra)[KB / 4],
         const int col = e / (KB / 2), k2 = e % (KB / 2);
         const int sw = col & 15;
         const int base = (2 * k2) ^ (sw & ~1);
-        const double2_t v = (sw & 1) ? rb[i].yx : rb[i];
-        *reinterpret_cast<double2_t *>(&Bs[col * KB + base]) = v;
+        const V2 v = (sw & 1) ? rb[i].yx : rb[i];
+        *reinterpret_cast<V2 *>(&Bs[col * KB + base]) = v;
     }
 }
 
 // KB = 16: 64 KB of LDS, two workgroups per CU; KB = 32: 128 KB, one
 // workgroup per CU with twice the prefetch distance and half the barriers.
-template <int KB, int MINB, bool SPLIT>
+template <class T, int KB, int MINB, bool SPLIT>
 __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
-    __shared__ double As[2][KB * BM];  // [k][m]
-    __shared__ double Bs[2][BN * KB];  // [n][k ^ swizzle(n)]
+    __shared__ T As[2][KB * BM];  // [k][m]
+    __shared__ T Bs[2][BN * KB];  // [n][k ^ swizzle(n)]
 
     // XCD-aware remap, then grouped row-major order inside the XCD's band
     // (split k: consecutive logical ids walk the tiles of one split).
@@ -169,26 +175,26 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
     const int wm = w & 1, wn = w >> 1;
     const int l16 = lane & 15, lk = lane >> 4;
 
-    const double *Ablk = g.Ap + (int64_t)tm * BM;
-    const double *Bblk = g.Bp + (int64_t)tn * BN * g.ldb;
+    const T *Ablk = static_cast<const T *>(g.Ap) + (int64_t)tm * BM;
+    const T *Bblk = static_cast<const T *>(g.Bp) + (int64_t)tn * BN * g.ldb;
 
-    double2_t ra[KB / 4], rb[KB / 4];
-    double4_t acc[4][4];
+    typename Vec2<T>::t ra[KB / 4], rb[KB / 4];
+    typename Mfma<T>::acc_t acc[4][4];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = (double4_t){0.0, 0.0, 0.0, 0.0};
+        for (int j = 0; j < 4; ++j) acc[i][j] = Mfma<T>::zero();
 
-    gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt0, tid);
-    gemm_lstore<KB>(ra, rb, As[0], Bs[0], tid);
+    gemm_gload<T, KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt0, tid);
+    gemm_lstore<T, KB>(ra, rb, As[0], Bs[0], tid);
     __syncthreads();
     for (int kt = kt0; kt < kt1; ++kt) {
         const int cur = (kt - kt0) & 1;
-        if (kt + 1 < kt1) gemm_gload<KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
+        if (kt + 1 < kt1) gemm_gload<T, KB>(ra, rb, Ablk, Bblk, g.lda, g.ldb, kt + 1, tid);
 #pragma unroll
         for (int ks = 0; ks < KB / 4; ++ks) {
             const int k = ks * 4 + lk;
-            double a[4], b[4];
+            T a[4], b[4];
 #pragma unroll
             for (int t = 0; t < 4; ++t) a[t] = As[cur][k * BM + wm * 64 + t * 16 + l16];
 #pragma unroll
@@ -200,18 +206,19 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
             for (int i = 0; i < 4; ++i)
 #pragma unroll
                 for (int j = 0; j < 4; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = Mfma<T>::step(a[i], b[j], acc[i][j]);
         }
-        if (kt + 1 < kt1) gemm_lstore<KB>(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
+        if (kt + 1 < kt1) gemm_lstore<T, KB>(ra, rb, As[cur ^ 1], Bs[cur ^ 1], tid);
         __syncthreads();
     }
 
-    // Epilogue: D(row, col) of a 16x16 FP64 tile sits in lane
-    // (col + 16 * (row % 4)), element row / 4.
+    // Epilogue: element e of lane l holds row Mfma<T>::row(e, l / 16),
+    // column l % 16 of its 16 x 16 tile.
+    const T alpha = (T)g.alpha, beta = (T)g.beta;
     if (SPLIT) {
         // Partial sums, row-major: 16 lanes store 16 consecutive columns.
         const int64_t ldp = (int64_t)g.tiles_n * BN;
-        double *P = g.part + (int64_t)split * g.tiles_m * BM * ldp;
+        T *P = static_cast<T *>(g.part) + (int64_t)split * g.tiles_m * BM * ldp;
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
@@ -219,7 +226,7 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
                 const int64_t col = (int64_t)tn * BN + wn * 64 + j * 16 + l16;
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + e * 4 + lk;
+                    const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + Mfma<T>::row(e, lk);
                     P[row * ldp + col] = acc[i][j][e];
                 }
             }
@@ -234,15 +241,15 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
             const int2 cm = g.cmap[col];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + e * 4 + lk;
+                const int64_t row = (int64_t)tm * BM + wm * 64 + i * 16 + Mfma<T>::row(e, lk);
                 if (row >= g.M) continue;
                 const int2 rm = g.rmap[row];
                 const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
                 const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
                 if (blk < 0) continue;
-                double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
-                const double prod = g.alpha * acc[i][j][e];
-                *dst = (g.beta == 0.0) ? prod : fma(g.beta, *dst, prod);
+                T *dst = static_cast<T *>(g.C) + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
+                const T prod = alpha * acc[i][j][e];
+                *dst = (beta == T(0)) ? prod : fma(beta, *dst, prod);
             }
         }
     }
@@ -251,23 +258,25 @@ __global__ __launch_bounds__(256, MINB) void k_dgemm_mfma(GemmArgs g) {
 // Split-k epilogue: C(row, col) = beta C + alpha * (sum of the partials in
 // split order), written into C's blocks like the GEMM epilogue; one thread
 // per element, consecutive threads on consecutive columns.
+template <class T>
 __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
+    const T alpha = (T)g.alpha, beta = (T)g.beta;
     const int64_t ldp = (int64_t)g.tiles_n * BN;
     const int64_t plane = (int64_t)g.tiles_m * BM * ldp;
     const int64_t n = g.M * g.N;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t row = t / g.N, col = t - row * g.N;
-        const double *p = g.part + row * ldp + col;
-        double v = p[0];
+        const T *p = static_cast<const T *>(g.part) + row * ldp + col;
+        T v = p[0];
         for (int sp = 1; sp < g.splits; ++sp) v += p[sp * plane];
         const int2 rm = g.rmap[row], cm = g.cmap[col];
         const int64_t bidx = (int64_t)rm.x * g.c_nbc + cm.x;
         const int32_t blk = g.c_map ? g.c_map[bidx] : (int32_t)bidx;
         if (blk < 0) continue;
-        double *dst = g.C + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
-        const double prod = g.alpha * v;
-        *dst = (g.beta == 0.0) ? prod : fma(g.beta, *dst, prod);
+        T *dst = static_cast<T *>(g.C) + g.c_blk_off[blk] + rm.y + (int64_t)g.c_rbs[rm.x] * cm.y;
+        const T prod = alpha * v;
+        *dst = (beta == T(0)) ? prod : fma(beta, *dst, prod);
     }
 }
 
@@ -302,8 +311,11 @@ int cu_count() {
 }
 
 
-int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
-                   double alpha, double beta, hipStream_t s) {
+namespace {
+
+template <class T>
+int dense_multiply_t(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
+                     double alpha, double beta, hipStream_t s) {
     const int64_t M = A->rows(), K = A->cols(), N = B->cols();
     if (M == 0 || N == 0 || C->nnzb == 0) return BSMM_OK;
     if (alpha == 0.0 || K == 0) return scale_blocks(C, nullptr, beta, s);
@@ -315,23 +327,23 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
         return BSMM_ERANGE;
     }
     DevBuf ap, bp, cmap;
-    BSMM_TRY(ap.reserve(sizeof(double) * Mp * Kp, s));
-    BSMM_TRY(bp.reserve(sizeof(double) * Kp * Np, s));
+    BSMM_TRY(ap.reserve(sizeof(T) * Mp * Kp, s));
+    BSMM_TRY(bp.reserve(sizeof(T) * Kp * Np, s));
     // Panels need zeros where blocks are absent and in the padding.
-    if (!A->full() || Mp != M || Kp != K) BSMM_TRY(fill_zero(ap.as<double>(), Mp * Kp, s));
-    if (!B->full() || Kp != K || Np != N) BSMM_TRY(fill_zero(bp.as<double>(), Kp * Np, s));
+    if (!A->full() || Mp != M || Kp != K) BSMM_TRY(fill_zero_bytes(ap.p, sizeof(T) * Mp * Kp, s));
+    if (!B->full() || Kp != K || Np != N) BSMM_TRY(fill_zero_bytes(bp.p, sizeof(T) * Kp * Np, s));
     if (A->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge, dim3(grid_of(A->nnzb, 4)), dim3(256), 0, s, A->nbr, A->nnzb,
+        hipLaunchKernelGGL(k_merge<T>, dim3(grid_of(A->nnzb, 4)), dim3(256), 0, s, A->nbr, A->nnzb,
                            A->d_rbs(), A->d_cbs(),
                            A->d_row_off(), A->d_col_off(), A->d_row_ptr(), A->d_col_ind(),
-                           A->d_blk_off(), A->d_data(), ap.as<double>(), Mp);
+                           A->d_blk_off(), (const T *)A->d_raw(), ap.as<T>(), Mp);
         BSMM_TRY(launch_check("merge_A"));
     }
     if (B->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge, dim3(grid_of(B->nnzb, 4)), dim3(256), 0, s, B->nbr, B->nnzb,
+        hipLaunchKernelGGL(k_merge<T>, dim3(grid_of(B->nnzb, 4)), dim3(256), 0, s, B->nbr, B->nnzb,
                            B->d_rbs(), B->d_cbs(),
                            B->d_row_off(), B->d_col_off(), B->d_row_ptr(), B->d_col_ind(),
-                           B->d_blk_off(), B->d_data(), bp.as<double>(), Kp);
+                           B->d_blk_off(), (const T *)B->d_raw(), bp.as<T>(), Kp);
         BSMM_TRY(launch_check("merge_B"));
     }
     const int32_t *d_cmap = nullptr;
@@ -348,8 +360,8 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
         d_cmap = cmap.as<int32_t>();
     }
     GemmArgs g{};
-    g.Ap = ap.as<double>();
-    g.Bp = bp.as<double>();
+    g.Ap = ap.p;
+    g.Bp = bp.p;
     g.lda = Mp;
     g.ldb = Kp;
     g.tiles_m = (int)(Mp / BM);
@@ -359,7 +371,7 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     g.N = N;
     g.alpha = alpha;
     g.beta = beta;
-    g.C = C->d_data();
+    g.C = C->d_raw();
     g.c_blk_off = C->d_blk_off();
     g.c_map = d_cmap;
     g.c_nbc = C->nbc;
@@ -373,7 +385,7 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
     int64_t splits = 1;
     if (tiles < slots) {
         splits = std::min<int64_t>(ceil_div(2 * slots, tiles), g.ktiles / 16);
-        splits = std::min<int64_t>(splits, (int64_t(1) << 31) / (int64_t)(sizeof(double) * Mp * Np));
+        splits = std::min<int64_t>(splits, (int64_t(1) << 31) / (int64_t)(sizeof(T) * Mp * Np));
         splits = std::max<int64_t>(splits, 1);
     }
     DevBuf part;
@@ -381,24 +393,32 @@ int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s
         g.kt_per = (int)ceil_div(g.ktiles, splits);
         splits = ceil_div(g.ktiles, g.kt_per);  // no empty split
         g.splits = (int)splits;
-        BSMM_TRY(part.reserve(sizeof(double) * splits * Mp * Np, s));
-        g.part = part.as<double>();
+        BSMM_TRY(part.reserve(sizeof(T) * splits * Mp * Np, s));
+        g.part = part.p;
     }
     {
         KernelTimer kt(0, s);
         const dim3 grid((unsigned)(tiles * splits));
         if (splits > 1) {
-            if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<32, 1, true>), grid, dim3(256), 0, s, g);
-            else hipLaunchKernelGGL((k_dgemm_mfma<16, 2, true>), grid, dim3(256), 0, s, g);
+            if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<T, 32, 1, true>), grid, dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_dgemm_mfma<T, 16, 2, true>), grid, dim3(256), 0, s, g);
         } else {
-            if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<32, 1, false>), grid, dim3(256), 0, s, g);
-            else hipLaunchKernelGGL((k_dgemm_mfma<16, 2, false>), grid, dim3(256), 0, s, g);
+            if (KB == 32) hipLaunchKernelGGL((k_dgemm_mfma<T, 32, 1, false>), grid, dim3(256), 0, s, g);
+            else hipLaunchKernelGGL((k_dgemm_mfma<T, 16, 2, false>), grid, dim3(256), 0, s, g);
         }
     }
     BSMM_TRY(launch_check("dgemm_mfma"));
     if (splits == 1) return BSMM_OK;
-    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_of(M * N, 256, 8192)), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(k_splitk_reduce<T>, dim3(grid_of(M * N, 256, 8192)), dim3(256), 0, s, g);
     return launch_check("splitk_reduce");
+}
+
+}  // namespace
+
+int dense_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
+                   double alpha, double beta, hipStream_t s) {
+    if (C->dtype == BSMM_F32) return dense_multiply_t<float>(A, B, C, alpha, beta, s);
+    return dense_multiply_t<double>(A, B, C, alpha, beta, s);
 }
 
 }  // namespace bsmm

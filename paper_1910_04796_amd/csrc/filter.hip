@@ -8,9 +8,11 @@ namespace bsmm {
 
 namespace {
 
-// One wave per block: keep flag and kept element count.
+// One wave per block: keep flag and kept element count (squares summed in
+// FP64 for either element type).
+template <class T>
 __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *blk_off,
-                                                   const double *data, double eps2,
+                                                   const T *data, double eps2,
                                                    int64_t *keep, int64_t *keep_elems) {
     const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (b >= nnzb) return;
@@ -19,15 +21,15 @@ __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *
     double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
     int64_t e = lane_id();
     for (; e + 3 * kWave < len; e += 4 * kWave) {
-        const double x0 = data[o + e], x1 = data[o + e + kWave];
-        const double x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
+        const double x0 = (double)data[o + e], x1 = (double)data[o + e + kWave];
+        const double x2 = (double)data[o + e + 2 * kWave], x3 = (double)data[o + e + 3 * kWave];
         s0 = fma(x0, x0, s0);
         s1 = fma(x1, x1, s1);
         s2 = fma(x2, x2, s2);
         s3 = fma(x3, x3, s3);
     }
     for (; e < len; e += kWave) {
-        const double x = data[o + e];
+        const double x = (double)data[o + e];
         s0 = fma(x, x, s0);
     }
     double s = wave_sum((s0 + s1) + (s2 + s3));
@@ -47,11 +49,11 @@ __global__ __launch_bounds__(256) void k_new_row_ptr(int32_t nbr, int64_t nnzb, 
 }
 
 // One wave per old block: kept blocks move to their new place.
+template <class T>
 __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci,
-                                                 const int64_t *blk_off, const double *data,
+                                                 const int64_t *blk_off, const T *data,
                                                  const int64_t *kpos, const int64_t *epos,
-                                                 int32_t *new_ci, int64_t *new_off,
-                                                 double *new_data) {
+                                                 int32_t *new_ci, int64_t *new_off, T *new_data) {
     const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (b >= nnzb) return;
     if (kpos[b + 1] == kpos[b]) return;  // dropped
@@ -63,8 +65,8 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
     }
     int64_t e = lane_id();
     for (; e + 3 * kWave < len; e += 4 * kWave) {
-        const double x0 = data[o + e], x1 = data[o + e + kWave];
-        const double x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
+        const T x0 = data[o + e], x1 = data[o + e + kWave];
+        const T x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
         new_data[no + e] = x0;
         new_data[no + e + kWave] = x1;
         new_data[no + e + 2 * kWave] = x2;
@@ -84,8 +86,14 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     BSMM_TRY(kel.reserve(sizeof(int64_t) * (nnzb + 1), s));
     BSMM_TRY(kpos.reserve(sizeof(int64_t) * (nnzb + 1), s));
     BSMM_TRY(epos.reserve(sizeof(int64_t) * (nnzb + 1), s));
-    hipLaunchKernelGGL(k_norm_keep, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb, C->d_blk_off(),
-                       C->d_data(), eps * eps, keep.as<int64_t>(), kel.as<int64_t>());
+    if (C->dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_norm_keep<float>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
+                           C->d_blk_off(), (const float *)C->d_raw(), eps * eps, keep.as<int64_t>(),
+                           kel.as<int64_t>());
+    else
+        hipLaunchKernelGGL(k_norm_keep<double>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
+                           C->d_blk_off(), (const double *)C->d_raw(), eps * eps, keep.as<int64_t>(),
+                           kel.as<int64_t>());
     BSMM_TRY(launch_check("norm_keep"));
     BSMM_TRY(scan_exclusive_i64(keep.as<int64_t>(), kpos.as<int64_t>(), nnzb, s));
     BSMM_TRY(scan_exclusive_i64(kel.as<int64_t>(), epos.as<int64_t>(), nnzb, s));
@@ -103,15 +111,21 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     BSMM_TRY(n_rp.reserve(sizeof(int64_t) * (C->nbr + 1), s));
     BSMM_TRY(n_ci.reserve(sizeof(int32_t) * (new_nnzb + 1), s));
     BSMM_TRY(n_off.reserve(sizeof(int64_t) * (new_nnzb + 1), s));
-    BSMM_TRY(n_data.reserve(sizeof(double) * (new_elems + 1), s));
+    BSMM_TRY(n_data.reserve(C->esize() * (new_elems + 1), s));
     hipLaunchKernelGGL(k_new_row_ptr, dim3(grid_of(C->nbr + 1, 256)), dim3(256), 0, s, C->nbr,
                        nnzb, C->d_row_ptr(), (const int64_t *)kpos.as<int64_t>(), n_rp.as<int64_t>(),
                        n_off.as<int64_t>(), new_elems);
     BSMM_TRY(launch_check("new_row_ptr"));
-    hipLaunchKernelGGL(k_compact, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb, C->d_col_ind(),
-                       C->d_blk_off(), C->d_data(), (const int64_t *)kpos.as<int64_t>(),
-                       (const int64_t *)epos.as<int64_t>(), n_ci.as<int32_t>(), n_off.as<int64_t>(),
-                       n_data.as<double>());
+    if (C->dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_compact<float>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
+                           C->d_col_ind(), C->d_blk_off(), (const float *)C->d_raw(),
+                           (const int64_t *)kpos.as<int64_t>(), (const int64_t *)epos.as<int64_t>(),
+                           n_ci.as<int32_t>(), n_off.as<int64_t>(), n_data.as<float>());
+    else
+        hipLaunchKernelGGL(k_compact<double>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
+                           C->d_col_ind(), C->d_blk_off(), (const double *)C->d_raw(),
+                           (const int64_t *)kpos.as<int64_t>(), (const int64_t *)epos.as<int64_t>(),
+                           n_ci.as<int32_t>(), n_off.as<int64_t>(), n_data.as<double>());
     BSMM_TRY(launch_check("compact"));
     C->b_row_ptr = std::move(n_rp);
     C->b_col_ind = std::move(n_ci);

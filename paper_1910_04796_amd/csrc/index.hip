@@ -166,11 +166,12 @@ __global__ __launch_bounds__(256) void k_full_pattern(int32_t nbr, int32_t nbc, 
 // ---------------------------------------------------------- relayout
 // One workgroup per new block row; each wave copies whole blocks: the old
 // block (found by binary search in the old row) or zeros.
+template <class T>
 __global__ __launch_bounds__(256) void k_relayout(const int32_t *rbs, const int32_t *cbs,
                                                   const int64_t *o_rp, const int32_t *o_ci,
-                                                  const int64_t *o_off, const double *o_data,
+                                                  const int64_t *o_off, const T *o_data,
                                                   const int64_t *n_rp, const int32_t *n_ci,
-                                                  const int64_t *n_off, double *n_data) {
+                                                  const int64_t *n_off, T *n_data) {
     const int32_t row = blockIdx.x;
     const int nw = blockDim.x / kWave;
     const int64_t m = rbs[row];
@@ -185,28 +186,28 @@ __global__ __launch_bounds__(256) void k_relayout(const int32_t *rbs, const int3
             else { found = mid; break; }
         }
         const int64_t len = m * cbs[j];
-        double *dst = n_data + n_off[p];
+        T *dst = n_data + n_off[p];
         if (found >= 0) {
-            const double *src = o_data + o_off[found];
+            const T *src = o_data + o_off[found];
             for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = src[e];
         } else {
-            for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = 0.0;
+            for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = T(0);
         }
     }
 }
 
 // One wave per block: data *= beta, or zeros when beta == 0, for the blocks
 // whose flag is zero.
+template <class T>
 __global__ __launch_bounds__(256) void k_scale_blocks(int64_t nnzb, const int64_t *blk_off,
-                                                      const int64_t *flags, double beta,
-                                                      double *data) {
+                                                      const int64_t *flags, T beta, T *data) {
     const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     if (b >= nnzb) return;
     if (flags && flags[b] != 0) return;
-    double *d = data + blk_off[b];
+    T *d = data + blk_off[b];
     const int64_t len = blk_off[b + 1] - blk_off[b];
-    if (beta == 0.0)
-        for (int64_t e = lane_id(); e < len; e += kWave) d[e] = 0.0;
+    if (beta == T(0))
+        for (int64_t e = lane_id(); e < len; e += kWave) d[e] = T(0);
     else
         for (int64_t e = lane_id(); e < len; e += kWave) d[e] *= beta;
 }
@@ -215,6 +216,12 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *p, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x)
         p[e] = 0.0;
+}
+
+__global__ __launch_bounds__(256) void k_fill_zero_u32(uint32_t *p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
 }
 
 }  // namespace
@@ -290,18 +297,29 @@ int full_pattern(int32_t nbr, int32_t nbc, int64_t ncols, int64_t *d_row_ptr,
 }
 
 int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *d_new_ci,
-             const int64_t *d_new_off, double *d_new_data, hipStream_t s) {
+             const int64_t *d_new_off, void *d_new_data, hipStream_t s) {
     if (Cold->nbr == 0) return BSMM_OK;
-    hipLaunchKernelGGL(k_relayout, dim3(Cold->nbr), dim3(256), 0, s, Cold->d_rbs(), Cold->d_cbs(),
-                       Cold->d_row_ptr(), Cold->d_col_ind(), Cold->d_blk_off(), Cold->d_data(),
-                       d_new_rp, d_new_ci, d_new_off, d_new_data);
+    if (Cold->dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_relayout<float>, dim3(Cold->nbr), dim3(256), 0, s, Cold->d_rbs(),
+                           Cold->d_cbs(), Cold->d_row_ptr(), Cold->d_col_ind(), Cold->d_blk_off(),
+                           (const float *)Cold->d_raw(), d_new_rp, d_new_ci, d_new_off,
+                           (float *)d_new_data);
+    else
+        hipLaunchKernelGGL(k_relayout<double>, dim3(Cold->nbr), dim3(256), 0, s, Cold->d_rbs(),
+                           Cold->d_cbs(), Cold->d_row_ptr(), Cold->d_col_ind(), Cold->d_blk_off(),
+                           (const double *)Cold->d_raw(), d_new_rp, d_new_ci, d_new_off,
+                           (double *)d_new_data);
     return launch_check("relayout");
 }
 
 int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hipStream_t s) {
     if (C->nnzb == 0) return BSMM_OK;
-    hipLaunchKernelGGL(k_scale_blocks, dim3(grid_of(C->nnzb, 4)), dim3(256), 0, s, C->nnzb,
-                       C->d_blk_off(), d_flags, beta, C->d_data());
+    if (C->dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_scale_blocks<float>, dim3(grid_of(C->nnzb, 4)), dim3(256), 0, s, C->nnzb,
+                           C->d_blk_off(), d_flags, (float)beta, (float *)C->d_raw());
+    else
+        hipLaunchKernelGGL(k_scale_blocks<double>, dim3(grid_of(C->nnzb, 4)), dim3(256), 0, s,
+                           C->nnzb, C->d_blk_off(), d_flags, beta, (double *)C->d_raw());
     return launch_check("scale_blocks");
 }
 
@@ -309,6 +327,14 @@ int fill_zero(double *p, int64_t n, hipStream_t s) {
     if (n <= 0) return BSMM_OK;
     hipLaunchKernelGGL(k_fill_zero, dim3(grid_of(n, 256, 16384)), dim3(256), 0, s, p, n);
     return launch_check("fill_zero");
+}
+
+int fill_zero_bytes(void *p, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return BSMM_OK;
+    if (bytes % sizeof(double) == 0) return fill_zero((double *)p, (int64_t)(bytes / sizeof(double)), s);
+    hipLaunchKernelGGL(k_fill_zero_u32, dim3(grid_of((int64_t)(bytes / 4), 256, 16384)), dim3(256), 0, s,
+                       (uint32_t *)p, (int64_t)(bytes / 4));
+    return launch_check("fill_zero_u32");
 }
 
 }  // namespace bsmm

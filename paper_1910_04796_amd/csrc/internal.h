@@ -59,6 +59,8 @@ struct Options {
     std::string tune_db;
     std::string mlp_weights;
     int forced[4] = {0, 0, 0, 0};  // "stack_params": tm tn kc waves for every class
+    int stack_tile = 32;   // tuned path: > 0 runs MFMA classes in one launch, tiles of this many blocks
+    int stack_sched = 1;   // scheduled kernel: 0 static XCD-aware striding, 1 dynamic run counter
 };
 Options &options();
 
@@ -165,6 +167,7 @@ struct bsmm_matrix_s {
     int64_t nnzb = 0, nelems = 0;
     int32_t max_rbs = 0, max_cbs = 0;
     int device = 0;
+    int dtype = BSMM_F64;          // element type of the block data
     hipStream_t last_stream = nullptr;
     uint64_t version = 0;          // changes whenever the pattern or a buffer changes
     bsmm::Plan *plan = nullptr;    // cached multiply plan of which this matrix is C
@@ -183,6 +186,8 @@ struct bsmm_matrix_s {
     int32_t *d_col_ind() const { return b_col_ind.as<int32_t>(); }
     int64_t *d_blk_off() const { return b_blk_off.as<int64_t>(); }
     double *d_data() const { return b_data.as<double>(); }
+    void *d_raw() const { return b_data.p; }
+    size_t esize() const { return dtype == BSMM_F32 ? sizeof(float) : sizeof(double); }
     int64_t rows() const { return row_off.empty() ? 0 : row_off.back(); }
     int64_t cols() const { return col_off.empty() ? 0 : col_off.back(); }
     bool full() const { return nnzb == (int64_t)nbr * (int64_t)nbc; }
@@ -220,11 +225,12 @@ int full_pattern(int32_t nbr, int32_t nbc, int64_t ncols, int64_t *d_row_ptr,
                  int32_t *d_col_ind, int64_t *d_row_elems, const int32_t *d_rbs, hipStream_t s);
 // Copies old C blocks into the new layout (zeros for new blocks).
 int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *d_new_ci,
-             const int64_t *d_new_off, double *d_new_data, hipStream_t s);
+             const int64_t *d_new_off, void *d_new_data, hipStream_t s);
 // data *= beta (beta == 0 writes zeros) over the blocks whose flag is zero
 // (flags == nullptr: every block).
 int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hipStream_t s);
 int fill_zero(double *p, int64_t n, hipStream_t s);
+int fill_zero_bytes(void *p, size_t bytes, hipStream_t s);
 
 // ---------------------------------------------------------------- stacks
 // A product entry keeps A's element offset in 48 bits and k in 16 bits.
@@ -251,6 +257,9 @@ struct Stacks {
     DevBuf d_rsi, d_csi, missing;     // size-class index of rows / columns; pattern flag
     int kparts = 1;                   // parts per A block row in count and fill
     DevBuf pcount;                    // int64[C.nnzb * kparts]: first position of each part (kparts > 1)
+    DevBuf sched;                     // uint64[n_sched]: scheduled runs (run << 16 | m << 8 | n)
+    int64_t n_sched = 0;
+    DevBuf sched_next;                // uint64 run counter of the dynamic schedule
     std::vector<char> class_active;   // class holds runs (any panel so far)
     std::vector<int> run_len_hint;    // mean run length per class over every panel (else empty)
 };
@@ -269,6 +278,11 @@ int stack_row_bounds(const bsmm_matrix_s *C, const Stacks &st, std::vector<int64
 // any) of every class over all C block rows.
 int stack_class_run_lengths(const bsmm_matrix_s *C, const Stacks &st, std::vector<int> *out,
                             hipStream_t s);
+// The scheduled kernel's run order: the runs of the classes flagged in
+// `eligible` (one flag per class), grouped by tiles of tile x tile C blocks
+// (tiles in row-major order), with each entry's block shape.
+int build_schedule(const bsmm_matrix_s *C, Stacks &st, const std::vector<char> &eligible, int tile,
+                   hipStream_t s);
 // After stack_count: the runs and products of C block rows [r0, r1) (C
 // blocks [c0, c1), nprod products), replacing the previous panel's.
 int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
@@ -294,9 +308,9 @@ int cu_count();
 constexpr int kMlpMaxRunLen = 32;
 // Kernel arguments of one small-block launch.
 struct SmmArgs {
-    const double *A;
-    const double *B;
-    double *C;
+    const void *A;          // block data of the matrix's element type
+    const void *B;
+    void *C;
     const int64_t *run_coff;
     const int64_t *run_ptr;
     const ulonglong2 *prods;
@@ -314,7 +328,15 @@ struct SmmArgs {
     // to part[((r - run_begin) * split + segment) * m * n] (column-major)
     // and k_smm_split_reduce applies the epilogue.
     int split;
-    double *part;
+    void *part;
+    // Scheduled MFMA kernel (one launch for every class with blocks up to
+    // 32 x 32): entries run << 16 | m << 8 | n in tile order; mode 0 static
+    // XCD-aware striding, 1 a run counter (*next, zeroed before the launch).
+    const unsigned long long *sched;
+    int64_t n_sched;
+    unsigned long long *next;
+    int sched_mode;
+    int sched_chunk;        // schedule entries taken per wave at a time
 };
 // A planned launch: kernel, shape-dependent arguments, block size, LDS.
 struct SmmLaunch {
@@ -322,10 +344,12 @@ struct SmmLaunch {
     SmmArgs args{};
     int waves = 1;
     size_t lds = 0;
+    int dtype = BSMM_F64;   // element type the kernel was planned for
 };
-int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out);
+// dtype: BSMM_F64 or BSMM_F32 (the kernel and the LDS budget follow it).
+int plan_smm(const SmmParams &prm, int m, int n, int kmax, int dtype, SmmLaunch *out);
 unsigned smm_grid(const SmmLaunch &L, int64_t nruns);
-int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const int64_t *run_coff,
+int launch_smm(SmmLaunch L, const void *A, const void *B, void *C, const int64_t *run_coff,
                const int64_t *run_ptr, const ulonglong2 *prods, int64_t rb, int64_t re,
                double alpha, double beta, hipStream_t s);
 using LaunchList = std::vector<std::pair<SmmLaunch, std::pair<int64_t, int64_t>>>;
@@ -359,8 +383,8 @@ std::vector<SmmParams> candidate_params(int m, int n, int k);
 bool mlp_select(int m, int n, int k, int run_len, SmmParams *out);
 // Plans and launches the stack kernels; the launches (and the instantiated
 // graph of the tuned path) are kept in *ex for replay.
-int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
-               const Stacks &st, double alpha, double beta, hipStream_t s, StackExec *ex);
+int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, Stacks &st,
+               double alpha, double beta, hipStream_t s, StackExec *ex);
 int build_graph(const LaunchList &launches, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
                 bsmm_matrix_s *C, const Stacks &st, double alpha, double beta,
                 hipGraphExec_t *out);

@@ -123,7 +123,7 @@ int symbolic(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, SymbolicTotal
 int install_pattern(bsmm_matrix_s *C, const SymbolicTotals &tot, NewPattern &np,
                     const DevBuf &row_elems, double beta, hipStream_t s) {
     BSMM_TRY(np.off.reserve(sizeof(int64_t) * (tot.nnzb + 1), s));
-    BSMM_TRY(np.data.reserve(sizeof(double) * (tot.nelems + 1), s));
+    BSMM_TRY(np.data.reserve(C->esize() * (tot.nelems + 1), s));
     BSMM_TRY(build_block_offsets(C->d_rbs(), C->d_cbs(), C->nbr, np.rp.as<int64_t>(),
                                  np.ci.as<int32_t>(), tot.nnzb, np.off.as<int64_t>(),
                                  row_elems.as<int64_t>(), s));
@@ -133,9 +133,9 @@ int install_pattern(bsmm_matrix_s *C, const SymbolicTotals &tot, NewPattern &np,
     if (beta != 0.0) {
         if (C->nnzb > 0)
             BSMM_TRY(relayout(C, np.rp.as<int64_t>(), np.ci.as<int32_t>(), np.off.as<int64_t>(),
-                              np.data.as<double>(), s));
+                              np.data.p, s));
         else
-            BSMM_TRY(fill_zero(np.data.as<double>(), tot.nelems, s));
+            BSMM_TRY(fill_zero_bytes(np.data.p, C->esize() * tot.nelems, s));
     }
     C->b_row_ptr = std::move(np.rp);
     C->b_col_ind = std::move(np.ci);
@@ -156,9 +156,9 @@ int active_classes(const Stacks &st) {
 // Options that change what a plan computes.
 std::string plan_key(const Options &o) {
     char buf[128];
-    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d|", o.path, o.stack_kernel,
+    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
              (long long)o.stack_chunk, (long long)o.stack_panel, o.emul_slices, o.forced[0],
-             o.forced[1], o.forced[2], o.forced[3]);
+             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched);
     return std::string(buf) + o.tune_db + "|" + o.mlp_weights;
 }
 
@@ -183,6 +183,10 @@ void free_plan(Plan *p) { delete p; }
 // C's block columns in LDS.
 int check_stack_limits(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
                        const Options &o) {
+    if (o.path == 3 && C->dtype != BSMM_F64) {
+        set_error(BSMM_ENOTSUP, "the split-precision emulation computes FP64 products only");
+        return BSMM_ENOTSUP;
+    }
     const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
     if (o.path == 3 || dense) return BSMM_OK;
     if (A->max_cbs > kMaxStackK) {
@@ -208,7 +212,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
     std::vector<int64_t> pb, cb;
     BSMM_TRY(stack_row_bounds(C, st, &pb, &cb, s));
     if (options().stack_kernel == 1) BSMM_TRY(stack_class_run_lengths(C, st, &st.run_len_hint, s));
-    int64_t runs = 0;
+    int64_t runs = 0, sched = 0;
     for (int32_t r0 = 0; r0 < C->nbr;) {
         int32_t r1 = r0 + 1;
         while (r1 < C->nbr && pb[r1 + 1] - pb[r0] <= cap) ++r1;
@@ -217,6 +221,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
             StackExec ex;  // a graph is retired only after its launch has completed
             BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s, &ex));
             runs += st.n_runs;
+            sched += st.n_sched;
             ++*n_panels;
             if (options().verbose) {
                 // Host progress of a long multiply (the panel is queued, not finished).
@@ -228,6 +233,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
         r0 = r1;
     }
     st.n_runs = runs;
+    st.n_sched = sched;
     st.n_prod = pb[C->nbr];
     return BSMM_OK;
 }
@@ -281,6 +287,7 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         stt.n_products = pl->tot.nprod;
         stt.flops = pl->tot.flops;
         stt.n_runs = pl->st.n_runs;
+        stt.n_sched_runs = pl->st.n_sched;
         stt.n_classes = active_classes(pl->st);
     } else {
         free_plan(C->plan);
@@ -306,6 +313,7 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         }
         stt.path = path;
         stt.n_runs = p->st.n_runs;
+        stt.n_sched_runs = p->st.n_sched;
         stt.n_classes = active_classes(p->st);
         // A multiply built in several row panels keeps no stacks to replay.
         if (o.plan_cache && stt.n_row_panels <= 1) {
@@ -361,6 +369,7 @@ int multiply_fixed_pattern(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, dou
     stt.n_products = tot.nprod;
     stt.flops = tot.flops;
     stt.n_runs = st.n_runs;
+    stt.n_sched_runs = st.n_sched;
     stt.n_classes = active_classes(st);
     return BSMM_OK;
 }

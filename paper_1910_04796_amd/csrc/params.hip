@@ -192,7 +192,7 @@ extern "C" int bsmm_tune_shape(int32_t m, int32_t n, int32_t k, int64_t n_runs, 
     for (int32_t c = 0; c < n_cands && status == BSMM_OK; ++c) {
         SmmParams prm{cands[4 * c], cands[4 * c + 1], cands[4 * c + 2], cands[4 * c + 3]};
         SmmLaunch L;
-        if (plan_smm(prm, m, n, k, &L) != BSMM_OK) {
+        if (plan_smm(prm, m, n, k, BSMM_F64, &L) != BSMM_OK) {
             out_us[c] = -1.0;
             clear_error();
             continue;

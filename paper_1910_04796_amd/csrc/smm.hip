@@ -26,19 +26,25 @@
 
 #include "dev_util.h"
 #include "internal.h"
+#include "mfma_util.h"
 
 namespace bsmm {
 
 namespace {
 
-template <int TM, int TN>
+template <class T, int TM, int TN>
 __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];
+    T *lds = reinterpret_cast<T *>(lds_raw);
+    const T *A = static_cast<const T *>(p.A);
+    const T *B = static_cast<const T *>(p.B);
+    T *C = static_cast<T *>(p.C);
+    const T alpha = (T)p.alpha, beta = (T)p.beta;
     const int lane = lane_id();
     const int g = lane / p.L;
     const int gl = lane - g * p.L;
     const bool in_group = g < p.G;
-    double *reg = lds + (size_t)(wave_id() * p.G + (in_group ? g : 0)) * p.region;
+    T *reg = lds + (size_t)(wave_id() * p.G + (in_group ? g : 0)) * p.region;
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     const int m = p.m, n = p.n;
@@ -56,11 +62,11 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
             const int it = tile_ok ? t % p.tiles_m : 0;
             const int jt = tile_ok ? t / p.tiles_m : 0;
             const int i0 = it * TM, j0 = jt * TN;
-            double acc[TM][TN];
+            T acc[TM][TN];
 #pragma unroll
             for (int a = 0; a < TM; ++a)
 #pragma unroll
-                for (int b = 0; b < TN; ++b) acc[a][b] = 0.0;
+                for (int b = 0; b < TN; ++b) acc[a][b] = T(0);
 
             for (int64_t qi = 0; qi < nq; ++qi) {
                 const bool act = has && qi < q1 - q0;
@@ -74,11 +80,11 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
                     const int kc = act ? std::min(p.kc_max, k - kc0) : 0;
                     // stage A(:, kc0:kc0+kc) (contiguous) and B(kc0:kc0+kc, :)
                     if (kc > 0) {
-                        const double *ga = p.A + a_off + (int64_t)m * kc0;
+                        const T *ga = A + a_off + (int64_t)m * kc0;
                         const int na = m * kc;
                         for (int e = gl; e < na; e += p.L) reg[e] = ga[e];
-                        double *rbuf = reg + na;
-                        const double *gb = p.B + b_off + kc0;
+                        T *rbuf = reg + na;
+                        const T *gb = B + b_off + kc0;
                         if (kc == k) {
                             const int nb = k * n;
                             for (int e = gl; e < nb; e += p.L) rbuf[e] = gb[e];
@@ -94,10 +100,10 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
                     }
                     wave_lds_sync();
                     if (tile_ok && kc > 0) {
-                        const double *As = reg + i0;
-                        const double *Bs = reg + m * kc + (int64_t)j0 * kc;
+                        const T *As = reg + i0;
+                        const T *Bs = reg + m * kc + (int64_t)j0 * kc;
                         for (int kk = 0; kk < kc; ++kk) {
-                            double av[TM], bv[TN];
+                            T av[TM], bv[TN];
 #pragma unroll
                             for (int a = 0; a < TM; ++a) av[a] = As[kk * m + a];
 #pragma unroll
@@ -112,7 +118,7 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
                 }
             }
             if (tile_ok) {
-                double *c = p.C + p.run_coff[r];
+                T *c = C + p.run_coff[r];
 #pragma unroll
                 for (int b = 0; b < TN; ++b) {
                     const int j = j0 + b;
@@ -121,9 +127,9 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
                     for (int a = 0; a < TM; ++a) {
                         const int i = i0 + a;
                         if (i < m) {
-                            double *dst = c + (int64_t)j * m + i;
-                            const double prod = p.alpha * acc[a][b];
-                            *dst = (p.beta == 0.0) ? prod : fma(p.beta, *dst, prod);
+                            T *dst = c + (int64_t)j * m + i;
+                            const T prod = alpha * acc[a][b];
+                            *dst = (beta == T(0)) ? prod : fma(beta, *dst, prod);
                         }
                     }
                 }
@@ -132,23 +138,105 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
     }
 }
 
-// FP64 MFMA variant for blocks of at least about 16 x 16 (parameter set
+// MFMA variant for blocks of at least about 16 x 16 (parameter set
 // tm = tn = 16): one wave owns one run at a time and keeps the C block as
-// MT x NT tiles of v_mfma_f64_16x16x4 accumulators (m <= 16 MT, n <= 16 NT).
-// Operands come straight from the contiguous A and B blocks (each product's
-// blocks are a few KB and stay in L1/L2), zero outside the block, so 23- or
-// 13-sized blocks are padded in registers only.
-// Result element e of lane l is row 4 e + l / 16, column l % 16 of a tile.
-typedef double v4d_t __attribute__((ext_vector_type(4)));
-typedef double v2d_t __attribute__((ext_vector_type(2)));
-
-template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
+// MT x NT tiles of 16 x 16 x 4 MFMA accumulators (m <= 16 MT, n <= 16 NT):
+// v_mfma_f64_16x16x4 for FP64, v_mfma_f32_16x16x4 for FP32.  Operands come
+// straight from the contiguous A and B blocks (each product's blocks are a
+// few KB and stay in L1/L2), zero outside the block, so 23- or 13-sized
+// blocks are padded in registers only.  Both instructions take lane l's
+// operands at row (or column) l % 16 and k = l / 16 of the step.
+// Products [q0, q1) of one run into the MT x NT accumulator tiles of an
+// m x n C block.
+template <class T, int MT, int NT>
+__device__ __forceinline__ void mfma_products(const SmmArgs &p, int m, int n, int64_t q0, int64_t q1,
+                                              typename Mfma<T>::acc_t (&acc)[MT][NT]) {
     const int lane = lane_id();
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<T>::zero();
+    const T *A = static_cast<const T *>(p.A);
+    const T *B = static_cast<const T *>(p.B);
+    // The next product's descriptor is loaded one product ahead.
+    ulonglong2 nxt = q0 < q1 ? p.prods[q0] : make_ulonglong2(0ull, 0ull);
+    for (int64_t q = q0; q < q1; ++q) {
+        const ulonglong2 pr = nxt;
+        if (q + 1 < q1) nxt = p.prods[q + 1];
+        const T *a = A + (int64_t)(pr.x & ((1ull << 48) - 1));
+        const int k = (int)(pr.x >> 48);
+        const T *b = B + (int64_t)pr.y;
+        for (int k0 = 0; k0 < k; k0 += 16) {
+            // Four k steps of fragments, then their MFMAs.  Lane group
+            // g = l / 16 supplies k = k0 + 4 g + s to step s (any
+            // assignment of k to steps is valid when A and B agree), so a
+            // lane's B operands are four consecutive values of a column.
+            T af[4][MT], bf[4][NT];
+            const int kb = k0 + 4 * lk;
+#pragma unroll
+            for (int i = 0; i < MT; ++i) {
+                const int row = 16 * i + lr;
+#pragma unroll
+                for (int s = 0; s < 4; ++s)
+                    af[s][i] = (row < m && kb + s < k) ? a[(int64_t)(kb + s) * m + row] : T(0);
+            }
+#pragma unroll
+            for (int j = 0; j < NT; ++j) {
+                const int col = 16 * j + lr;
+                const T *bc = b + (int64_t)col * k + kb;
+                if (col < n && kb + 3 < k) {
+                    T v[4];
+                    Mfma<T>::load4(bc, v);
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) bf[s][j] = v[s];
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) bf[s][j] = (col < n && kb + s < k) ? bc[s] : T(0);
+                }
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<T>::step(af[s][i], bf[s][j], acc[i][j]);
+        }
+    }
+}
+
+// C block (column-major, ld = m) <- beta C + alpha acc, or the unscaled
+// accumulators into a partial block when alpha is not applied here.
+template <class T, int MT, int NT>
+__device__ __forceinline__ void mfma_store(T *c, int m, int n,
+                                           const typename Mfma<T>::acc_t (&acc)[MT][NT],
+                                           bool partial, T alpha, T beta) {
+    const int lane = lane_id();
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * i + Mfma<T>::row(e, lk), col = 16 * j + lr;
+                if (row < m && col < n) {
+                    T *dst = c + (int64_t)col * m + row;
+                    if (partial) {
+                        *dst = acc[i][j][e];
+                    } else {
+                        const T prod = alpha * acc[i][j][e];
+                        *dst = (beta == T(0)) ? prod : fma(beta, *dst, prod);
+                    }
+                }
+            }
+}
+
+template <class T, int MT, int NT>
+__global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     const int64_t wid = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     const int m = p.m, n = p.n;
-    const int lr = lane & 15, lk = lane >> 4;
     const int S = p.split > 1 ? p.split : 1;
     const int64_t items = (p.run_end - p.run_begin) * S;
     for (int64_t it = wid; it < items; it += waves) {
@@ -158,157 +246,152 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
         const int sg = (int)(it % S);
         const int64_t rq0 = p.run_ptr[r], len = p.run_ptr[r + 1] - rq0;
         const int64_t q0 = rq0 + len * sg / S, q1 = rq0 + len * (sg + 1) / S;
-        v4d_t acc[MT][NT];
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-#pragma unroll
-            for (int j = 0; j < NT; ++j) acc[i][j] = (v4d_t){0.0, 0.0, 0.0, 0.0};
-        // The next product's descriptor is loaded one product ahead.
-        ulonglong2 nxt = q0 < q1 ? p.prods[q0] : make_ulonglong2(0ull, 0ull);
-        for (int64_t q = q0; q < q1; ++q) {
-            const ulonglong2 pr = nxt;
-            if (q + 1 < q1) nxt = p.prods[q + 1];
-            const double *a = p.A + (int64_t)(pr.x & ((1ull << 48) - 1));
-            const int k = (int)(pr.x >> 48);
-            const double *b = p.B + (int64_t)pr.y;
-            for (int k0 = 0; k0 < k; k0 += 16) {
-                // Four k steps of fragments, then their MFMAs.  Lane group
-                // g = l / 16 supplies k = k0 + 4 g + s to step s (any
-                // assignment of k to steps is valid when A and B agree), so a
-                // lane's B operands are four consecutive doubles of a column.
-                double af[4][MT], bf[4][NT];
-                const int kb = k0 + 4 * lk;
-#pragma unroll
-                for (int i = 0; i < MT; ++i) {
-                    const int row = 16 * i + lr;
-#pragma unroll
-                    for (int s = 0; s < 4; ++s)
-                        af[s][i] = (row < m && kb + s < k) ? a[(int64_t)(kb + s) * m + row] : 0.0;
-                }
-#pragma unroll
-                for (int j = 0; j < NT; ++j) {
-                    const int col = 16 * j + lr;
-                    const double *bc = b + (int64_t)col * k + kb;
-                    if (col < n && kb + 3 < k) {
-                        // 16-byte loads at 8-byte alignment (dword alignment
-                        // is all the vector loads need).
-                        v2d_t lo, hi;
-                        __builtin_memcpy(&lo, bc, sizeof lo);
-                        __builtin_memcpy(&hi, bc + 2, sizeof hi);
-                        bf[0][j] = lo[0];
-                        bf[1][j] = lo[1];
-                        bf[2][j] = hi[0];
-                        bf[3][j] = hi[1];
-                    } else {
-#pragma unroll
-                        for (int s = 0; s < 4; ++s) bf[s][j] = (col < n && kb + s < k) ? bc[s] : 0.0;
-                    }
-                }
-#pragma unroll
-                for (int s = 0; s < 4; ++s)
-#pragma unroll
-                    for (int i = 0; i < MT; ++i)
-#pragma unroll
-                        for (int j = 0; j < NT; ++j)
-                            acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[s][i], bf[s][j], acc[i][j],
-                                                                             0, 0, 0);
-            }
-        }
-        if (S > 1) {
-            double *w = p.part + it * (int64_t)m * n;
-#pragma unroll
-            for (int i = 0; i < MT; ++i)
-#pragma unroll
-                for (int j = 0; j < NT; ++j)
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        const int row = 16 * i + 4 * e + lk, col = 16 * j + lr;
-                        if (row < m && col < n) w[(int64_t)col * m + row] = acc[i][j][e];
-                    }
-            continue;
-        }
-        double *c = p.C + p.run_coff[r];
-#pragma unroll
-        for (int i = 0; i < MT; ++i)
-#pragma unroll
-            for (int j = 0; j < NT; ++j)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int row = 16 * i + 4 * e + lk, col = 16 * j + lr;
-                    if (row < m && col < n) {
-                        double *dst = c + (int64_t)col * m + row;
-                        const double prod = p.alpha * acc[i][j][e];
-                        *dst = (p.beta == 0.0) ? prod : fma(p.beta, *dst, prod);
-                    }
-                }
+        typename Mfma<T>::acc_t acc[MT][NT];
+        mfma_products<T, MT, NT>(p, m, n, q0, q1, acc);
+        if (S > 1)
+            mfma_store<T, MT, NT>(static_cast<T *>(p.part) + it * (int64_t)m * n, m, n, acc, true, T(0),
+                                  T(0));
+        else
+            mfma_store<T, MT, NT>(static_cast<T *>(p.C) + p.run_coff[r], m, n, acc, false, (T)p.alpha,
+                                  (T)p.beta);
     }
 }
 
+// Runs of every class with C blocks up to 32 x 32 in one launch, in the
+// order of a schedule that groups the runs by 2-D tiles of C blocks: the
+// waves in flight then work on nearby block rows and block columns and
+// share their A and B blocks in the caches.  Schedule entry: run << 16 |
+// m << 8 | n.  Static mode: wave slots are numbered XCD by XCD (workgroup g
+// runs on XCD g % 8), so each XCD takes a contiguous part of every window
+// of in-flight runs; dynamic mode: waves take the next run from a counter.
+template <class T, int MT, int NT>
+__device__ __forceinline__ void sched_run(const SmmArgs &p, int64_t r, int m, int n) {
+    typename Mfma<T>::acc_t acc[MT][NT];
+    mfma_products<T, MT, NT>(p, m, n, p.run_ptr[r], p.run_ptr[r + 1], acc);
+    mfma_store<T, MT, NT>(static_cast<T *>(p.C) + p.run_coff[r], m, n, acc, false, (T)p.alpha,
+                          (T)p.beta);
+}
+
+constexpr int kXcds = 8;
+// Fewest runs for which the MFMA classes go through the scheduled launch.
+constexpr int64_t kSchedMinRuns = 4096;
+
+template <class T>
+__global__ __launch_bounds__(256, 4) void k_smm_mfma_sched(SmmArgs p) {
+    const int wpw = blockDim.x / kWave;
+    const int64_t waves = (int64_t)gridDim.x * wpw;
+    // A wave takes `chunk` consecutive entries at a time (short runs: fewer
+    // counter updates).
+    const int64_t chunk = p.sched_chunk > 1 ? p.sched_chunk : 1;
+    int64_t it;
+    if (p.sched_mode == 0) {
+        const int G = gridDim.x, xcd = blockIdx.x % kXcds, loc = blockIdx.x / kXcds;
+        const int before = xcd * (G / kXcds) + min(xcd, G % kXcds);
+        it = ((int64_t)(before + loc) * wpw + wave_id()) * chunk;
+    } else {
+        unsigned long long t = 0;
+        if (lane_id() == 0) t = atomicAdd(p.next, (unsigned long long)chunk);
+        it = (int64_t)__shfl(t, 0, kWave);
+    }
+    while (it < p.n_sched) {
+        const int64_t end = min(it + chunk, p.n_sched);
+        for (int64_t i = it; i < end; ++i) {
+            const unsigned long long e = p.sched[i];
+            const int64_t r = (int64_t)(e >> 16);
+            const int m = (int)((e >> 8) & 255), n = (int)(e & 255);
+            if (m > 16) {
+                if (n > 16) sched_run<T, 2, 2>(p, r, m, n);
+                else sched_run<T, 2, 1>(p, r, m, n);
+            } else {
+                if (n > 16) sched_run<T, 1, 2>(p, r, m, n);
+                else sched_run<T, 1, 1>(p, r, m, n);
+            }
+        }
+        if (p.sched_mode == 0) {
+            it += waves * chunk;
+        } else {
+            unsigned long long t = 0;
+            if (lane_id() == 0) t = atomicAdd(p.next, (unsigned long long)chunk);
+            it = (int64_t)__shfl(t, 0, kWave);
+        }
+    }
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
 // Epilogue of split runs: C block of run r = beta C + alpha * (sum of its
 // segments' partial blocks in segment order); one thread per element.
+template <class T>
 __global__ __launch_bounds__(256) void k_smm_split_reduce(SmmArgs p) {
     const int64_t mn = (int64_t)p.m * p.n;
     const int64_t total = (p.run_end - p.run_begin) * mn;
+    const T *part = static_cast<const T *>(p.part);
+    T *C = static_cast<T *>(p.C);
+    const T alpha = (T)p.alpha, beta = (T)p.beta;
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
          t += (int64_t)gridDim.x * blockDim.x) {
         const int64_t rl = t / mn, e = t - rl * mn;
-        const double *w = p.part + rl * p.split * mn + e;
-        double v = w[0];
+        const T *w = part + rl * p.split * mn + e;
+        T v = w[0];
         for (int sg = 1; sg < p.split; ++sg) v += w[sg * mn];
-        double *dst = p.C + p.run_coff[p.run_begin + rl] + e;
-        const double prod = p.alpha * v;
-        *dst = (p.beta == 0.0) ? prod : fma(p.beta, *dst, prod);
+        T *dst = C + p.run_coff[p.run_begin + rl] + e;
+        const T prod = alpha * v;
+        *dst = (beta == T(0)) ? prod : fma(beta, *dst, prod);
     }
 }
 
 using SmmKernel = void (*)(SmmArgs);
 
-template <int MT> SmmKernel pick_mfma_nt(int nt) {
+template <class T, int MT> SmmKernel pick_mfma_nt(int nt) {
     switch (nt) {
-    case 1: return k_smm_mfma<MT, 1>;
-    case 2: return k_smm_mfma<MT, 2>;
-    case 3: return k_smm_mfma<MT, 3>;
-    case 4: return k_smm_mfma<MT, 4>;
+    case 1: return k_smm_mfma<T, MT, 1>;
+    case 2: return k_smm_mfma<T, MT, 2>;
+    case 3: return k_smm_mfma<T, MT, 3>;
+    case 4: return k_smm_mfma<T, MT, 4>;
     default: return nullptr;
     }
 }
 
 // MFMA kernels for C blocks up to 64 x 64 (MT, NT in 1..4).
-SmmKernel mfma_kernel_for(int mt, int nt) {
+template <class T> SmmKernel mfma_kernel_for(int mt, int nt) {
     switch (mt) {
-    case 1: return pick_mfma_nt<1>(nt);
-    case 2: return pick_mfma_nt<2>(nt);
-    case 3: return pick_mfma_nt<3>(nt);
-    case 4: return pick_mfma_nt<4>(nt);
+    case 1: return pick_mfma_nt<T, 1>(nt);
+    case 2: return pick_mfma_nt<T, 2>(nt);
+    case 3: return pick_mfma_nt<T, 3>(nt);
+    case 4: return pick_mfma_nt<T, 4>(nt);
     default: return nullptr;
     }
 }
 
 // Register-tile shapes with a compiled kernel: TM, TN in {1,2,3,4,5,6,8}.
-template <int TM> SmmKernel pick_tn(int tn) {
+template <class T, int TM> SmmKernel pick_tn(int tn) {
     switch (tn) {
-    case 1: return k_smm_valu<TM, 1>;
-    case 2: return k_smm_valu<TM, 2>;
-    case 3: return k_smm_valu<TM, 3>;
-    case 4: return k_smm_valu<TM, 4>;
-    case 5: return k_smm_valu<TM, 5>;
-    case 6: return k_smm_valu<TM, 6>;
-    case 8: return k_smm_valu<TM, 8>;
+    case 1: return k_smm_valu<T, TM, 1>;
+    case 2: return k_smm_valu<T, TM, 2>;
+    case 3: return k_smm_valu<T, TM, 3>;
+    case 4: return k_smm_valu<T, TM, 4>;
+    case 5: return k_smm_valu<T, TM, 5>;
+    case 6: return k_smm_valu<T, TM, 6>;
+    case 8: return k_smm_valu<T, TM, 8>;
     default: return nullptr;
     }
 }
 
-SmmKernel kernel_for(int tm, int tn) {
+template <class T> SmmKernel kernel_for(int tm, int tn) {
     switch (tm) {
-    case 1: return pick_tn<1>(tn);
-    case 2: return pick_tn<2>(tn);
-    case 3: return pick_tn<3>(tn);
-    case 4: return pick_tn<4>(tn);
-    case 5: return pick_tn<5>(tn);
-    case 6: return pick_tn<6>(tn);
-    case 8: return pick_tn<8>(tn);
+    case 1: return pick_tn<T, 1>(tn);
+    case 2: return pick_tn<T, 2>(tn);
+    case 3: return pick_tn<T, 3>(tn);
+    case 4: return pick_tn<T, 4>(tn);
+    case 5: return pick_tn<T, 5>(tn);
+    case 6: return pick_tn<T, 6>(tn);
+    case 8: return pick_tn<T, 8>(tn);
     default: return nullptr;
     }
+}
+
+bool is_sched_kernel(const void *fn) {
+    return fn == (const void *)k_smm_mfma_sched<double> || fn == (const void *)k_smm_mfma_sched<float>;
 }
 
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per workgroup
@@ -329,10 +412,13 @@ SmmParams plain_params(int m, int n) {
     return SmmParams{t, t, 0, 0};
 }
 
-int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
+int plan_smm(const SmmParams &prm, int m, int n, int kmax, int dtype, SmmLaunch *out) {
+    const bool f32 = dtype == BSMM_F32;
+    const size_t esize = f32 ? sizeof(float) : sizeof(double);
+    out->dtype = dtype;
     if (prm.tm == kMfmaTile && prm.tn == kMfmaTile) {
         const int mt = (int)ceil_div(m, 16), nt = (int)ceil_div(n, 16);
-        SmmKernel fn = mfma_kernel_for(mt, nt);
+        SmmKernel fn = f32 ? mfma_kernel_for<float>(mt, nt) : mfma_kernel_for<double>(mt, nt);
         if (!fn) {
             set_error(BSMM_ENOTSUP, "MFMA small-block kernel covers blocks up to 64 x 64, not %dx%d", m, n);
             return BSMM_ENOTSUP;
@@ -352,7 +438,7 @@ int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
         return BSMM_OK;
     }
     const int TM = prm.tm, TN = prm.tn;
-    SmmKernel fn = kernel_for(TM, TN);
+    SmmKernel fn = f32 ? kernel_for<float>(TM, TN) : kernel_for<double>(TM, TN);
     if (!fn) {
         set_error(BSMM_EINVAL, "no small-block kernel for register tile %dx%d", TM, TN);
         return BSMM_EINVAL;
@@ -370,8 +456,8 @@ int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
     // for the tail reads of the last register tile.
     const int n_pad = a.tiles_n * TN;
     const int waves_req = prm.waves > 0 ? std::min(prm.waves, 4) : 1;
-    const int max_group_doubles = kLdsBudget / 8 / a.G / waves_req;
-    int kc = (max_group_doubles - TM - 3) / (m + n_pad);
+    const int max_group_elems = (int)(kLdsBudget / esize / a.G / waves_req);
+    int kc = (max_group_elems - TM - 3) / (m + n_pad);
     kc = std::min(kc, std::max(1, kmax));
     if (prm.kc > 0) kc = std::min(kc, prm.kc);
     if (kc < 1) {
@@ -381,7 +467,7 @@ int plan_smm(const SmmParams &prm, int m, int n, int kmax, SmmLaunch *out) {
     a.kc_max = kc;
     a.region = (m + n_pad) * kc + TM + 2;
     a.region = (a.region + 1) & ~1;
-    const size_t wave_bytes = sizeof(double) * (size_t)a.G * a.region;
+    const size_t wave_bytes = esize * (size_t)a.G * a.region;
     int waves = prm.waves > 0 ? waves_req
                               : (int)std::max<int64_t>(1, std::min<int64_t>(4, kLdsBudget / wave_bytes));
     if (wave_bytes * waves > (size_t)kLdsBudget) {
@@ -407,7 +493,7 @@ unsigned smm_grid(const SmmLaunch &L, int64_t nruns) {
     return grid_of(waves_needed, L.waves, wg_cap);
 }
 
-int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const int64_t *run_coff,
+int launch_smm(SmmLaunch L, const void *A, const void *B, void *C, const int64_t *run_coff,
                const int64_t *run_ptr, const ulonglong2 *prods, int64_t rb, int64_t re,
                double alpha, double beta, hipStream_t s) {
     SmmArgs a = L.args;
@@ -421,6 +507,10 @@ int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const i
     a.run_end = re;
     a.alpha = alpha;
     a.beta = beta;
+    if (is_sched_kernel(L.fn) && a.sched_mode == 1) {
+        hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, a.next);
+        BSMM_TRY(launch_check("zero_u64"));
+    }
     {
         KernelTimer kt(1, s);
         hipLaunchKernelGGL((SmmKernel)L.fn, dim3(smm_grid(L, re - rb)), dim3(64 * L.waves), L.lds, s,
@@ -428,7 +518,10 @@ int launch_smm(SmmLaunch L, const double *A, const double *B, double *C, const i
     }
     BSMM_TRY(launch_check("smm_valu"));
     if (a.split <= 1) return BSMM_OK;
-    hipLaunchKernelGGL(k_smm_split_reduce, dim3(split_reduce_grid(a)), dim3(256), 0, s, a);
+    if (L.dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_smm_split_reduce<float>, dim3(split_reduce_grid(a)), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(k_smm_split_reduce<double>, dim3(split_reduce_grid(a)), dim3(256), 0, s, a);
     return launch_check("smm_split_reduce");
 }
 
@@ -472,20 +565,21 @@ static int representative_k(const bsmm_matrix_s *A) {
 // the one-wave-per-run MFMA kernel: enough (run, segment) items for about
 // 16 waves per CU when the runs alone are fewer, each segment at least 16
 // products long, at most 64 segments and 1 GiB of partial blocks.
-static int split_for(int64_t runs, int64_t prods, int m, int n) {
+static int split_for(int64_t runs, int64_t prods, int m, int n, size_t esize) {
     const int64_t target = (int64_t)cu_count() * 16;
     if (runs <= 0 || runs >= target) return 1;
     int64_t S = ceil_div(target, runs);
     S = std::min<int64_t>(S, prods / runs / 16);
     S = std::min<int64_t>(S, 64);
-    S = std::min<int64_t>(S, (int64_t(1) << 30) / (runs * (int64_t)m * n * (int64_t)sizeof(double)));
+    S = std::min<int64_t>(S, (int64_t(1) << 30) / (runs * (int64_t)m * n * (int64_t)esize));
     return (int)std::max<int64_t>(S, 1);
 }
 
-int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
-               const Stacks &st, double alpha, double beta, hipStream_t s, StackExec *ex) {
+int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, Stacks &st,
+               double alpha, double beta, hipStream_t s, StackExec *ex) {
     ex->launches.clear();
     ex->parts.clear();
+    st.n_sched = 0;
     if (st.n_runs == 0) return BSMM_OK;
     const int kmax = std::max(1, A->max_cbs);
     const int64_t chunk = options().stack_chunk;
@@ -506,18 +600,28 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         else class_run_lengths(st, &rlen);
     }
     LaunchList &launches = ex->launches;
+    // Tuned path with a tile size: the MFMA classes of blocks up to 32 x 32
+    // whose runs need no splitting go to one scheduled launch.
+    const bool sched_on = tuned && chunk <= 0 && options().stack_tile > 0 &&
+                          (int)st.class_prod_begin.size() == st.n_classes + 1;
+    std::vector<char> eligible(st.n_classes, 0);
     for (int cl = 0; cl < st.n_classes; ++cl) {
         const int64_t rb = st.class_begin[cl], re = st.class_begin[cl + 1];
         if (re <= rb) continue;
         const int m = st.row_sizes[cl / st.ncs], n = st.col_sizes[cl % st.ncs];
         SmmParams prm = tuned ? select_params(m, n, krep, rlen[cl]) : plain_params(m, n);
         SmmLaunch L;
-        BSMM_TRY(plan_smm(prm, m, n, kmax, &L));
+        BSMM_TRY(plan_smm(prm, m, n, kmax, C->dtype, &L));
         if (chunk <= 0 && prm.tm == kMfmaTile && (int)st.class_prod_begin.size() == st.n_classes + 1) {
-            const int S = split_for(re - rb, st.class_prod_begin[cl + 1] - st.class_prod_begin[cl], m, n);
+            const int S = split_for(re - rb, st.class_prod_begin[cl + 1] - st.class_prod_begin[cl], m, n,
+                                    C->esize());
+            if (sched_on && S == 1 && m <= 32 && n <= 32) {
+                eligible[cl] = 1;
+                continue;
+            }
             if (S > 1) {
                 DevBuf part;
-                BSMM_TRY(part.reserve(sizeof(double) * (size_t)(re - rb) * S * m * n, s));
+                BSMM_TRY(part.reserve(C->esize() * (size_t)(re - rb) * S * m * n, s));
                 L.args.split = S;
                 L.args.part = part.as<double>();
                 ex->parts.push_back(std::move(part));
@@ -535,6 +639,45 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
             launches.push_back({L, {b0, b1}});
             b0 = b1;
         }
+    }
+    int64_t sched_runs = 0, sched_prods = 0;
+    for (int cl = 0; cl < st.n_classes; ++cl)
+        if (eligible[cl]) {
+            sched_runs += st.class_begin[cl + 1] - st.class_begin[cl];
+            sched_prods += st.class_prod_begin[cl + 1] - st.class_prod_begin[cl];
+        }
+    if (sched_on && sched_runs > 0 && sched_runs < kSchedMinRuns) {
+        // Too few runs for the scheduling passes to pay off: those classes
+        // take their own launches after all.
+        for (int cl = 0; cl < st.n_classes; ++cl) {
+            if (!eligible[cl]) continue;
+            const int m = st.row_sizes[cl / st.ncs], n = st.col_sizes[cl % st.ncs];
+            SmmLaunch L;
+            BSMM_TRY(plan_smm(select_params(m, n, krep, rlen[cl]), m, n, kmax, C->dtype, &L));
+            launches.push_back({L, {st.class_begin[cl], st.class_begin[cl + 1]}});
+            eligible[cl] = 0;
+        }
+        sched_runs = 0;
+    }
+    if (sched_on && sched_runs > 0) {
+        BSMM_TRY(build_schedule(C, st, eligible, options().stack_tile, s));
+        SmmLaunch L;
+        L.fn = C->dtype == BSMM_F32 ? (void *)k_smm_mfma_sched<float> : (void *)k_smm_mfma_sched<double>;
+        L.dtype = C->dtype;
+        L.args.L = kWave;
+        L.args.G = 1;
+        L.args.passes = 1;
+        L.args.sched = st.sched.as<unsigned long long>();
+        L.args.n_sched = st.n_sched;
+        L.args.next = st.sched_next.as<unsigned long long>();
+        L.args.sched_mode = options().stack_sched;
+        // About 32 products per counter update: runs of one product go
+        // 16 at a time, runs of 32 or more one at a time.
+        const int64_t mean_len = std::max<int64_t>(1, sched_prods / sched_runs);
+        L.args.sched_chunk = (int)std::min<int64_t>(16, std::max<int64_t>(1, 32 / mean_len));
+        L.waves = 4;
+        L.lds = 0;
+        launches.push_back({L, {0, st.n_sched}});
     }
     // Instantiating a graph may allocate device memory: a multiply running
     // on a scratch arena launches its classes one by one instead.
@@ -588,7 +731,7 @@ int replay_stacks(const StackExec &ex, const bsmm_matrix_s *A, const bsmm_matrix
         return BSMM_OK;
     }
     for (auto &l : ex.launches)
-        BSMM_TRY(launch_smm(l.first, A->d_data(), B->d_data(), C->d_data(),
+        BSMM_TRY(launch_smm(l.first, A->d_raw(), B->d_raw(), C->d_raw(),
                             st.run_coff.as<int64_t>(), st.run_ptr.as<int64_t>(),
                             st.prods.as<ulonglong2>(), l.second.first, l.second.second, alpha, beta,
                             s));
@@ -607,9 +750,9 @@ int build_graph(const LaunchList &launches, const bsmm_matrix_s *A, const bsmm_m
     for (size_t i = 0; i < launches.size() && status == BSMM_OK; ++i) {
         const SmmLaunch &L = launches[i].first;
         SmmArgs a = L.args;
-        a.A = A->d_data();
-        a.B = B->d_data();
-        a.C = C->d_data();
+        a.A = A->d_raw();
+        a.B = B->d_raw();
+        a.C = C->d_raw();
         a.run_coff = st.run_coff.as<int64_t>();
         a.run_ptr = st.run_ptr.as<int64_t>();
         a.prods = st.prods.as<ulonglong2>();
@@ -625,14 +768,34 @@ int build_graph(const LaunchList &launches, const bsmm_matrix_s *A, const bsmm_m
         kp.sharedMemBytes = (unsigned)L.lds;
         kp.kernelParams = &argp;
         kp.extra = nullptr;
-        hipGraphNode_t node;
-        if (hipGraphAddKernelNode(&node, graph, nullptr, 0, &kp) != hipSuccess) {
+        hipGraphNode_t node, zero;
+        const bool counter = is_sched_kernel(L.fn) && a.sched_mode == 1;
+        void *zargp = &a.next;
+        if (counter) {
+            // The dynamic schedule's run counter starts at zero every replay
+            // (a kernel node: memset nodes are not used in the graph).
+            hipKernelNodeParams zp{};
+            zp.func = (void *)k_zero_u64;
+            zp.gridDim = dim3(1);
+            zp.blockDim = dim3(1);
+            zp.sharedMemBytes = 0;
+            zp.kernelParams = &zargp;
+            zp.extra = nullptr;
+            if (hipGraphAddKernelNode(&zero, graph, nullptr, 0, &zp) != hipSuccess) {
+                set_error(BSMM_EDEVICE, "hipGraphAddKernelNode failed");
+                status = BSMM_EDEVICE;
+                break;
+            }
+        }
+        if (hipGraphAddKernelNode(&node, graph, counter ? &zero : nullptr, counter ? 1 : 0, &kp) !=
+            hipSuccess) {
             set_error(BSMM_EDEVICE, "hipGraphAddKernelNode failed");
             status = BSMM_EDEVICE;
         } else if (a.split > 1) {
             // The class's split-run epilogue runs after its kernel.
             hipKernelNodeParams rp{};
-            rp.func = (void *)k_smm_split_reduce;
+            rp.func = L.dtype == BSMM_F32 ? (void *)k_smm_split_reduce<float>
+                                          : (void *)k_smm_split_reduce<double>;
             rp.gridDim = dim3(split_reduce_grid(a));
             rp.blockDim = dim3(256);
             rp.sharedMemBytes = 0;

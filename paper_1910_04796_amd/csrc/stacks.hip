@@ -241,7 +241,79 @@ __global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const i
     }
 }
 
+// Tile of C block (I, J): tiles of `tile` x `tile` blocks in row-major order.
+__device__ __forceinline__ int64_t tile_key(int32_t I, int32_t J, int tile, int64_t ntj) {
+    return (int64_t)(I / tile) * ntj + J / tile;
+}
+
+// Runs per tile (runs of eligible classes only).
+__global__ __launch_bounds__(256) void k_sched_hist(int64_t nruns, const int64_t *run_cblk,
+                                                    const int32_t *run_class, const char *elig,
+                                                    const int32_t *c_row, const int32_t *c_ci,
+                                                    int tile, int64_t ntj, int64_t *hist) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nruns;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        if (!elig[run_class[r]]) continue;
+        const int64_t c = run_cblk[r];
+        atomicAdd((unsigned long long *)&hist[tile_key(c_row[c], c_ci[c], tile, ntj)], 1ull);
+    }
+}
+
+// Every eligible run into its tile's range of the schedule (the order of
+// the runs inside a tile is not fixed; it does not change any result).
+__global__ __launch_bounds__(256) void k_sched_scatter(int64_t nruns, const int64_t *run_cblk,
+                                                       const int32_t *run_class, const char *elig,
+                                                       const int32_t *c_row, const int32_t *c_ci,
+                                                       const int32_t *rbs, const int32_t *cbs,
+                                                       int tile, int64_t ntj, int64_t *cursor,
+                                                       unsigned long long *sched) {
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < nruns;
+         r += (int64_t)gridDim.x * blockDim.x) {
+        if (!elig[run_class[r]]) continue;
+        const int64_t c = run_cblk[r];
+        const int32_t I = c_row[c], J = c_ci[c];
+        const int64_t pos =
+            (int64_t)atomicAdd((unsigned long long *)&cursor[tile_key(I, J, tile, ntj)], 1ull);
+        sched[pos] = ((unsigned long long)r << 16) | ((unsigned long long)rbs[I] << 8) |
+                     (unsigned long long)cbs[J];
+    }
+}
+
 }  // namespace
+
+int build_schedule(const bsmm_matrix_s *C, Stacks &st, const std::vector<char> &eligible, int tile,
+                   hipStream_t s) {
+    st.n_sched = 0;
+    for (int cl = 0; cl < st.n_classes; ++cl)
+        if (eligible[cl]) st.n_sched += st.class_begin[cl + 1] - st.class_begin[cl];
+    if (st.n_sched == 0) return BSMM_OK;
+    tile = std::max(tile, 1);
+    const int64_t nti = ceil_div(C->nbr, tile), ntj = ceil_div(C->nbc, tile);
+    const int64_t ntiles = nti * ntj;
+    DevBuf elig, hist, off;
+    BSMM_TRY(elig.reserve(eligible.size(), s));
+    BSMM_TRY(hist.reserve(sizeof(int64_t) * (ntiles + 1), s));
+    BSMM_TRY(off.reserve(sizeof(int64_t) * (ntiles + 1), s));
+    BSMM_TRY(st.sched.reserve(sizeof(unsigned long long) * st.n_sched, s));
+    BSMM_TRY(st.sched_next.reserve(sizeof(unsigned long long), s));
+    BSMM_HIP(hipMemcpyAsync(elig.p, eligible.data(), eligible.size(), hipMemcpyHostToDevice, s));
+    BSMM_TRY(fill_zero(hist.as<double>(), ntiles + 1, s));
+    const unsigned grid = grid_of(st.n_runs, 256, 8192);
+    hipLaunchKernelGGL(k_sched_hist, dim3(grid), dim3(256), 0, s, st.n_runs,
+                       (const int64_t *)st.run_cblk.as<int64_t>(),
+                       (const int32_t *)st.run_class.as<int32_t>(), (const char *)elig.as<char>(),
+                       (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(), tile, ntj,
+                       hist.as<int64_t>());
+    BSMM_TRY(launch_check("sched_hist"));
+    BSMM_TRY(scan_exclusive_i64(hist.as<int64_t>(), off.as<int64_t>(), ntiles, s));
+    hipLaunchKernelGGL(k_sched_scatter, dim3(grid), dim3(256), 0, s, st.n_runs,
+                       (const int64_t *)st.run_cblk.as<int64_t>(),
+                       (const int32_t *)st.run_class.as<int32_t>(), (const char *)elig.as<char>(),
+                       (const int32_t *)st.c_row.as<int32_t>(), C->d_col_ind(), C->d_rbs(),
+                       C->d_cbs(), tile, ntj, off.as<int64_t>(),
+                       st.sched.as<unsigned long long>());
+    return launch_check("sched_scatter");
+}
 
 // Distinct sizes of a size vector and the index of every entry.
 static void size_classes(const std::vector<int32_t> &sizes, std::vector<int32_t> &distinct,

@@ -70,3 +70,21 @@ def from_dense(D, rbs, cbs):
     data = [np.asarray(D[ro[i]:ro[i + 1], co[j]:co[j + 1]], np.float64).ravel(order="F")
             for i in range(len(rbs)) for j in range(len(cbs))]
     return BlockCSR(rbs, cbs, rp, ci, np.concatenate(data))
+
+
+def device_rows(M, r0, r1):
+    """Block rows [r0, r1) of a device matrix as a host block-CSR; the data
+    pass through a device buffer so that only those rows reach the host."""
+    import torch
+
+    from synth import BlockCSR, block_elems
+    b = lib()
+    nbr, nbc, nnzb, ne = M.info()
+    dev = torch.empty(max(ne, 1), dtype=torch.float64, device="cuda")
+    rp, ci, _ = b.bsmm_copy_out(M.handle, device_out=dev)
+    sizes = block_elems(M.rbs, M.cbs, rp, ci)
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    a0, a1 = int(rp[r0]), int(rp[r1])
+    data = dev[int(start[a0]):int(start[a1])].cpu().numpy()
+    return BlockCSR(np.asarray(M.rbs[r0:r1], np.int32), np.asarray(M.cbs, np.int32),
+                    rp[r0:r1 + 1] - rp[r0], ci[a0:a1].astype(np.int32), data)

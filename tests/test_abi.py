@@ -50,6 +50,22 @@ def test_create_rejects_malformed_input():
     assert _err(c, 2, [1, 1], 2, [1, 1], 3, [0, 1, 2], [0, 1], None) == b.BSMM_EINDEX
 
 
+def test_create_typed_rejects_unknown_type_and_malformed_input():
+    """The element-type check and the index checks of the typed create run
+    on the host, before any HIP call."""
+    import ctypes
+    from paper_1910_04796_amd import bsmm as b
+    rbs = np.array([1, 1], np.int32)
+    rp = np.array([0, 0, 0], np.int64)
+    h = ctypes.c_void_p()
+    st = b._lib.bsmm_create_matrix_typed(2, rbs.ctypes.data_as(b._i32p), 2, rbs.ctypes.data_as(b._i32p), 0,
+                                         rp.ctypes.data_as(b._i64p), None, 7, None, 0, None, ctypes.byref(h))
+    assert st == b.BSMM_EINVAL and "element type" in b.bsmm_last_error()
+    c = b.bsmm_create_matrix
+    assert _err(lambda: c(2, [1, 1], 2, [1, 1], 2, [0, 1, 2], [1, 5], None, dtype="f32")) == b.BSMM_EINDEX
+    assert _err(lambda: c(2, [0, 1], 2, [1, 1], 0, [0, 0, 0], [], None, dtype="f32")) == b.BSMM_EINVAL
+
+
 def test_multiply_rejects_null_handles():
     from paper_1910_04796_amd import bsmm as b
     assert _err(b.bsmm_multiply, 1.0, None, None, 0.0, None, 0.0, 0) == b.BSMM_EINVAL

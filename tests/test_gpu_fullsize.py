@@ -6,7 +6,7 @@ import pytest
 from oracle import oracle as orc
 from synth import banded_uneven, dense_rect, wide_range_dense, wide_range_sparse
 
-from tests.helpers import gpu_multiply, lib
+from tests.helpers import check_against_oracle, device_rows, gpu_multiply, lib, set_path
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-12
@@ -74,3 +74,29 @@ def test_sparse_wide_range_32752(path):
     X, st = gpu_multiply(1.0, A, B, 0.0, path=path, kernel="tuned")
     assert st["path"] == (1 if path == "stack" else 3)
     _check_rows(X, A, B, [3, 700, 1420])
+
+
+def test_banded_uneven_50000_30pct_tuned():
+    """The benchmark's headline workload at full size, in its launch
+    configuration (tuned stacks, scheduled MFMA kernel, filter 1e-10):
+    block rows at the edges, the middle and two seeded random rows checked
+    against the reference (only those rows reach the host)."""
+    b = lib()
+    A, B = banded_uneven(seed=0, occupancy=0.30, target=50000)
+    set_path("stack", "tuned")
+    try:
+        MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
+        MC = b.Matrix.empty(A.rbs, B.cbs)
+        b.multiply(1.0, MA, MB, 0.0, MC, 1e-10)
+        st = b.bsmm_last_stats()
+        assert st["path"] == 1 and st["n_classes"] == 16 and st["n_products"] > 9e8
+        nbr = len(A.rbs)
+        rng = np.random.default_rng(30)
+        rows = [0, nbr // 2, nbr - 1] + [int(x) for x in rng.integers(1, nbr - 1, 2)]
+        for r in rows:
+            R = orc.multiply(1.0, A, B, 0.0, filter_eps=1e-10, rows=(r, r + 1))
+            check_against_oracle(device_rows(MC, r, r + 1), R, TOL)
+        for M in (MA, MB, MC):
+            M.close()
+    finally:
+        set_path()
