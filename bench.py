@@ -14,7 +14,9 @@ Further legs (extra JSON fields, each with a warm-up and median/min over
 repeated multiplies): the dense N = 8192 product in 32-blocks (densified
 GEMM, blocked plain and tuned, INT8 split-precision emulation), the
 split-precision workload N = 16384 (native vs emulated), the banded product
-at 1 % and 10 %, and the 460 x 460 sparse case's latency.  The CPU
+at 1 % and 10 %, the 460 x 460 sparse case's latency, FP32 matrices (dense
+and banded), and the learned model deciding for block sizes absent from the
+tuning database.  The CPU
 reference is timed on a bounded sample of the headline workload and checks
 the GPU results on those rows.
 
@@ -116,12 +118,13 @@ def rows_slice(torch, M, r0, r1):
     from paper_1910_04796_amd import bsmm
     from synth import BlockCSR, block_elems
     nbr, nbc, nnzb, ne = M.info()
-    dev = torch.empty(max(ne, 1), dtype=torch.float64, device="cuda")
+    tdt = torch.float32 if getattr(M, "dtype", "f64") == "f32" else torch.float64
+    dev = torch.empty(max(ne, 1), dtype=tdt, device="cuda")
     rp, ci, _ = bsmm.bsmm_copy_out(M.handle, device_out=dev)
     sizes = block_elems(M.rbs, M.cbs, rp, ci)
     start = np.concatenate([[0], np.cumsum(sizes)])
     a0, a1 = int(rp[r0]), int(rp[r1])
-    data = dev[int(start[a0]):int(start[a1])].cpu().numpy()
+    data = dev[int(start[a0]):int(start[a1])].cpu().numpy().astype(np.float64)
     del dev
     return BlockCSR(M.rbs[r0:r1], M.cbs, rp[r0:r1 + 1] - rp[r0], ci[a0:a1].astype(np.int32), data)
 
@@ -367,6 +370,109 @@ def extras_banded(bsmm, torch, stream, args, orc, threads):
     return out
 
 
+PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 matrix and vector peak
+HELDOUT_DB = os.path.join(ROOT, "paper_1910_04796_amd", "tune_db", "gfx950_heldout_sizes.txt")
+
+
+def as_f32(M):
+    """The same matrix with its values rounded to FP32 (held as float64,
+    which represents them exactly): the reference's inputs for FP32 legs."""
+    from synth import BlockCSR
+    return BlockCSR(M.rbs, M.cbs, M.row_ptr, M.col_ind, np.asarray(M.data, np.float32).astype(np.float64))
+
+
+def extras_f32(bsmm, torch, stream, args, orc, threads):
+    """Single-precision matrices: the dense N = 8192 product in 32-blocks
+    (densified, FP32 MFMA GEMM) and the banded 10 % product (plain and
+    tuned stacks), checked against the FP64 reference of the FP32-rounded
+    inputs on sampled block rows (tolerance 1e-5)."""
+    from synth import banded_uneven, dense_square
+    out = {}
+    A, B = dense_square(seed=0, n=8192, bs=32)
+    A, B = as_f32(A), as_f32(B)
+    MA, MB = bsmm.Matrix.from_blocks(A, dtype="f32"), bsmm.Matrix.from_blocks(B, dtype="f32")
+    F = 2.0 * 8192 ** 3
+    set_opts(bsmm, path="dense")
+    MC = bsmm.Matrix.empty(A.rbs, B.cbs, dtype="f32")
+    bsmm.bsmm_set_option("time_kernels", "1")
+    bsmm.bsmm_kernel_times(reset=True)
+    t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MC, 0.0, stream), 2, args.reps * 2)
+    g_ms, g_n, _, _ = bsmm.bsmm_kernel_times(reset=True)
+    bsmm.bsmm_set_option("time_kernels", "0")
+    g = g_ms / max(g_n, 1)
+    r = dict(t, gflops=gflops(F, t["median_ms"]), gemm_kernel_ms=round(g, 4),
+             gemm_roofline={"kernel": "k_dgemm_mfma<float>", "achieved": round(F / (g * 1e-3) / 1e12, 3),
+                            "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(F / (g * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)})
+    if orc is not None:
+        r["rel_err_rows_0_127_255"] = sampled_err(orc, torch, MC, A, B, (0, 127, 255), threads)
+    out["dense_square_8192_b32_f32"] = r
+    log(f"f32 dense 8192: {t['median_ms']:.3f} ms (GEMM {g:.3f} ms)")
+    for M in (MA, MB, MC):
+        M.close()
+    del A, B
+    U, V = banded_uneven(seed=0, occupancy=0.10, target=50000)
+    U, V = as_f32(U), as_f32(V)
+    MU, MV = bsmm.Matrix.from_blocks(U, dtype="f32"), bsmm.Matrix.from_blocks(V, dtype="f32")
+    r = {}
+    for kern in ("plain", "tuned"):
+        set_opts(bsmm, path="stack", stack_kernel=kern)
+        MW = bsmm.Matrix.empty(U.rbs, V.cbs, dtype="f32")
+        t = timed_calls(torch, lambda: bsmm.multiply(1.0, MU, MV, 0.0, MW, HEADLINE_EPS, stream), 2, args.reps)
+        st = bsmm.bsmm_last_stats()
+        r[kern] = dict(t, gflops=gflops(st["flops"], t["median_ms"]))
+        if orc is not None:
+            nb = len(U.rbs)
+            r[kern]["rel_err_sampled_rows"] = sampled_err(orc, torch, MW, U, V, (3, nb // 2, nb - 4), threads,
+                                                          HEADLINE_EPS)
+        MW.close()
+    r["tuned_speedup"] = round(r["plain"]["median_ms"] / r["tuned"]["median_ms"], 3)
+    out["banded_uneven_10pct_f32"] = r
+    log(f"f32 banded 10 %: plain {r['plain']['median_ms']} ms, tuned {r['tuned']['median_ms']} ms")
+    MU.close()
+    MV.close()
+    set_opts(bsmm, path="auto", stack_kernel="plain")
+    return out
+
+
+def extras_learned(bsmm, torch, stream, args, orc, threads):
+    """The learned model deciding: the banded 10 % product with block sizes
+    {6, 14, 22, 30}, none of whose 64 shapes is in the shipped tuning
+    database, so the tuned path takes the model's pick for every class.
+    Timed against the plain rule and against the exhaustive choice of the
+    tuner for those shapes (a database made offline by the tuner)."""
+    from synth import banded_uneven
+    U, V = banded_uneven(seed=0, occupancy=0.10, target=50000, choices=(6, 14, 22, 30))
+    MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
+    db = bsmm.bsmm_get_option("tune_db")
+    r = {"block_sizes": [6, 14, 22, 30], "occupancy": 0.10}
+    legs = [("plain", "plain", db), ("learned", "tuned", db)]
+    if os.path.exists(HELDOUT_DB):
+        legs.append(("exhaustive", "tuned", HELDOUT_DB))
+    for name, kern, dbpath in legs:
+        set_opts(bsmm, path="stack", stack_kernel=kern, tune_db=dbpath)
+        MW = bsmm.Matrix.empty(U.rbs, V.cbs)
+        t = timed_calls(torch, lambda: bsmm.multiply(1.0, MU, MV, 0.0, MW, HEADLINE_EPS, stream), 2, args.reps)
+        st = bsmm.bsmm_last_stats()
+        r[name] = dict(t, gflops=gflops(st["flops"], t["median_ms"]))
+        if kern == "tuned":
+            r[name]["picks_k22_R8"] = {f"{m}x{n}": list(bsmm.bsmm_select_params(m, n, 22, 8))
+                                       for m in (6, 14, 22, 30) for n in (6, 14, 22, 30)}
+        if orc is not None and name == "learned":
+            nb = len(U.rbs)
+            r[name]["rel_err_sampled_rows"] = sampled_err(orc, torch, MW, U, V, (3, nb // 2, nb - 4), threads,
+                                                          HEADLINE_EPS)
+        MW.close()
+        log(f"learned-model leg {name}: {t['median_ms']:.3f} ms")
+    set_opts(bsmm, path="auto", stack_kernel="plain", tune_db=db)
+    r["learned_speedup_vs_plain"] = round(r["plain"]["median_ms"] / r["learned"]["median_ms"], 3)
+    if "exhaustive" in r:
+        r["exhaustive_over_learned_time"] = round(r["exhaustive"]["median_ms"] / r["learned"]["median_ms"], 4)
+    MU.close()
+    MV.close()
+    return r
+
+
 def extras_tiny(bsmm, torch, stream, args):
     """460 x 460 in 23-blocks, 10 %: latency of one multiply."""
     from synth import sparse_uniform
@@ -609,6 +715,8 @@ def main():
         extras["emulated_wide_dense_16384"] = extras_wide(bsmm, torch, stream, args, orc, threads)
         extras.update(extras_banded(bsmm, torch, stream, args, orc, threads))
         extras["sparse_460_b23_latency"] = extras_tiny(bsmm, torch, stream, args)
+        extras.update(extras_f32(bsmm, torch, stream, args, orc, threads))
+        extras["learned_banded_10pct_b6-14-22-30"] = extras_learned(bsmm, torch, stream, args, orc, threads)
     if args.all_configs:
         extras["all_configs"], keep = all_configs(bsmm, torch, stream, args)
         if orc is not None:

@@ -218,6 +218,15 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
                  in one launch, its runs ordered by tiles of T x T C blocks
                  (when those classes hold at least 4096 runs); "0" launches
                  every class on its own.  Results are the same bits.
+   "jit"         tuned path: "1" compiles, at run time (hiprtc), an FP64 or
+                 FP32 MFMA small-block kernel with m, n and k as compile-time
+                 constants for every class whose products share one depth
+                 k (A's block columns all of one size) and whose parameters
+                 select the MFMA kernel; compiled kernels are cached for the
+                 process; such classes are launched on their own (no
+                 hipGraph).  Without hiprtc, or when a compilation fails,
+                 the precompiled kernels run.  "0" (default): precompiled
+                 kernels only
    "stack_sched" order in which the scheduled launch's waves take runs:
                  "dynamic" (default; a run counter, several short runs per
                  update) or "static" (fixed strides, numbered XCD by XCD)
@@ -276,6 +285,8 @@ typedef struct bsmm_multiply_stats {
                               the other paths                               */
     int64_t n_sched_runs;  /* runs executed by the scheduled small-block
                               launch (tuned path, option "stack_tile")      */
+    int64_t n_jit_classes; /* shape classes run on run-time compiled
+                              kernels (tuned path, option "jit")            */
 } bsmm_multiply_stats;
 int bsmm_last_stats(bsmm_multiply_stats *out);
 
@@ -297,6 +308,13 @@ int bsmm_inspect_stacks(bsmm_matrix A, bsmm_matrix B, bsmm_matrix C,
                         int64_t *n_runs, int64_t *n_products,
                         int64_t *run_cblk, int32_t *run_class, int64_t *run_ptr,
                         int64_t *prod_ablk, int64_t *prod_bblk, void *stream);
+
+/*
+ * Run-time compiled kernels of option "jit", process-wide: kernels
+ * compiled, launches served from the cache, compilations that failed (or
+ * found no hiprtc), and the total compilation time.  Outputs may be NULL.
+ */
+int bsmm_jit_stats(int64_t *compiled, int64_t *cache_hits, int64_t *failures, double *compile_ms);
 
 /*
  * Device time of the recorded kernel launches (option "time_kernels"):

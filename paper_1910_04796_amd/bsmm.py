@@ -59,7 +59,7 @@ class bsmm_multiply_stats(ctypes.Structure):
                 ("n_products", ctypes.c_int64), ("n_runs", ctypes.c_int64),
                 ("c_nnzb_before", ctypes.c_int64), ("c_nnzb_after", ctypes.c_int64),
                 ("flops", ctypes.c_double), ("n_row_panels", ctypes.c_int64),
-                ("n_sched_runs", ctypes.c_int64)]
+                ("n_sched_runs", ctypes.c_int64), ("n_jit_classes", ctypes.c_int64)]
 
 
 _lib.bsmm_create_matrix.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _vp, ctypes.c_int,
@@ -81,6 +81,7 @@ _lib.bsmm_last_error.argtypes = []
 _lib.bsmm_last_stats.argtypes = [ctypes.POINTER(bsmm_multiply_stats)]
 _lib.bsmm_inspect_stacks.argtypes = [_vp, _vp, _vp, _i64p, _i64p, _i64p, _i32p, _i64p, _i64p, _i64p, _vp]
 _lib.bsmm_kernel_times.argtypes = [_f64p, _i64p, _f64p, _i64p, ctypes.c_int]
+_lib.bsmm_jit_stats.argtypes = [_i64p, _i64p, _i64p, _f64p]
 _lib.bsmm_tune_candidates.argtypes = [_i32, _i32, _i32, _i32p, _i32p]
 _lib.bsmm_tune_shape.argtypes = [_i32, _i32, _i32, _i64, _i32, _i32, _i32p, _i32, _f64p, _vp]
 _lib.bsmm_select_params.argtypes = [_i32, _i32, _i32, _i32, _i32p]
@@ -94,7 +95,7 @@ _lib.bsmm_mlp_adam_step.argtypes = [_i32, _f32p, _f32p, _f32p, _f32p, _i32, ctyp
 _lib.bsmm_mlp_train.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _i32, _i32, ctypes.c_float,
                                 ctypes.c_uint64, _f32p]
 for _f in ("bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
-           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix",
+           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_jit_stats", "bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix",
            "bsmm_matrix_info", "bsmm_copy_out", "bsmm_create_matrix_typed", "bsmm_matrix_dtype",
            "bsmm_copy_out_typed", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
            "bsmm_last_stats", "bsmm_inspect_stacks"):
@@ -103,7 +104,7 @@ for _f in ("bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsm
 EXPORTED = ("bsmm_create_matrix", "bsmm_create_matrix_typed", "bsmm_matrix_dtype", "bsmm_copy_out_typed",
             "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix", "bsmm_matrix_info",
             "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
-            "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times",
+            "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times", "bsmm_jit_stats",
             "bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params",
             "bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
             "bsmm_mlp_adam_step", "bsmm_mlp_train")
@@ -304,6 +305,14 @@ def bsmm_kernel_times(reset=True):
     _check(_lib.bsmm_kernel_times(ctypes.byref(gm), ctypes.byref(gn), ctypes.byref(sm),
                                   ctypes.byref(sn), 1 if reset else 0))
     return gm.value, gn.value, sm.value, sn.value
+
+
+def bsmm_jit_stats():
+    """(compiled, cache_hits, failures, compile_ms) of the run-time compiled
+    kernels (option jit)."""
+    c, h, f, ms = _i64(), _i64(), _i64(), ctypes.c_double()
+    _check(_lib.bsmm_jit_stats(ctypes.byref(c), ctypes.byref(h), ctypes.byref(f), ctypes.byref(ms)))
+    return c.value, h.value, f.value, ms.value
 
 
 def bsmm_tune_candidates(m, n, k):

@@ -59,6 +59,7 @@ struct Options {
     std::string tune_db;
     std::string mlp_weights;
     int forced[4] = {0, 0, 0, 0};  // "stack_params": tm tn kc waves for every class
+    int jit = 0;           // tuned path: run-time compiled kernels for classes of one product depth
     int stack_tile = 32;   // tuned path: > 0 runs MFMA classes in one launch, tiles of this many blocks
     int stack_sched = 1;   // scheduled kernel: 0 static XCD-aware striding, 1 dynamic run counter
 };
@@ -260,6 +261,7 @@ struct Stacks {
     DevBuf sched;                     // uint64[n_sched]: scheduled runs (run << 16 | m << 8 | n)
     int64_t n_sched = 0;
     DevBuf sched_next;                // uint64 run counter of the dynamic schedule
+    int n_jit = 0;                    // classes on run-time compiled kernels
     std::vector<char> class_active;   // class holds runs (any panel so far)
     std::vector<int> run_len_hint;    // mean run length per class over every panel (else empty)
 };
@@ -345,6 +347,7 @@ struct SmmLaunch {
     int waves = 1;
     size_t lds = 0;
     int dtype = BSMM_F64;   // element type the kernel was planned for
+    hipFunction_t jit_fn = nullptr;  // run-time compiled kernel (then fn is unused)
 };
 // dtype: BSMM_F64 or BSMM_F32 (the kernel and the LDS budget follow it).
 int plan_smm(const SmmParams &prm, int m, int n, int kmax, int dtype, SmmLaunch *out);
@@ -372,6 +375,18 @@ struct StackExec {
         else if (done) (void)hipEventDestroy(done);
     }
 };
+// Run-time specialised MFMA small-block kernel for products of one shape
+// (m, n, k), compiled with hiprtc on first use and cached per device;
+// nullptr when hiprtc or the compilation is unavailable.
+hipFunction_t jit_smm_kernel(int dtype, int m, int n, int k);
+int launch_jit_smm(hipFunction_t fn, unsigned grid, int waves, const void *A, const void *B, void *C,
+                   const int64_t *run_coff, const int64_t *run_ptr, const ulonglong2 *prods,
+                   int64_t rb, int64_t re, double alpha, double beta, hipStream_t s);
+struct JitStats {
+    int64_t compiled = 0, cache_hits = 0, failures = 0;
+    double compile_ms = 0.0;
+};
+JitStats jit_stats();
 SmmParams plain_params(int m, int n);
 // Selected parameters for shape (m, n, k) in runs of about run_len products
 // per C block: tuning database, then learned model, then the plain rule.

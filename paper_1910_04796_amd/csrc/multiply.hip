@@ -156,9 +156,9 @@ int active_classes(const Stacks &st) {
 // Options that change what a plan computes.
 std::string plan_key(const Options &o) {
     char buf[128];
-    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
+    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
              (long long)o.stack_chunk, (long long)o.stack_panel, o.emul_slices, o.forced[0],
-             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched);
+             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched, o.jit);
     return std::string(buf) + o.tune_db + "|" + o.mlp_weights;
 }
 
@@ -213,6 +213,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
     BSMM_TRY(stack_row_bounds(C, st, &pb, &cb, s));
     if (options().stack_kernel == 1) BSMM_TRY(stack_class_run_lengths(C, st, &st.run_len_hint, s));
     int64_t runs = 0, sched = 0;
+    int jit = 0;
     for (int32_t r0 = 0; r0 < C->nbr;) {
         int32_t r1 = r0 + 1;
         while (r1 < C->nbr && pb[r1 + 1] - pb[r0] <= cap) ++r1;
@@ -222,6 +223,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
             BSMM_TRY(run_stacks(A, B, C, st, alpha, beta, s, &ex));
             runs += st.n_runs;
             sched += st.n_sched;
+            jit = std::max(jit, st.n_jit);
             ++*n_panels;
             if (options().verbose) {
                 // Host progress of a long multiply (the panel is queued, not finished).
@@ -234,6 +236,7 @@ int stacks_by_panels(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doubl
     }
     st.n_runs = runs;
     st.n_sched = sched;
+    st.n_jit = jit;
     st.n_prod = pb[C->nbr];
     return BSMM_OK;
 }
@@ -288,6 +291,7 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         stt.flops = pl->tot.flops;
         stt.n_runs = pl->st.n_runs;
         stt.n_sched_runs = pl->st.n_sched;
+        stt.n_jit_classes = pl->st.n_jit;
         stt.n_classes = active_classes(pl->st);
     } else {
         free_plan(C->plan);
@@ -314,6 +318,7 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         stt.path = path;
         stt.n_runs = p->st.n_runs;
         stt.n_sched_runs = p->st.n_sched;
+        stt.n_jit_classes = p->st.n_jit;
         stt.n_classes = active_classes(p->st);
         // A multiply built in several row panels keeps no stacks to replay.
         if (o.plan_cache && stt.n_row_panels <= 1) {
@@ -370,6 +375,7 @@ int multiply_fixed_pattern(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, dou
     stt.flops = tot.flops;
     stt.n_runs = st.n_runs;
     stt.n_sched_runs = st.n_sched;
+    stt.n_jit_classes = st.n_jit;
     stt.n_classes = active_classes(st);
     return BSMM_OK;
 }

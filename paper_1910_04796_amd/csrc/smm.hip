@@ -507,6 +507,9 @@ int launch_smm(SmmLaunch L, const void *A, const void *B, void *C, const int64_t
     a.run_end = re;
     a.alpha = alpha;
     a.beta = beta;
+    if (L.jit_fn)
+        return launch_jit_smm(L.jit_fn, smm_grid(L, re - rb), L.waves, A, B, C, run_coff, run_ptr, prods,
+                              rb, re, alpha, beta, s);
     if (is_sched_kernel(L.fn) && a.sched_mode == 1) {
         hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, a.next);
         BSMM_TRY(launch_check("zero_u64"));
@@ -580,11 +583,17 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
     ex->launches.clear();
     ex->parts.clear();
     st.n_sched = 0;
+    st.n_jit = 0;
     if (st.n_runs == 0) return BSMM_OK;
     const int kmax = std::max(1, A->max_cbs);
     const int64_t chunk = options().stack_chunk;
     const bool tuned = options().stack_kernel == 1;
     const int krep = representative_k(A);
+    // Every product has the same depth when A's block columns share one size.
+    const int uniform_k = !A->cbs.empty() &&
+                                  *std::min_element(A->cbs.begin(), A->cbs.end()) == A->max_cbs
+                              ? A->max_cbs
+                              : 0;
     std::vector<int64_t> run_ptr_h;
     if (chunk > 0) {
         run_ptr_h.resize(st.n_runs + 1);
@@ -615,6 +624,15 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         if (chunk <= 0 && prm.tm == kMfmaTile && (int)st.class_prod_begin.size() == st.n_classes + 1) {
             const int S = split_for(re - rb, st.class_prod_begin[cl + 1] - st.class_prod_begin[cl], m, n,
                                     C->esize());
+            if (tuned && options().jit && S == 1 && uniform_k > 0) {
+                // One product depth: a kernel compiled for this (m, n, k).
+                if (hipFunction_t f = jit_smm_kernel(C->dtype, m, n, uniform_k)) {
+                    L.jit_fn = f;
+                    launches.push_back({L, {rb, re}});
+                    ++st.n_jit;
+                    continue;
+                }
+            }
             if (sched_on && S == 1 && m <= 32 && n <= 32) {
                 eligible[cl] = 1;
                 continue;
@@ -680,8 +698,10 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         launches.push_back({L, {0, st.n_sched}});
     }
     // Instantiating a graph may allocate device memory: a multiply running
-    // on a scratch arena launches its classes one by one instead.
-    if (tuned && chunk <= 0 && launches.size() > 1 && !scratch_arena()) {
+    // on a scratch arena launches its classes one by one instead, and so
+    // does one with run-time compiled kernels (module functions, which a
+    // graph kernel node does not take).
+    if (tuned && chunk <= 0 && launches.size() > 1 && !scratch_arena() && st.n_jit == 0) {
         BSMM_TRY(build_graph(launches, A, B, C, st, alpha, beta, &ex->exec));
         BSMM_HIP(hipEventCreateWithFlags(&ex->done, hipEventDisableTiming));
     }

@@ -80,11 +80,12 @@ def device_rows(M, r0, r1):
     from synth import BlockCSR, block_elems
     b = lib()
     nbr, nbc, nnzb, ne = M.info()
-    dev = torch.empty(max(ne, 1), dtype=torch.float64, device="cuda")
+    tdt = torch.float32 if getattr(M, "dtype", "f64") == "f32" else torch.float64
+    dev = torch.empty(max(ne, 1), dtype=tdt, device="cuda")
     rp, ci, _ = b.bsmm_copy_out(M.handle, device_out=dev)
     sizes = block_elems(M.rbs, M.cbs, rp, ci)
     start = np.concatenate([[0], np.cumsum(sizes)])
     a0, a1 = int(rp[r0]), int(rp[r1])
-    data = dev[int(start[a0]):int(start[a1])].cpu().numpy()
+    data = dev[int(start[a0]):int(start[a1])].cpu().numpy().astype(np.float64)
     return BlockCSR(np.asarray(M.rbs[r0:r1], np.int32), np.asarray(M.cbs, np.int32),
                     rp[r0:r1 + 1] - rp[r0], ci[a0:a1].astype(np.int32), data)
