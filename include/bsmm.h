@@ -317,6 +317,23 @@ int bsmm_inspect_stacks(bsmm_matrix A, bsmm_matrix B, bsmm_matrix C,
 int bsmm_jit_stats(int64_t *compiled, int64_t *cache_hits, int64_t *failures, double *compile_ms);
 
 /*
+ * Measured rates of the current device, for the rooflines (each output may
+ * be NULL to skip that measurement): fp64_mfma, fp32_mfma (TFLOP/s),
+ * int8_mfma (TOP/s) and bf16_mfma (TFLOP/s) from long loops of independent
+ * v_mfma_f64_16x16x4, v_mfma_f32_16x16x4, v_mfma_i32_32x32x32_i8 and
+ * v_mfma_f32_32x32x16_bf16 on register operands at 32 waves per CU;
+ * fp64_valu (TFLOP/s) from independent v_fma_f64 chains;
+ * hbm_gbs (GB/s, bytes read + written) from a 16-byte-vector copy between
+ * two device buffers of copy_bytes each (taken from the registered
+ * allocator), hbm_read_gbs (GB/s) from reading one of them.  Each figure
+ * is one timed launch after an untimed one.
+ * Errors: EINVAL (copy_bytes outside [0, 64 GiB]), ENOMEM, EDEVICE.
+ */
+int bsmm_measure_peaks(double *fp64_mfma, double *fp32_mfma, double *int8_mfma, double *bf16_mfma,
+                       double *fp64_valu, double *hbm_gbs, double *hbm_read_gbs, int64_t copy_bytes,
+                       void *stream);
+
+/*
  * Device time of the recorded kernel launches (option "time_kernels"):
  * total milliseconds and launch counts of the dense GEMM and of the
  * small-block stack kernels.  Waits for the recorded events.  reset != 0

@@ -82,6 +82,7 @@ _lib.bsmm_last_stats.argtypes = [ctypes.POINTER(bsmm_multiply_stats)]
 _lib.bsmm_inspect_stacks.argtypes = [_vp, _vp, _vp, _i64p, _i64p, _i64p, _i32p, _i64p, _i64p, _i64p, _vp]
 _lib.bsmm_kernel_times.argtypes = [_f64p, _i64p, _f64p, _i64p, ctypes.c_int]
 _lib.bsmm_jit_stats.argtypes = [_i64p, _i64p, _i64p, _f64p]
+_lib.bsmm_measure_peaks.argtypes = [_f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _f64p, _i64, _vp]
 _lib.bsmm_tune_candidates.argtypes = [_i32, _i32, _i32, _i32p, _i32p]
 _lib.bsmm_tune_shape.argtypes = [_i32, _i32, _i32, _i64, _i32, _i32, _i32p, _i32, _f64p, _vp]
 _lib.bsmm_select_params.argtypes = [_i32, _i32, _i32, _i32, _i32p]
@@ -95,7 +96,7 @@ _lib.bsmm_mlp_adam_step.argtypes = [_i32, _f32p, _f32p, _f32p, _f32p, _i32, ctyp
 _lib.bsmm_mlp_train.argtypes = [_i32, _f32p, _i64, _f32p, _f32p, _i32, _i32, ctypes.c_float,
                                 ctypes.c_uint64, _f32p]
 for _f in ("bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
-           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_jit_stats", "bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix",
+           "bsmm_mlp_adam_step", "bsmm_mlp_train","bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params", "bsmm_kernel_times", "bsmm_jit_stats", "bsmm_measure_peaks", "bsmm_create_matrix", "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix",
            "bsmm_matrix_info", "bsmm_copy_out", "bsmm_create_matrix_typed", "bsmm_matrix_dtype",
            "bsmm_copy_out_typed", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
            "bsmm_last_stats", "bsmm_inspect_stacks"):
@@ -105,6 +106,7 @@ EXPORTED = ("bsmm_create_matrix", "bsmm_create_matrix_typed", "bsmm_matrix_dtype
             "bsmm_multiply", "bsmm_multiply_noalloc", "bsmm_destroy_matrix", "bsmm_matrix_info",
             "bsmm_copy_out", "bsmm_set_allocator", "bsmm_set_option", "bsmm_get_option",
             "bsmm_last_error", "bsmm_last_stats", "bsmm_inspect_stacks", "bsmm_kernel_times", "bsmm_jit_stats",
+            "bsmm_measure_peaks",
             "bsmm_tune_candidates", "bsmm_tune_shape", "bsmm_select_params",
             "bsmm_mlp_param_count", "bsmm_mlp_features", "bsmm_mlp_forward", "bsmm_mlp_grad",
             "bsmm_mlp_adam_step", "bsmm_mlp_train")
@@ -313,6 +315,16 @@ def bsmm_jit_stats():
     c, h, f, ms = _i64(), _i64(), _i64(), ctypes.c_double()
     _check(_lib.bsmm_jit_stats(ctypes.byref(c), ctypes.byref(h), ctypes.byref(f), ctypes.byref(ms)))
     return c.value, h.value, f.value, ms.value
+
+
+def bsmm_measure_peaks(copy_bytes=1 << 31, stream=None):
+    """Measured device rates: dict of fp64_mfma, fp32_mfma (TFLOP/s),
+    int8_mfma (TOP/s), bf16_mfma, fp64_valu (TFLOP/s), hbm_gbs (copy, read +
+    write) and hbm_read_gbs (GB/s)."""
+    v = [ctypes.c_double() for _ in range(7)]
+    _check(_lib.bsmm_measure_peaks(*[ctypes.byref(x) for x in v], int(copy_bytes), _stream(stream)))
+    return dict(zip(("fp64_mfma", "fp32_mfma", "int8_mfma", "bf16_mfma", "fp64_valu", "hbm_gbs",
+                     "hbm_read_gbs"), (x.value for x in v)))
 
 
 def bsmm_tune_candidates(m, n, k):

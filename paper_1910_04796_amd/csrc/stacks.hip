@@ -200,10 +200,13 @@ __global__ void k_gather_class_begin(const int64_t *hoff, const int64_t *hoff_p,
 }
 
 // Products of one C block row, K ascending inside every run.  Within one K
-// every C slot is hit at most once, so the per-slot cursors need no atomics;
-// a barrier separates consecutive K.
+// every C slot is hit at most once, so the per-slot write positions need no
+// atomics; a barrier separates consecutive K.  When the row has at most
+// `cap` slots, each slot's next position in the stacks is kept in LDS as a
+// 64-bit index, so a product costs no global gather; longer rows keep a
+// 32-bit count per slot and gather the run's first position per product.
 __global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const int64_t *poff,
-                                                    int32_t nbc, const int64_t *a_rp,
+                                                    int32_t nbc, int32_t cap, const int64_t *a_rp,
                                                     const int32_t *a_ci, const int64_t *a_off,
                                                     const int64_t *b_rp, const int32_t *b_ci,
                                                     const int64_t *b_off, const int32_t *kbs,
@@ -212,16 +215,25 @@ __global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const i
                                                     ulonglong2 *prods) {
     extern __shared__ int32_t lds[];
     int32_t *map = lds;
-    int32_t *cur = lds + nbc;
+    const int32_t nbc_pad = (nbc + 1) & ~1;
+    int64_t *next = reinterpret_cast<int64_t *>(lds + nbc_pad);  // rows of at most cap slots
+    int32_t *cur = lds + nbc_pad;                                // longer rows
     const int32_t row = row0 + (int32_t)blockIdx.x;
     const int part = blockIdx.y;
     const int64_t p0 = c_rp[row];
     const int32_t len = (int32_t)(c_rp[row + 1] - p0);
+    const bool in_lds = len <= cap;
     for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
     __syncthreads();
     for (int s = threadIdx.x; s < len; s += blockDim.x) {
         map[c_ci[p0 + s]] = s;
-        cur[s] = P == 1 ? 0 : (int32_t)poff[(p0 + s) * P + part];
+        const int64_t first = P == 1 ? 0 : poff[(p0 + s) * P + part];
+        if (in_lds) {
+            const int64_t r = run_of_c[p0 + s];
+            next[s] = r >= 0 ? run_ptr[r] + first : 0;  // r < 0: the slot receives no product
+        } else {
+            cur[s] = (int32_t)first;
+        }
     }
     __syncthreads();
     int64_t pa0, pa1;
@@ -232,9 +244,14 @@ __global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const i
         for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
             const int32_t s = map[b_ci[q]];
             if (s < 0) continue;
-            const int64_t r = run_of_c[p0 + s];
-            const int64_t pos = run_ptr[r] + cur[s];
-            cur[s] += 1;
+            int64_t pos;
+            if (in_lds) {
+                pos = next[s];
+                next[s] = pos + 1;
+            } else {
+                pos = run_ptr[run_of_c[p0 + s]] + cur[s];
+                cur[s] += 1;
+            }
             prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
         }
         __syncthreads();
@@ -516,9 +533,13 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     BSMM_TRY(scan_exclusive_i64(run_cnt.as<int64_t>(), st.run_ptr.as<int64_t>(), st.n_runs, s));
     if (nprod > 0) {
         BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
-        const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
-        hipLaunchKernelGGL(k_stack_fill, dim3(r1 - r0, st.kparts), dim3(256), map_lds, s, r0,
-                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), nbc,
+        // LDS: the column map, then per slot a 64-bit next position (rows of
+        // at most cap slots) or a 32-bit count; at most 64 KB.
+        const int64_t nbc_pad = (nbc + 1) & ~1;
+        const int32_t cap = (int32_t)std::min<int64_t>(nbc, (65536 - 4 * nbc_pad) / 8);
+        const size_t fill_lds = 4 * nbc_pad + std::max<int64_t>(4 * (int64_t)nbc, 8 * (int64_t)cap);
+        hipLaunchKernelGGL(k_stack_fill, dim3(r1 - r0, st.kparts), dim3(256), fill_lds, s, r0,
+                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), nbc, cap,
                            A->d_row_ptr(), A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(),
                            B->d_col_ind(), B->d_blk_off(), B->d_rbs(), C->d_row_ptr(),
                            C->d_col_ind(), (const int64_t *)st.run_of_c.as<int64_t>(),
