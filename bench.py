@@ -258,7 +258,8 @@ def cpu_baseline(orc, torch, res, threads_all):
 
 def extras_dense(bsmm, torch, stream, args):
     """Dense N = 8192 in 32-blocks: densified GEMM (with the GEMM kernel's
-    own roofline), blocked plain and tuned stacks, INT8 emulation."""
+    own roofline), blocked plain and tuned stacks (also with the run-time
+    compiled kernel of the one 32 x 32 x 32 class), INT8 emulation."""
     from synth import dense_square
     N, BS = 8192, 32
     A, B = dense_square(seed=0, n=N, bs=BS)
@@ -282,7 +283,7 @@ def extras_dense(bsmm, torch, stream, args):
             r["stack_kernel_ms"] = round(s_ms / s_n, 4)
         out[name] = r
         log(f"dense 8192 {name}: {t['median_ms']:.3f} ms")
-        set_opts(bsmm, path="auto", stack_kernel="plain", dense_kb=16)
+        set_opts(bsmm, path="auto", stack_kernel="plain", dense_kb=16, jit=0)
         return MC
 
     keep["densified"] = leg("densified", args.reps * 2, path="dense")
@@ -297,6 +298,9 @@ def extras_dense(bsmm, torch, stream, args):
         leg(f"blocked_{kern}", args.reps, path="stack", stack_kernel=kern).close()
         out[f"blocked_{kern}"]["t_blocked_over_t_densified"] = round(
             out[f"blocked_{kern}"]["median_ms"] / out["densified"]["median_ms"], 3)
+    leg("blocked_tuned_jit", args.reps, path="stack", stack_kernel="tuned", jit=1).close()
+    out["blocked_tuned_jit"]["t_blocked_over_t_densified"] = round(
+        out["blocked_tuned_jit"]["median_ms"] / out["densified"]["median_ms"], 3)
     keep["emulated_int8_s7"] = leg("emulated_int8_s7", args.reps, path="emul", emul_slices=7)
     e = out["emulated_int8_s7"]
     e["speedup_vs_densified_fp64"] = round(out["densified"]["median_ms"] / e["median_ms"], 3)

@@ -23,7 +23,10 @@ typedef float v16f __attribute__((ext_vector_type(16)));
 
 constexpr int kChains = 16;  // independent accumulators per wave (FP64 / FP32 MFMA)
 
-__global__ __launch_bounds__(256) void k_peak_f64_mfma(int iters, double seed, double *out) {
+// At least two workgroups per CU: with one, the compiler keeps the loop's
+// accumulators in VGPRs but runs the MFMAs on AGPR copies, moving all of
+// them back and forth every iteration (about half the rate).
+__global__ __launch_bounds__(256, 2) void k_peak_f64_mfma(int iters, double seed, double *out) {
     v4d_t acc[kChains];
 #pragma unroll
     for (int c = 0; c < kChains; ++c) acc[c] = (v4d_t){0.0, 0.0, 0.0, 0.0};
