@@ -106,7 +106,7 @@ __device__ __forceinline__ acc_t mfma(T a, T b, acc_t c) {
 }
 // Result element e of lane l: FP64 row 4 e + l / 16, FP32 row 4 (l / 16) + e.
 __device__ __forceinline__ int out_row(int e, int lk) { return @F64@ ? 4 * e + lk : 4 * lk + e; }
-extern "C" __global__ __launch_bounds__(256) void bsmm_jit_smm(JitArgs p) {
+extern "C" __global__ __launch_bounds__(256, 4) void bsmm_jit_smm(JitArgs p) {
     const int lane = threadIdx.x & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const long long waves = (long long)gridDim.x * (blockDim.x / 64);
@@ -117,10 +117,16 @@ extern "C" __global__ __launch_bounds__(256) void bsmm_jit_smm(JitArgs p) {
         for (int i = 0; i < MT; ++i)
 #pragma unroll
             for (int j = 0; j < NT; ++j) acc[i][j] = (acc_t){0, 0, 0, 0};
-        const long long q1 = p.run_ptr[r + 1];
-        for (long long q = p.run_ptr[r]; q < q1; ++q) {
-            const T *a = p.A + (long long)(p.prods[2 * q] & ((1ull << 48) - 1));
-            const T *b = p.B + (long long)p.prods[2 * q + 1];
+        const long long q0 = p.run_ptr[r], q1 = p.run_ptr[r + 1];
+        // The next product's descriptor is loaded one product ahead.
+        unsigned long long na = q0 < q1 ? p.prods[2 * q0] : 0ull, nb = q0 < q1 ? p.prods[2 * q0 + 1] : 0ull;
+        for (long long q = q0; q < q1; ++q) {
+            const T *a = p.A + (long long)(na & ((1ull << 48) - 1));
+            const T *b = p.B + (long long)nb;
+            if (q + 1 < q1) {
+                na = p.prods[2 * q + 2];
+                nb = p.prods[2 * q + 3];
+            }
 #pragma unroll
             for (int c = 0; c < KC; ++c) {
                 T af[4][MT], bf[4][NT];
