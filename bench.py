@@ -635,6 +635,19 @@ def paper_workloads(bsmm, torch, stream, names, threads):
     return out
 
 
+EXTRA_LEGS = ("dense", "wide", "banded", "tiny", "f32", "learned", "all_configs")
+
+
+def add_all_configs_errors(orc, out, keep, threads):
+    """Reference check of the all-configs results on their sampled block rows."""
+    for name, (X, Aref, Bref, eps, rows) in keep.items():
+        e = sampled_err_host(orc, X, Aref, Bref, rows, threads, eps)
+        d = out["dense_rect_4096x4096x65536"] if name == "rect" else \
+            out["sparse_wide_range_32752_b23"][name[len("sparse_"):]]
+        d["rel_err_sampled_rows"] = e
+        d["sampled_block_rows"] = list(rows)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -648,6 +661,9 @@ def main():
                     help="also run the rectangular dense and sparse split-precision workloads")
     ap.add_argument("--paper-workloads", default="",
                     help="only run the paper's products: comma list of " + ", ".join(PAPER_SHAPES))
+    ap.add_argument("--extras-only", default="",
+                    help="only run these extra legs, no headline (for profiling): comma list of "
+                         + ", ".join(EXTRA_LEGS))
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -684,6 +700,36 @@ def main():
         res = paper_workloads(bsmm, torch, stream, names, threads)
         print(json.dumps({"paper_workloads": res, "dtype": "f64", "data": "synthetic", "n_gpus": 1}),
               flush=True)
+        bsmm.bsmm_set_allocator()
+        return
+
+    if args.extras_only:
+        names = [x for x in args.extras_only.split(",") if x]
+        bad = [x for x in names if x not in EXTRA_LEGS]
+        if bad:
+            sys.exit(f"bench.py: unknown extra leg(s) {bad}")
+        extras = {}
+        for name in names:
+            if name == "dense":
+                extras["dense_square_8192_b32"], keep, _, _ = extras_dense(bsmm, torch, stream, args)
+                for M in keep.values():
+                    M.close()
+            elif name == "wide":
+                extras["emulated_wide_dense_16384"] = extras_wide(bsmm, torch, stream, args, None, threads)
+            elif name == "banded":
+                extras.update(extras_banded(bsmm, torch, stream, args, None, threads))
+            elif name == "tiny":
+                extras["sparse_460_b23_latency"] = extras_tiny(bsmm, torch, stream, args)
+            elif name == "f32":
+                extras.update(extras_f32(bsmm, torch, stream, args, None, threads))
+            elif name == "learned":
+                extras["learned_banded_10pct_b6-14-22-30"] = extras_learned(bsmm, torch, stream, args, None,
+                                                                            threads)
+            elif name == "all_configs":
+                from oracle import oracle as orc
+                extras["all_configs"], keep = all_configs(bsmm, torch, stream, args)
+                add_all_configs_errors(orc, extras["all_configs"], keep, threads)
+        print(json.dumps({"extras": extras, "dtype": "f64", "data": "synthetic", "n_gpus": 1}), flush=True)
         bsmm.bsmm_set_allocator()
         return
 
@@ -742,15 +788,7 @@ def main():
     if args.all_configs:
         extras["all_configs"], keep = all_configs(bsmm, torch, stream, args)
         if orc is not None:
-            for name, (X, Aref, Bref, eps, rows) in keep.items():
-                e = sampled_err_host(orc, X, Aref, Bref, rows, threads, eps)
-                d = extras["all_configs"]
-                if name == "rect":
-                    d = d["dense_rect_4096x4096x65536"]
-                else:
-                    d = d["sparse_wide_range_32752_b23"][name[len("sparse_"):]]
-                d["rel_err_sampled_rows"] = e
-                d["sampled_block_rows"] = list(rows)
+            add_all_configs_errors(orc, extras["all_configs"], keep, threads)
 
     ms = tuned["ms_per_step"]
     out = {
