@@ -557,7 +557,7 @@ PAPER_SHAPES = {"square_63360": (63360, 63360, 63360),
 BLOCKED_MAX_PRODUCTS = 3e10
 
 
-def paper_workloads(bsmm, torch, stream, names, threads):
+def paper_workloads(bsmm, torch, stream, names, threads, blocks=None):
     """The paper's own benchmark products (Sec. IV) on one GPU: square
     M = N = K = 63,360 and tall-and-skinny M = N = 1,408, K = 1,982,464, in
     square blocks of 22 or 64, every block present, values U[-1, 1].  Each
@@ -585,6 +585,8 @@ def paper_workloads(bsmm, torch, stream, names, threads):
         # The paper's square product also in blocks of 4 (its comparison with
         # a dense library); blocked mode there is far beyond the stack cap.
         sizes = (64, 22, 4) if name == "square_63360" else (64, 22)
+        if blocks:
+            sizes = tuple(b for b in sizes if b in blocks)
         for bs in sizes:
             ms_, ns_, ks_ = (np.full(x // bs, bs, np.int32) for x in (M, Nn, K))
             A = BlockCSR(ms_, ks_, *pattern_full(len(ms_), len(ks_)), a_vals)
@@ -627,8 +629,10 @@ def paper_workloads(bsmm, torch, stream, names, threads):
             MA.close()
             MB.close()
             del A, B
-        res["densified_b22_over_b64"] = round(res["b22"]["densified"]["ms"] / res["b64"]["densified"]["ms"], 4)
-        if "b4" in res:
+        if "b22" in res and "b64" in res:
+            res["densified_b22_over_b64"] = round(res["b22"]["densified"]["ms"] / res["b64"]["densified"]["ms"],
+                                                  4)
+        if "b4" in res and "b64" in res:
             res["densified_b4_over_b64"] = round(res["b4"]["densified"]["ms"] / res["b64"]["densified"]["ms"], 4)
         out[name] = res
         del a_vals, b_vals
@@ -661,6 +665,8 @@ def main():
                     help="also run the rectangular dense and sparse split-precision workloads")
     ap.add_argument("--paper-workloads", default="",
                     help="only run the paper's products: comma list of " + ", ".join(PAPER_SHAPES))
+    ap.add_argument("--paper-blocks", default="",
+                    help="with --paper-workloads: only these block sizes (comma list of 64, 22, 4)")
     ap.add_argument("--extras-only", default="",
                     help="only run these extra legs, no headline (for profiling): comma list of "
                          + ", ".join(EXTRA_LEGS))
@@ -697,7 +703,8 @@ def main():
         bad = [x for x in names if x not in PAPER_SHAPES]
         if bad:
             sys.exit(f"bench.py: unknown paper workload(s) {bad}")
-        res = paper_workloads(bsmm, torch, stream, names, threads)
+        blocks = tuple(int(x) for x in args.paper_blocks.split(",") if x) or None
+        res = paper_workloads(bsmm, torch, stream, names, threads, blocks)
         print(json.dumps({"paper_workloads": res, "dtype": "f64", "data": "synthetic", "n_gpus": 1}),
               flush=True)
         bsmm.bsmm_set_allocator()

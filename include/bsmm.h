@@ -410,7 +410,8 @@ int bsmm_select_params(int32_t m, int32_t n, int32_t k, int32_t run_len, int32_t
  * The tuned path loads a model from the file named by option "mlp_weights"
  * (text: "bsmm-mlp features F mean ... std ... params COUNT ...") and, for a
  * shape missing from the tuning database, takes the candidate with the
- * lowest prediction.  Errors: EINVAL on bad arguments, ENOMEM, EDEVICE.
+ * lowest prediction.  Errors: EINVAL on bad arguments, ERANGE for more
+ * than 4 (2^22 - 1) samples (forward, grad, train), ENOMEM, EDEVICE.
  */
 int bsmm_mlp_param_count(int32_t n_features, int64_t *count);
 int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, int32_t run_len, const int32_t *params4,

@@ -46,32 +46,33 @@ __global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const 
                                                const int64_t *col_off, const int64_t *rp,
                                                const int32_t *ci, const int64_t *blk_off,
                                                const T *data, T *panel, int64_t ld) {
-    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (p >= nnzb) return;
-    int32_t lo = 0, hi = nbr;  // row = last lo with rp[lo] <= p
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (rp[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    const int32_t row = lo;
-    const int m = rbs[row];
-    const int64_t r0 = row_off[row];
-    const int32_t j = ci[p];
-    const int n = cbs[j];
-    const int64_t c0 = col_off[j];
-    const T *src = data + blk_off[p];
-    const int64_t len = (int64_t)m * n;
-    if (len < (1 << 20) && m < 4096) {
-        const float rcp = 1.0f / (float)m;
-        for (int e = lane_id(); e < len; e += kWave) {
-            int ii;
-            const int jj = divmod_small(e, m, rcp, &ii);
-            panel[(c0 + jj) * ld + r0 + ii] = src[e];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); p < nnzb; p += waves) {
+        int32_t lo = 0, hi = nbr;  // row = last lo with rp[lo] <= p
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (rp[mid] <= p) lo = mid;
+            else hi = mid;
         }
-    } else {
-        for (int64_t e = lane_id(); e < len; e += kWave)
-            panel[(c0 + e / m) * ld + r0 + e % m] = src[e];
+        const int32_t row = lo;
+        const int m = rbs[row];
+        const int64_t r0 = row_off[row];
+        const int32_t j = ci[p];
+        const int n = cbs[j];
+        const int64_t c0 = col_off[j];
+        const T *src = data + blk_off[p];
+        const int64_t len = (int64_t)m * n;
+        if (len < (1 << 20) && m < 4096) {
+            const float rcp = 1.0f / (float)m;
+            for (int e = lane_id(); e < len; e += kWave) {
+                int ii;
+                const int jj = divmod_small(e, m, rcp, &ii);
+                panel[(c0 + jj) * ld + r0 + ii] = src[e];
+            }
+        } else {
+            for (int64_t e = lane_id(); e < len; e += kWave)
+                panel[(c0 + e / m) * ld + r0 + e % m] = src[e];
+        }
     }
 }
 
@@ -283,11 +284,13 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(GemmArgs g) {
 // c_map[I*nbc + J] = CSR position of block (I,J) in C, or -1.
 __global__ __launch_bounds__(256) void k_block_map(int32_t nbr, int32_t nbc, const int64_t *rp,
                                                    const int32_t *ci, int32_t *map) {
-    const int32_t row = blockIdx.x;
-    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[(int64_t)row * nbc + j] = -1;
-    __syncthreads();
-    for (int64_t p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x)
-        map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[(int64_t)row * nbc + j] = -1;
+        __syncthreads();
+        for (int64_t p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x)
+            map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
+        __syncthreads();
+    }
 }
 
 }  // namespace
@@ -322,7 +325,7 @@ int dense_multiply_t(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix
     const int KB = options().dense_kb == 32 ? 32 : 16;
     const int64_t Mp = ceil_div(M, BM) * BM, Np = ceil_div(N, BN) * BN, Kp = ceil_div(K, KB) * KB;
     const int64_t tiles = (Mp / BM) * (Np / BN);
-    if (tiles > INT32_MAX || Mp * Kp > (int64_t(1) << 47) || Kp * Np > (int64_t(1) << 47)) {
+    if (tiles > kMaxGridBlocks || Mp * Kp > (int64_t(1) << 47) || Kp * Np > (int64_t(1) << 47)) {
         set_error(BSMM_ERANGE, "dense panels too large");
         return BSMM_ERANGE;
     }
@@ -354,7 +357,7 @@ int dense_multiply_t(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix
             return BSMM_ENOTSUP;
         }
         BSMM_TRY(cmap.reserve(sizeof(int32_t) * cells, s));
-        hipLaunchKernelGGL(k_block_map, dim3(C->nbr), dim3(256), 0, s, C->nbr, C->nbc,
+        hipLaunchKernelGGL(k_block_map, dim3(grid_rows(C->nbr)), dim3(256), 0, s, C->nbr, C->nbc,
                            C->d_row_ptr(), C->d_col_ind(), cmap.as<int32_t>());
         BSMM_TRY(launch_check("block_map"));
         d_cmap = cmap.as<int32_t>();

@@ -96,21 +96,21 @@ constexpr int kNonFiniteExp = INT_MIN;
 // Row exponents of a k-contiguous matrix (rows x ld): one wave per row.
 __global__ __launch_bounds__(256) void k_row_exp(const double *X, int64_t rows, int64_t K,
                                                  int64_t ld, int *e) {
-    const int64_t r = (int64_t)blockIdx.x * 4 + wave_id();
-    if (r >= rows) return;
-    double mx = 0.0;
-    bool bad = false;
-    for (int64_t k = lane_id(); k < K; k += kWave) {
-        const double x = X[r * ld + k];
-        bad |= !isfinite(x);
-        mx = fmax(mx, fabs(x));
-    }
-    mx = wave_max(mx);
-    const bool any_bad = __ballot(bad) != 0;
-    if (lane_id() == 0) {
-        int ex = 0;
-        if (mx > 0.0) (void)frexp(mx, &ex);
-        e[r] = any_bad ? kNonFiniteExp : ex;
+    for (int64_t r = (int64_t)blockIdx.x * 4 + wave_id(); r < rows; r += (int64_t)gridDim.x * 4) {
+        double mx = 0.0;
+        bool bad = false;
+        for (int64_t k = lane_id(); k < K; k += kWave) {
+            const double x = X[r * ld + k];
+            bad |= !isfinite(x);
+            mx = fmax(mx, fabs(x));
+        }
+        mx = wave_max(mx);
+        const bool any_bad = __ballot(bad) != 0;
+        if (lane_id() == 0) {
+            int ex = 0;
+            if (mx > 0.0) (void)frexp(mx, &ex);
+            e[r] = any_bad ? kNonFiniteExp : ex;
+        }
     }
 }
 
@@ -122,29 +122,31 @@ __global__ __launch_bounds__(256) void k_slice(const double *X, int64_t rows, in
                                                const int *e, signed char *out) {
     // Thread -> (k panel p, row r, quarter q of the panel's 32 bytes):
     // consecutive threads write consecutive 8-byte groups of the output.
-    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= rows * (ld / 8)) return;
-    const int q = (int)(idx & 3);
-    const int64_t rp = idx >> 2;
-    const int64_t p = rp / rows, r = rp - p * rows;
-    const int64_t k = 32 * p + 8 * q;
-    // Scaling by 2^-e in one step is exact also for subnormal rows (e below
-    // -1022, where 2^-e itself would overflow).
-    const int er = e[r];
-    double v[8];
+    const int64_t total = rows * (ld / 8);
+    for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+         idx += (int64_t)gridDim.x * blockDim.x) {
+        const int q = (int)(idx & 3);
+        const int64_t rp = idx >> 2;
+        const int64_t p = rp / rows, r = rp - p * rows;
+        const int64_t k = 32 * p + 8 * q;
+        // Scaling by 2^-e in one step is exact also for subnormal rows (e
+        // below -1022, where 2^-e itself would overflow).
+        const int er = e[r];
+        double v[8];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) v[j] = er == kNonFiniteExp ? 0.0 : ldexp(X[r * ld + k + j], -er);
-    for (int s = 0; s < S; ++s) {
-        unsigned long long w = 0;
+        for (int j = 0; j < 8; ++j) v[j] = er == kNonFiniteExp ? 0.0 : ldexp(X[r * ld + k + j], -er);
+        for (int s = 0; s < S; ++s) {
+            unsigned long long w = 0;
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            const double t = v[j] * 128.0;
-            const double d = trunc(t);
-            v[j] = t - d;
-            w |= (unsigned long long)(unsigned char)(signed char)(int)d << (8 * j);
+            for (int j = 0; j < 8; ++j) {
+                const double t = v[j] * 128.0;
+                const double d = trunc(t);
+                v[j] = t - d;
+                w |= (unsigned long long)(unsigned char)(signed char)(int)d << (8 * j);
+            }
+            *reinterpret_cast<unsigned long long *>(out + (int64_t)s * rows * ld + p * rows * 32 + r * 32 +
+                                                    8 * q) = w;
         }
-        *reinterpret_cast<unsigned long long *>(out + (int64_t)s * rows * ld + p * rows * 32 + r * 32 +
-                                                8 * q) = w;
     }
 }
 
@@ -654,26 +656,27 @@ __global__ __launch_bounds__(256) void k_merge_t(int32_t nbr, int64_t nnzb, cons
                                                  const int64_t *col_off, const int64_t *rp,
                                                  const int32_t *ci, const int64_t *blk_off,
                                                  const double *data, double *panel, int64_t ld) {
-    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (p >= nnzb) return;
-    int32_t lo = 0, hi = nbr;  // block row: rp[lo] <= p < rp[lo + 1]
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (rp[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    const int m = rbs[lo];
-    const int64_t r0 = row_off[lo];
-    const int32_t j = ci[p];
-    const int n = cbs[j];
-    const int64_t c0 = col_off[j];
-    const double *src = data + blk_off[p];
-    const int64_t len = (int64_t)m * n;
-    // Consecutive lanes write consecutive columns of one panel row (reads
-    // stride through the block, which stays in cache).
-    for (int64_t e = lane_id(); e < len; e += kWave) {
-        const int64_t ii = e / n, jj = e - ii * n;
-        panel[(r0 + ii) * ld + c0 + jj] = src[jj * m + ii];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); p < nnzb; p += waves) {
+        int32_t lo = 0, hi = nbr;  // block row: rp[lo] <= p < rp[lo + 1]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (rp[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        const int m = rbs[lo];
+        const int64_t r0 = row_off[lo];
+        const int32_t j = ci[p];
+        const int n = cbs[j];
+        const int64_t c0 = col_off[j];
+        const double *src = data + blk_off[p];
+        const int64_t len = (int64_t)m * n;
+        // Consecutive lanes write consecutive columns of one panel row
+        // (reads stride through the block, which stays in cache).
+        for (int64_t e = lane_id(); e < len; e += kWave) {
+            const int64_t ii = e / n, jj = e - ii * n;
+            panel[(r0 + ii) * ld + c0 + jj] = src[jj * m + ii];
+        }
     }
 }
 
@@ -682,34 +685,37 @@ __global__ __launch_bounds__(256) void k_merge_c(int32_t nbr, int64_t nnzb, cons
                                                  const int64_t *col_off, const int64_t *rp,
                                                  const int32_t *ci, const int64_t *blk_off,
                                                  const double *data, double *panel, int64_t ld) {
-    const int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (p >= nnzb) return;
-    int32_t lo = 0, hi = nbr;  // block row: rp[lo] <= p < rp[lo + 1]
-    while (hi - lo > 1) {
-        const int32_t mid = (lo + hi) >> 1;
-        if (rp[mid] <= p) lo = mid;
-        else hi = mid;
-    }
-    const int m = rbs[lo];
-    const int64_t r0 = row_off[lo];
-    const int32_t j = ci[p];
-    const int n = cbs[j];
-    const int64_t c0 = col_off[j];
-    const double *src = data + blk_off[p];
-    const int64_t len = (int64_t)m * n;
-    for (int64_t e = lane_id(); e < len; e += kWave) {
-        const int64_t jj = e / m, ii = e - jj * m;
-        panel[(c0 + jj) * ld + r0 + ii] = src[e];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); p < nnzb; p += waves) {
+        int32_t lo = 0, hi = nbr;  // block row: rp[lo] <= p < rp[lo + 1]
+        while (hi - lo > 1) {
+            const int32_t mid = (lo + hi) >> 1;
+            if (rp[mid] <= p) lo = mid;
+            else hi = mid;
+        }
+        const int m = rbs[lo];
+        const int64_t r0 = row_off[lo];
+        const int32_t j = ci[p];
+        const int n = cbs[j];
+        const int64_t c0 = col_off[j];
+        const double *src = data + blk_off[p];
+        const int64_t len = (int64_t)m * n;
+        for (int64_t e = lane_id(); e < len; e += kWave) {
+            const int64_t jj = e / m, ii = e - jj * m;
+            panel[(c0 + jj) * ld + r0 + ii] = src[e];
+        }
     }
 }
 
-__global__ __launch_bounds__(256) void k_block_map_e(int32_t nbc, const int64_t *rp,
+__global__ __launch_bounds__(256) void k_block_map_e(int32_t nbr, int32_t nbc, const int64_t *rp,
                                                      const int32_t *ci, int32_t *map) {
-    const int32_t row = blockIdx.x;
-    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[(int64_t)row * nbc + j] = -1;
-    __syncthreads();
-    for (int64_t p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x)
-        map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[(int64_t)row * nbc + j] = -1;
+        __syncthreads();
+        for (int64_t p = rp[row] + threadIdx.x; p < rp[row + 1]; p += blockDim.x)
+            map[(int64_t)row * nbc + ci[p]] = (int32_t)p;
+        __syncthreads();
+    }
 }
 
 using EmulKernel = void (*)(EmulArgs);
@@ -804,7 +810,8 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
             return BSMM_ENOTSUP;
         }
         BSMM_TRY(cmap.reserve(sizeof(int32_t) * cells, s));
-        hipLaunchKernelGGL(k_block_map_e, dim3(C->nbr), dim3(256), 0, s, C->nbc, C->d_row_ptr(),
+        hipLaunchKernelGGL(k_block_map_e, dim3(grid_rows(C->nbr)), dim3(256), 0, s, C->nbr, C->nbc,
+                           C->d_row_ptr(),
                            C->d_col_ind(), cmap.as<int32_t>());
         BSMM_TRY(launch_check("emul block map"));
         d_cmap = cmap.as<int32_t>();
@@ -813,7 +820,7 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
     const int64_t nchunks = ceil_div(Kp, chunk);
     if (nchunks > 1) BSMM_TRY(V.reserve(sizeof(long long) * S * Mp * Np, s));
     const int64_t tiles = (Mp / tile_m) * (Np / tile_n);
-    if (tiles > INT32_MAX) {
+    if (tiles > kMaxGridBlocks) {
         set_error(BSMM_ERANGE, "emulated product too large");
         return BSMM_ERANGE;
     }

@@ -14,38 +14,41 @@ template <class T>
 __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *blk_off,
                                                    const T *data, double eps2,
                                                    int64_t *keep, int64_t *keep_elems) {
-    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (b >= nnzb) return;
-    const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
-    // Four independent partial sums per lane keep four loads in flight.
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int64_t e = lane_id();
-    for (; e + 3 * kWave < len; e += 4 * kWave) {
-        const double x0 = (double)data[o + e], x1 = (double)data[o + e + kWave];
-        const double x2 = (double)data[o + e + 2 * kWave], x3 = (double)data[o + e + 3 * kWave];
-        s0 = fma(x0, x0, s0);
-        s1 = fma(x1, x1, s1);
-        s2 = fma(x2, x2, s2);
-        s3 = fma(x3, x3, s3);
-    }
-    for (; e < len; e += kWave) {
-        const double x = (double)data[o + e];
-        s0 = fma(x, x, s0);
-    }
-    double s = wave_sum((s0 + s1) + (s2 + s3));
-    if (lane_id() == 0) {
-        const int64_t k = (s < eps2) ? 0 : 1;
-        keep[b] = k;
-        keep_elems[b] = k ? len : 0;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
+        const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
+        // Four independent partial sums per lane keep four loads in flight.
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int64_t e = lane_id();
+        for (; e + 3 * kWave < len; e += 4 * kWave) {
+            const double x0 = (double)data[o + e], x1 = (double)data[o + e + kWave];
+            const double x2 = (double)data[o + e + 2 * kWave], x3 = (double)data[o + e + 3 * kWave];
+            s0 = fma(x0, x0, s0);
+            s1 = fma(x1, x1, s1);
+            s2 = fma(x2, x2, s2);
+            s3 = fma(x3, x3, s3);
+        }
+        for (; e < len; e += kWave) {
+            const double x = (double)data[o + e];
+            s0 = fma(x, x, s0);
+        }
+        double s = wave_sum((s0 + s1) + (s2 + s3));
+        if (lane_id() == 0) {
+            const int64_t k = (s < eps2) ? 0 : 1;
+            keep[b] = k;
+            keep_elems[b] = k ? len : 0;
+        }
     }
 }
 
 __global__ __launch_bounds__(256) void k_new_row_ptr(int32_t nbr, int64_t nnzb, const int64_t *rp,
                                                      const int64_t *kpos, int64_t *new_rp,
                                                      int64_t *new_off, int64_t total_elems) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i <= nbr) new_rp[i] = kpos[rp[i]];
-    if (i == 0) new_off[kpos[nnzb]] = total_elems;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i <= nbr;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        new_rp[i] = kpos[rp[i]];
+        if (i == 0) new_off[kpos[nnzb]] = total_elems;
+    }
 }
 
 // One wave per old block: kept blocks move to their new place.
@@ -54,25 +57,26 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
                                                  const int64_t *blk_off, const T *data,
                                                  const int64_t *kpos, const int64_t *epos,
                                                  int32_t *new_ci, int64_t *new_off, T *new_data) {
-    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (b >= nnzb) return;
-    if (kpos[b + 1] == kpos[b]) return;  // dropped
-    const int64_t nb = kpos[b];
-    const int64_t o = blk_off[b], len = blk_off[b + 1] - o, no = epos[b];
-    if (lane_id() == 0) {
-        new_ci[nb] = ci[b];
-        new_off[nb] = no;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
+        if (kpos[b + 1] == kpos[b]) continue;  // dropped
+        const int64_t nb = kpos[b];
+        const int64_t o = blk_off[b], len = blk_off[b + 1] - o, no = epos[b];
+        if (lane_id() == 0) {
+            new_ci[nb] = ci[b];
+            new_off[nb] = no;
+        }
+        int64_t e = lane_id();
+        for (; e + 3 * kWave < len; e += 4 * kWave) {
+            const T x0 = data[o + e], x1 = data[o + e + kWave];
+            const T x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
+            new_data[no + e] = x0;
+            new_data[no + e + kWave] = x1;
+            new_data[no + e + 2 * kWave] = x2;
+            new_data[no + e + 3 * kWave] = x3;
+        }
+        for (; e < len; e += kWave) new_data[no + e] = data[o + e];
     }
-    int64_t e = lane_id();
-    for (; e + 3 * kWave < len; e += 4 * kWave) {
-        const T x0 = data[o + e], x1 = data[o + e + kWave];
-        const T x2 = data[o + e + 2 * kWave], x3 = data[o + e + 3 * kWave];
-        new_data[no + e] = x0;
-        new_data[no + e + kWave] = x1;
-        new_data[no + e + 2 * kWave] = x2;
-        new_data[no + e + 3 * kWave] = x3;
-    }
-    for (; e < len; e += kWave) new_data[no + e] = data[o + e];
 }
 
 }  // namespace

@@ -21,19 +21,20 @@ __global__ __launch_bounds__(256) void k_block_offsets(const int32_t *rbs, const
                                                        int32_t nbr, const int64_t *rp,
                                                        const int32_t *ci, const int64_t *row_base,
                                                        int64_t *blk_off) {
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (row >= nbr) return;
-    const int64_t m = rbs[row];
-    int64_t base = row_base[row];
-    const int64_t p0 = rp[row], p1 = rp[row + 1];
-    for (int64_t c = p0; c < p1; c += kWave) {
-        const int64_t p = c + lane_id();
-        const int64_t v = p < p1 ? m * cbs[ci[p]] : 0;
-        const int64_t inc = wave_inclusive_scan(v);
-        if (p < p1) blk_off[p] = base + inc - v;
-        base += __shfl(inc, kWave - 1, kWave);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); row < nbr; row += waves) {
+        const int64_t m = rbs[row];
+        int64_t base = row_base[row];
+        const int64_t p0 = rp[row], p1 = rp[row + 1];
+        for (int64_t c = p0; c < p1; c += kWave) {
+            const int64_t p = c + lane_id();
+            const int64_t v = p < p1 ? m * cbs[ci[p]] : 0;
+            const int64_t inc = wave_inclusive_scan(v);
+            if (p < p1) blk_off[p] = base + inc - v;
+            base += __shfl(inc, kWave - 1, kWave);
+        }
+        if (row == nbr - 1 && lane_id() == 0) blk_off[p1] = row_base[nbr];
     }
-    if (row == nbr - 1 && lane_id() == 0) blk_off[p1] = row_base[nbr];
 }
 
 __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
@@ -42,12 +43,13 @@ __global__ void k_set_i64(int64_t *p, int64_t v) { *p = v; }
 __global__ __launch_bounds__(256) void k_row_elems(const int32_t *rbs, const int32_t *cbs,
                                                    int32_t nbr, const int64_t *rp,
                                                    const int32_t *ci, int64_t *row_elems) {
-    const int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (row >= nbr) return;
-    int64_t s = 0;
-    for (int64_t p = rp[row] + lane_id(); p < rp[row + 1]; p += kWave) s += cbs[ci[p]];
-    s = wave_sum(s);
-    if (lane_id() == 0) row_elems[row] = s * rbs[row];
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t row = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); row < nbr; row += waves) {
+        int64_t s = 0;
+        for (int64_t p = rp[row] + lane_id(); p < rp[row + 1]; p += kWave) s += cbs[ci[p]];
+        s = wave_sum(s);
+        if (lane_id() == 0) row_elems[row] = s * rbs[row];
+    }
 }
 
 // --------------------------------------------------------- symbolic
@@ -85,67 +87,71 @@ __device__ void mark_row(uint32_t *bm, int nwords, int32_t row, const int64_t *a
 }
 
 __global__ __launch_bounds__(kRowThreads) void k_symbolic_count(
-    int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
+    int32_t nbr, int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
     const int32_t *b_ci, const int64_t *c_rp, const int32_t *c_ci, const int32_t *rbs,
     const int32_t *kbs, const int32_t *cbs, int64_t *row_nnz, int64_t *row_elems,
     int64_t *row_prod, double *row_flops) {
     extern __shared__ uint32_t bm[];
     __shared__ int64_t red_i[16];
     __shared__ double red_d[16];
-    const int32_t row = blockIdx.x;
     const int nwords = (nbc + 31) >> 5;
-    int64_t np;
-    double kn;
-    mark_row(bm, nwords, row, a_rp, a_ci, b_rp, b_ci, c_rp, c_ci, kbs, cbs, &np, &kn);
-    int64_t cnt = 0, cols = 0;
-    for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
-        uint32_t bits = bm[w];
-        cnt += __popc(bits);
-        while (bits) {
-            const int b = __ffs(bits) - 1;
-            bits &= bits - 1;
-            cols += cbs[(w << 5) + b];
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        int64_t np;
+        double kn;
+        mark_row(bm, nwords, row, a_rp, a_ci, b_rp, b_ci, c_rp, c_ci, kbs, cbs, &np, &kn);
+        int64_t cnt = 0, cols = 0;
+        for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
+            uint32_t bits = bm[w];
+            cnt += __popc(bits);
+            while (bits) {
+                const int b = __ffs(bits) - 1;
+                bits &= bits - 1;
+                cols += cbs[(w << 5) + b];
+            }
         }
-    }
-    cnt = block_sum(cnt, red_i);
-    cols = block_sum(cols, red_i);
-    np = block_sum(np, red_i);
-    kn = block_sum(kn, red_d);
-    if (threadIdx.x == 0) {
-        const int64_t m = rbs[row];
-        row_nnz[row] = cnt;
-        row_elems[row] = m * cols;
-        row_prod[row] = np;
-        row_flops[row] = 2.0 * (double)m * kn;
+        cnt = block_sum(cnt, red_i);
+        cols = block_sum(cols, red_i);
+        np = block_sum(np, red_i);
+        kn = block_sum(kn, red_d);
+        if (threadIdx.x == 0) {
+            const int64_t m = rbs[row];
+            row_nnz[row] = cnt;
+            row_elems[row] = m * cols;
+            row_prod[row] = np;
+            row_flops[row] = 2.0 * (double)m * kn;
+        }
+        __syncthreads();  // the bitmap is cleared for the next row
     }
 }
 
 __global__ __launch_bounds__(kRowThreads) void k_symbolic_fill(
-    int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
+    int32_t nbr, int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
     const int32_t *b_ci, const int64_t *c_rp, const int32_t *c_ci, const int32_t *kbs,
     const int32_t *cbs, const int64_t *new_rp, int32_t *new_ci) {
     extern __shared__ uint32_t bm[];
     __shared__ int64_t red[16];
-    const int32_t row = blockIdx.x;
     const int nwords = (nbc + 31) >> 5;
-    int64_t np;
-    double kn;
-    mark_row(bm, nwords, row, a_rp, a_ci, b_rp, b_ci, c_rp, c_ci, kbs, cbs, &np, &kn);
-    int64_t out = new_rp[row];
-    for (int w0 = 0; w0 < nwords; w0 += blockDim.x) {
-        const int w = w0 + threadIdx.x;
-        const uint32_t bits = w < nwords ? bm[w] : 0u;
-        int64_t total;
-        const int64_t pos = out + block_exclusive_scan((int64_t)__popc(bits), red, &total);
-        uint32_t b = bits;
-        int64_t k = 0;
-        while (b) {
-            const int bit = __ffs(b) - 1;
-            b &= b - 1;
-            new_ci[pos + k] = (w << 5) + bit;
-            ++k;
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        int64_t np;
+        double kn;
+        mark_row(bm, nwords, row, a_rp, a_ci, b_rp, b_ci, c_rp, c_ci, kbs, cbs, &np, &kn);
+        int64_t out = new_rp[row];
+        for (int w0 = 0; w0 < nwords; w0 += blockDim.x) {
+            const int w = w0 + threadIdx.x;
+            const uint32_t bits = w < nwords ? bm[w] : 0u;
+            int64_t total;
+            const int64_t pos = out + block_exclusive_scan((int64_t)__popc(bits), red, &total);
+            uint32_t b = bits;
+            int64_t k = 0;
+            while (b) {
+                const int bit = __ffs(b) - 1;
+                b &= b - 1;
+                new_ci[pos + k] = (w << 5) + bit;
+                ++k;
+            }
+            out += total;
         }
-        out += total;
+        __syncthreads();  // the bitmap is cleared for the next row
     }
 }
 
@@ -167,31 +173,32 @@ __global__ __launch_bounds__(256) void k_full_pattern(int32_t nbr, int32_t nbc, 
 // One workgroup per new block row; each wave copies whole blocks: the old
 // block (found by binary search in the old row) or zeros.
 template <class T>
-__global__ __launch_bounds__(256) void k_relayout(const int32_t *rbs, const int32_t *cbs,
+__global__ __launch_bounds__(256) void k_relayout(int32_t nbr, const int32_t *rbs, const int32_t *cbs,
                                                   const int64_t *o_rp, const int32_t *o_ci,
                                                   const int64_t *o_off, const T *o_data,
                                                   const int64_t *n_rp, const int32_t *n_ci,
                                                   const int64_t *n_off, T *n_data) {
-    const int32_t row = blockIdx.x;
     const int nw = blockDim.x / kWave;
-    const int64_t m = rbs[row];
-    for (int64_t p = n_rp[row] + wave_id(); p < n_rp[row + 1]; p += nw) {
-        const int32_t j = n_ci[p];
-        int64_t lo = o_rp[row], hi = o_rp[row + 1], found = -1;
-        while (lo < hi) {
-            const int64_t mid = lo + (hi - lo) / 2;
-            const int32_t c = o_ci[mid];
-            if (c < j) lo = mid + 1;
-            else if (c > j) hi = mid;
-            else { found = mid; break; }
-        }
-        const int64_t len = m * cbs[j];
-        T *dst = n_data + n_off[p];
-        if (found >= 0) {
-            const T *src = o_data + o_off[found];
-            for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = src[e];
-        } else {
-            for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = T(0);
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        const int64_t m = rbs[row];
+        for (int64_t p = n_rp[row] + wave_id(); p < n_rp[row + 1]; p += nw) {
+            const int32_t j = n_ci[p];
+            int64_t lo = o_rp[row], hi = o_rp[row + 1], found = -1;
+            while (lo < hi) {
+                const int64_t mid = lo + (hi - lo) / 2;
+                const int32_t c = o_ci[mid];
+                if (c < j) lo = mid + 1;
+                else if (c > j) hi = mid;
+                else { found = mid; break; }
+            }
+            const int64_t len = m * cbs[j];
+            T *dst = n_data + n_off[p];
+            if (found >= 0) {
+                const T *src = o_data + o_off[found];
+                for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = src[e];
+            } else {
+                for (int64_t e = lane_id(); e < len; e += kWave) dst[e] = T(0);
+            }
         }
     }
 }
@@ -201,15 +208,16 @@ __global__ __launch_bounds__(256) void k_relayout(const int32_t *rbs, const int3
 template <class T>
 __global__ __launch_bounds__(256) void k_scale_blocks(int64_t nnzb, const int64_t *blk_off,
                                                       const int64_t *flags, T beta, T *data) {
-    const int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
-    if (b >= nnzb) return;
-    if (flags && flags[b] != 0) return;
-    T *d = data + blk_off[b];
-    const int64_t len = blk_off[b + 1] - blk_off[b];
-    if (beta == T(0))
-        for (int64_t e = lane_id(); e < len; e += kWave) d[e] = T(0);
-    else
-        for (int64_t e = lane_id(); e < len; e += kWave) d[e] *= beta;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
+        if (flags && flags[b] != 0) continue;
+        T *d = data + blk_off[b];
+        const int64_t len = blk_off[b + 1] - blk_off[b];
+        if (beta == T(0))
+            for (int64_t e = lane_id(); e < len; e += kWave) d[e] = T(0);
+        else
+            for (int64_t e = lane_id(); e < len; e += kWave) d[e] *= beta;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_fill_zero(double *p, int64_t n) {
@@ -267,7 +275,7 @@ int symbolic_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_ma
     size_t lds;
     BSMM_TRY(bitmap_lds_bytes(B->nbc, &lds));
     const bool has_c = C && C->nnzb > 0;
-    hipLaunchKernelGGL(k_symbolic_count, dim3(A->nbr), dim3(kRowThreads), lds, s, B->nbc,
+    hipLaunchKernelGGL(k_symbolic_count, dim3(grid_rows(A->nbr)), dim3(kRowThreads), lds, s, A->nbr, B->nbc,
                        A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
                        has_c ? C->d_row_ptr() : nullptr, has_c ? C->d_col_ind() : nullptr,
                        A->d_rbs(), B->d_rbs(), B->d_cbs(), d_row_nnz, d_row_elems, d_row_prod,
@@ -281,7 +289,7 @@ int symbolic_fill(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_mat
     size_t lds;
     BSMM_TRY(bitmap_lds_bytes(B->nbc, &lds));
     const bool has_c = C && C->nnzb > 0;
-    hipLaunchKernelGGL(k_symbolic_fill, dim3(A->nbr), dim3(kRowThreads), lds, s, B->nbc,
+    hipLaunchKernelGGL(k_symbolic_fill, dim3(grid_rows(A->nbr)), dim3(kRowThreads), lds, s, A->nbr, B->nbc,
                        A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
                        has_c ? C->d_row_ptr() : nullptr, has_c ? C->d_col_ind() : nullptr,
                        B->d_rbs(), B->d_cbs(), d_new_row_ptr, d_new_col_ind);
@@ -300,12 +308,14 @@ int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *
              const int64_t *d_new_off, void *d_new_data, hipStream_t s) {
     if (Cold->nbr == 0) return BSMM_OK;
     if (Cold->dtype == BSMM_F32)
-        hipLaunchKernelGGL(k_relayout<float>, dim3(Cold->nbr), dim3(256), 0, s, Cold->d_rbs(),
+        hipLaunchKernelGGL(k_relayout<float>, dim3(grid_rows(Cold->nbr)), dim3(256), 0, s, Cold->nbr,
+                           Cold->d_rbs(),
                            Cold->d_cbs(), Cold->d_row_ptr(), Cold->d_col_ind(), Cold->d_blk_off(),
                            (const float *)Cold->d_raw(), d_new_rp, d_new_ci, d_new_off,
                            (float *)d_new_data);
     else
-        hipLaunchKernelGGL(k_relayout<double>, dim3(Cold->nbr), dim3(256), 0, s, Cold->d_rbs(),
+        hipLaunchKernelGGL(k_relayout<double>, dim3(grid_rows(Cold->nbr)), dim3(256), 0, s, Cold->nbr,
+                           Cold->d_rbs(),
                            Cold->d_cbs(), Cold->d_row_ptr(), Cold->d_col_ind(), Cold->d_blk_off(),
                            (const double *)Cold->d_raw(), d_new_rp, d_new_ci, d_new_off,
                            (double *)d_new_data);

@@ -428,11 +428,20 @@ int multiply_fixed_pattern(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, dou
 
 // --------------------------------------------------------------- helpers
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
-inline unsigned grid_of(int64_t n, int64_t per, int64_t cap = 1 << 30) {
+// Largest one-dimensional grid in workgroups: a launch counts its grid in
+// work-items with 32 bits, so gridDim.x * blockDim.x must stay below 2^32
+// (past it the launch is refused, or wraps to a smaller grid); with up to
+// 1024 threads per workgroup that allows 2^22 - 1 workgroups.  Every kernel
+// launched with grid_of or grid_rows strides over its items by the grid.
+constexpr int64_t kMaxGridBlocks = (int64_t(1) << 22) - 1;
+inline unsigned grid_of(int64_t n, int64_t per, int64_t cap = kMaxGridBlocks) {
     int64_t g = ceil_div(n, per);
     if (g < 1) g = 1;
     if (g > cap) g = cap;
+    if (g > kMaxGridBlocks) g = kMaxGridBlocks;
     return (unsigned)g;
 }
+// One workgroup per row, up to the grid limit (the kernel strides over rows).
+inline unsigned grid_rows(int64_t rows) { return grid_of(rows, 1); }
 
 }  // namespace bsmm

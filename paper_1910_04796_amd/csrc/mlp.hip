@@ -293,10 +293,21 @@ extern "C" int bsmm_mlp_features(int32_t m, int32_t n, int32_t k, int32_t run_le
     return BSMM_OK;
 }
 
+// The sample kernels run one wave per sample over at most kMaxGridBlocks
+// workgroups of four waves.
+static int check_samples(int64_t n) {
+    if (n > 4 * kMaxGridBlocks) {
+        set_error(BSMM_ERANGE, "more than %lld samples", (long long)(4 * kMaxGridBlocks));
+        return BSMM_ERANGE;
+    }
+    return BSMM_OK;
+}
+
 extern "C" int bsmm_mlp_forward(int32_t n_features, const float *params, int64_t n, const float *x,
                                 float *y) {
     clear_error();
     BSMM_TRY(check_f(n_features));
+    BSMM_TRY(check_samples(n));
     if (!params || (n > 0 && (!x || !y)) || n < 0) {
         set_error(BSMM_EINVAL, "bad arguments");
         return BSMM_EINVAL;
@@ -316,6 +327,7 @@ extern "C" int bsmm_mlp_grad(int32_t n_features, const float *params, int64_t n,
                              const float *t, float *grad, float *loss) {
     clear_error();
     BSMM_TRY(check_f(n_features));
+    BSMM_TRY(check_samples(n));
     if (!params || !x || !t || !grad || n < 1) {
         set_error(BSMM_EINVAL, "bad arguments");
         return BSMM_EINVAL;
@@ -390,6 +402,7 @@ extern "C" int bsmm_mlp_train(int32_t n_features, float *params, int64_t n, cons
                               float *final_loss) {
     clear_error();
     BSMM_TRY(check_f(n_features));
+    BSMM_TRY(check_samples(n));
     if (!params || !x || !t || n < 1 || epochs < 0 || batch < 1 || !(lr > 0.0f)) {
         set_error(BSMM_EINVAL, "bad arguments");
         return BSMM_EINVAL;

@@ -47,7 +47,7 @@ __device__ __forceinline__ void a_part(const int64_t *a_rp, int32_t row, int par
 // Workgroup (row, part): products per C block of the row from the part's
 // share of A's block row (P > 1 splits long A rows of few-row products;
 // the part counts go to pcount[c * P + part], else straight to c_count).
-__global__ __launch_bounds__(256) void k_stack_count(int32_t nbc, const int64_t *a_rp,
+__global__ __launch_bounds__(256) void k_stack_count(int32_t nbr, int32_t nbc, const int64_t *a_rp,
                                                      const int32_t *a_ci, const int64_t *b_rp,
                                                      const int32_t *b_ci, const int64_t *c_rp,
                                                      const int32_t *c_ci, int64_t *c_count,
@@ -56,33 +56,35 @@ __global__ __launch_bounds__(256) void k_stack_count(int32_t nbc, const int64_t 
     extern __shared__ int32_t lds[];
     int32_t *map = lds;          // nbc entries: column -> slot in the C row, or -1
     int32_t *cnt = lds + nbc;    // row length entries
-    const int32_t row = blockIdx.x;
     const int part = blockIdx.y;
-    const int64_t p0 = c_rp[row];
-    const int32_t len = (int32_t)(c_rp[row + 1] - p0);
-    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
-    __syncthreads();
-    for (int s = threadIdx.x; s < len; s += blockDim.x) {
-        map[c_ci[p0 + s]] = s;
-        cnt[s] = 0;
-    }
-    __syncthreads();
     const int nw = blockDim.x / kWave;
-    int64_t pa0, pa1;
-    a_part(a_rp, row, part, P, &pa0, &pa1);
-    for (int64_t pa = pa0 + wave_id(); pa < pa1; pa += nw) {
-        const int32_t kb = a_ci[pa];
-        for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
-            const int32_t s = map[b_ci[q]];
-            if (s >= 0) atomicAdd(&cnt[s], 1);
-            else *missing = 1;
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        const int64_t p0 = c_rp[row];
+        const int32_t len = (int32_t)(c_rp[row + 1] - p0);
+        for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
+        __syncthreads();
+        for (int s = threadIdx.x; s < len; s += blockDim.x) {
+            map[c_ci[p0 + s]] = s;
+            cnt[s] = 0;
         }
-    }
-    __syncthreads();
-    for (int s = threadIdx.x; s < len; s += blockDim.x) {
-        if (P == 1) c_count[p0 + s] = cnt[s];
-        else pcount[(p0 + s) * P + part] = cnt[s];
-        c_row[p0 + s] = row;  // every part writes the same value
+        __syncthreads();
+        int64_t pa0, pa1;
+        a_part(a_rp, row, part, P, &pa0, &pa1);
+        for (int64_t pa = pa0 + wave_id(); pa < pa1; pa += nw) {
+            const int32_t kb = a_ci[pa];
+            for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
+                const int32_t s = map[b_ci[q]];
+                if (s >= 0) atomicAdd(&cnt[s], 1);
+                else *missing = 1;
+            }
+        }
+        __syncthreads();
+        for (int s = threadIdx.x; s < len; s += blockDim.x) {
+            if (P == 1) c_count[p0 + s] = cnt[s];
+            else pcount[(p0 + s) * P + part] = cnt[s];
+            c_row[p0 + s] = row;  // every part writes the same value
+        }
+        __syncthreads();  // map and counts are reset for the next row
     }
 }
 
@@ -116,28 +118,31 @@ __global__ __launch_bounds__(256) void k_class_hist(int64_t c_base, int64_t nnzb
                                                     const int32_t *csi, int ncs, int ncl,
                                                     int64_t *hist, int64_t *hist_p) {
     extern __shared__ int64_t lds_h[];
-    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     unsigned long long *psum = (unsigned long long *)lds_h + wave_id() * ncl;
     int32_t *cnt = (int32_t *)(lds_h + (blockDim.x / kWave) * ncl) + wave_id() * ncl;
-    if (tile >= ntiles) return;
-    for (int cl = lane_id(); cl < ncl; cl += kWave) {
-        cnt[cl] = 0;
-        psum[cl] = 0;
-    }
-    wave_lds_sync();
-    const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
-    for (int64_t c = c_base + tile * kTile + lane_id(); c < end; c += kWave) {
-        const int64_t n = c_count[c];
-        if (n > 0) {
-            const int cl = class_of(c, c_row, c_ci, rsi, csi, ncs);
-            atomicAdd(&cnt[cl], 1);
-            atomicAdd(&psum[cl], (unsigned long long)n);
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); tile < ntiles;
+         tile += waves) {
+        for (int cl = lane_id(); cl < ncl; cl += kWave) {
+            cnt[cl] = 0;
+            psum[cl] = 0;
         }
-    }
-    wave_lds_sync();
-    for (int cl = lane_id(); cl < ncl; cl += kWave) {
-        hist[(int64_t)cl * ntiles + tile] = cnt[cl];
-        hist_p[(int64_t)cl * ntiles + tile] = (int64_t)psum[cl];
+        wave_lds_sync();
+        const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
+        for (int64_t c = c_base + tile * kTile + lane_id(); c < end; c += kWave) {
+            const int64_t n = c_count[c];
+            if (n > 0) {
+                const int cl = class_of(c, c_row, c_ci, rsi, csi, ncs);
+                atomicAdd(&cnt[cl], 1);
+                atomicAdd(&psum[cl], (unsigned long long)n);
+            }
+        }
+        wave_lds_sync();
+        for (int cl = lane_id(); cl < ncl; cl += kWave) {
+            hist[(int64_t)cl * ntiles + tile] = cnt[cl];
+            hist_p[(int64_t)cl * ntiles + tile] = (int64_t)psum[cl];
+        }
+        wave_lds_sync();
     }
 }
 
@@ -148,36 +153,38 @@ __global__ __launch_bounds__(256) void k_class_scatter(
     int ncs, int ncl, const int64_t *hoff, int64_t *run_cblk, int32_t *run_class,
     int64_t *run_coff, int64_t *run_cnt, int64_t *run_of_c) {
     extern __shared__ int64_t lds64[];
-    const int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id();
     int64_t *next = lds64 + wave_id() * ncl;
-    if (tile >= ntiles) return;
-    for (int cl = lane_id(); cl < ncl; cl += kWave) next[cl] = hoff[(int64_t)cl * ntiles + tile];
-    wave_lds_sync();
-    const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
-    for (int64_t base = c_base + tile * kTile; base < end; base += kWave) {
-        const int64_t c = base + lane_id();
-        const bool inb = c < end;
-        const int64_t cnt = inb ? c_count[c] : 0;
-        const bool valid = cnt > 0;
-        const int cl = valid ? class_of(c, c_row, c_ci, rsi, csi, ncs) : -1;
-        if (inb && !valid) run_of_c[c] = -1;
-        uint64_t pending = __ballot(valid);
-        while (pending) {
-            const int leader = __ffsll((unsigned long long)pending) - 1;
-            const int cl_lead = __shfl(cl, leader, kWave);
-            const uint64_t mask = __ballot(valid && cl == cl_lead);
-            if (valid && cl == cl_lead) {
-                const int64_t r = next[cl_lead] + __popcll(mask & lanemask_lt());
-                run_cblk[r] = c;
-                run_class[r] = cl;
-                run_coff[r] = c_blk_off[c];
-                run_cnt[r] = cnt;
-                run_of_c[c] = r;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t tile = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); tile < ntiles;
+         tile += waves) {
+        for (int cl = lane_id(); cl < ncl; cl += kWave) next[cl] = hoff[(int64_t)cl * ntiles + tile];
+        wave_lds_sync();
+        const int64_t end = c_base + std::min<int64_t>(nnzb, (tile + 1) * kTile);
+        for (int64_t base = c_base + tile * kTile; base < end; base += kWave) {
+            const int64_t c = base + lane_id();
+            const bool inb = c < end;
+            const int64_t cnt = inb ? c_count[c] : 0;
+            const bool valid = cnt > 0;
+            const int cl = valid ? class_of(c, c_row, c_ci, rsi, csi, ncs) : -1;
+            if (inb && !valid) run_of_c[c] = -1;
+            uint64_t pending = __ballot(valid);
+            while (pending) {
+                const int leader = __ffsll((unsigned long long)pending) - 1;
+                const int cl_lead = __shfl(cl, leader, kWave);
+                const uint64_t mask = __ballot(valid && cl == cl_lead);
+                if (valid && cl == cl_lead) {
+                    const int64_t r = next[cl_lead] + __popcll(mask & lanemask_lt());
+                    run_cblk[r] = c;
+                    run_class[r] = cl;
+                    run_coff[r] = c_blk_off[c];
+                    run_cnt[r] = cnt;
+                    run_of_c[c] = r;
+                }
+                wave_lds_sync();
+                if (lane_id() == leader) next[cl_lead] += __popcll(mask);
+                wave_lds_sync();
+                pending &= ~mask;
             }
-            wave_lds_sync();
-            if (lane_id() == leader) next[cl_lead] += __popcll(mask);
-            wave_lds_sync();
-            pending &= ~mask;
         }
     }
 }
@@ -186,8 +193,9 @@ __global__ void k_zero_i32(int32_t *p) { *p = 0; }
 
 // out[r] = scan[rp[r]] for r = 0..nbr: products before each C block row.
 __global__ void k_gather_rows(const int64_t *scan, const int64_t *rp, int32_t nbr, int64_t *out) {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r <= nbr) out[r] = scan[rp[r]];
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= nbr;
+         r += (int64_t)gridDim.x * blockDim.x)
+        out[r] = scan[rp[r]];
 }
 
 // out[0..ncl]: first run of every class; out[ncl+1..2 ncl+1]: its first product.
@@ -205,7 +213,7 @@ __global__ void k_gather_class_begin(const int64_t *hoff, const int64_t *hoff_p,
 // `cap` slots, each slot's next position in the stacks is kept in LDS as a
 // 64-bit index, so a product costs no global gather; longer rows keep a
 // 32-bit count per slot and gather the run's first position per product.
-__global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const int64_t *poff,
+__global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int32_t row1, int P, const int64_t *poff,
                                                     int32_t nbc, int32_t cap, const int64_t *a_rp,
                                                     const int32_t *a_ci, const int64_t *a_off,
                                                     const int64_t *b_rp, const int32_t *b_ci,
@@ -218,43 +226,45 @@ __global__ __launch_bounds__(256) void k_stack_fill(int32_t row0, int P, const i
     const int32_t nbc_pad = (nbc + 1) & ~1;
     int64_t *next = reinterpret_cast<int64_t *>(lds + nbc_pad);  // rows of at most cap slots
     int32_t *cur = lds + nbc_pad;                                // longer rows
-    const int32_t row = row0 + (int32_t)blockIdx.x;
     const int part = blockIdx.y;
-    const int64_t p0 = c_rp[row];
-    const int32_t len = (int32_t)(c_rp[row + 1] - p0);
-    const bool in_lds = len <= cap;
-    for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
-    __syncthreads();
-    for (int s = threadIdx.x; s < len; s += blockDim.x) {
-        map[c_ci[p0 + s]] = s;
-        const int64_t first = P == 1 ? 0 : poff[(p0 + s) * P + part];
-        if (in_lds) {
-            const int64_t r = run_of_c[p0 + s];
-            next[s] = r >= 0 ? run_ptr[r] + first : 0;  // r < 0: the slot receives no product
-        } else {
-            cur[s] = (int32_t)first;
-        }
-    }
-    __syncthreads();
-    int64_t pa0, pa1;
-    a_part(a_rp, row, part, P, &pa0, &pa1);
-    for (int64_t pa = pa0; pa < pa1; ++pa) {
-        const int32_t kb = a_ci[pa];
-        const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
-        for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
-            const int32_t s = map[b_ci[q]];
-            if (s < 0) continue;
-            int64_t pos;
+    for (int32_t row = row0 + (int32_t)blockIdx.x; row < row1; row += gridDim.x) {
+        const int64_t p0 = c_rp[row];
+        const int32_t len = (int32_t)(c_rp[row + 1] - p0);
+        const bool in_lds = len <= cap;
+        for (int j = threadIdx.x; j < nbc; j += blockDim.x) map[j] = -1;
+        __syncthreads();
+        for (int s = threadIdx.x; s < len; s += blockDim.x) {
+            map[c_ci[p0 + s]] = s;
+            const int64_t first = P == 1 ? 0 : poff[(p0 + s) * P + part];
             if (in_lds) {
-                pos = next[s];
-                next[s] = pos + 1;
+                const int64_t r = run_of_c[p0 + s];
+                next[s] = r >= 0 ? run_ptr[r] + first : 0;  // r < 0: the slot receives no product
             } else {
-                pos = run_ptr[run_of_c[p0 + s]] + cur[s];
-                cur[s] += 1;
+                cur[s] = (int32_t)first;
             }
-            prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
         }
         __syncthreads();
+        int64_t pa0, pa1;
+        a_part(a_rp, row, part, P, &pa0, &pa1);
+        for (int64_t pa = pa0; pa < pa1; ++pa) {
+            const int32_t kb = a_ci[pa];
+            const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
+            for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
+                const int32_t s = map[b_ci[q]];
+                if (s < 0) continue;
+                int64_t pos;
+                if (in_lds) {
+                    pos = next[s];
+                    next[s] = pos + 1;
+                } else {
+                    pos = run_ptr[run_of_c[p0 + s]] + cur[s];
+                    cur[s] += 1;
+                }
+                prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
+            }
+            __syncthreads();
+        }
+        __syncthreads();  // map and positions are reset for the next row
     }
 }
 
@@ -390,7 +400,7 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, st.missing.as<int32_t>());
     BSMM_TRY(launch_check("zero_i32"));
     const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
-    hipLaunchKernelGGL(k_stack_count, dim3(nbr, st.kparts), dim3(256), map_lds, s, nbc,
+    hipLaunchKernelGGL(k_stack_count, dim3(grid_rows(nbr), st.kparts), dim3(256), map_lds, s, nbr, nbc,
                        A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
                        C->d_row_ptr(), C->d_col_ind(), st.c_count.as<int64_t>(),
                        st.c_row.as<int32_t>(), st.missing.as<int32_t>(), st.kparts,
@@ -538,8 +548,8 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
         const int64_t nbc_pad = (nbc + 1) & ~1;
         const int32_t cap = (int32_t)std::min<int64_t>(nbc, (65536 - 4 * nbc_pad) / 8);
         const size_t fill_lds = 4 * nbc_pad + std::max<int64_t>(4 * (int64_t)nbc, 8 * (int64_t)cap);
-        hipLaunchKernelGGL(k_stack_fill, dim3(r1 - r0, st.kparts), dim3(256), fill_lds, s, r0,
-                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), nbc, cap,
+        hipLaunchKernelGGL(k_stack_fill, dim3(grid_rows(r1 - r0), st.kparts), dim3(256), fill_lds, s, r0,
+                           r1, st.kparts, (const int64_t *)st.pcount.as<int64_t>(), nbc, cap,
                            A->d_row_ptr(), A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(),
                            B->d_col_ind(), B->d_blk_off(), B->d_rbs(), C->d_row_ptr(),
                            C->d_col_ind(), (const int64_t *)st.run_of_c.as<int64_t>(),
