@@ -236,7 +236,8 @@ int fill_zero_bytes(void *p, size_t bytes, hipStream_t s);
 // ---------------------------------------------------------------- stacks
 // A product entry keeps A's element offset in 48 bits and k in 16 bits.
 constexpr int kMaxStackK = 0xFFFF;
-// Block columns of C the count and fill phases map in LDS (64 KB).
+// Block columns of C the count and fill phases map in LDS (64 KB); wider C
+// rows are searched in global memory instead.
 constexpr int kMaxStackCols = 8192;
 // Product stacks of C += A*B, grouped by shape class (m, n).
 struct Stacks {

@@ -194,11 +194,6 @@ int check_stack_limits(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsm
                   kMaxStackK, A->max_cbs);
         return BSMM_ENOTSUP;
     }
-    if (C->nbc > kMaxStackCols) {
-        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns (found %d)",
-                  kMaxStackCols, C->nbc);
-        return BSMM_ENOTSUP;
-    }
     return BSMM_OK;
 }
 

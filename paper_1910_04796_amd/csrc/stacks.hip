@@ -88,6 +88,44 @@ __global__ __launch_bounds__(256) void k_stack_count(int32_t nbr, int32_t nbc, c
     }
 }
 
+// Position of block column j in C's row [lo, hi) (sorted), or -1.
+__device__ __forceinline__ int64_t find_col(const int32_t *ci, int64_t lo, int64_t hi, int32_t j) {
+    const int64_t end = hi;
+    while (lo < hi) {
+        const int64_t mid = lo + (hi - lo) / 2;
+        if (ci[mid] < j) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo < end && ci[lo] == j ? lo : -1;
+}
+
+// k_stack_count for C with more block columns than the LDS column map
+// holds: each product's C block is found by binary search in the row's
+// column indices and counted with a global atomic (cnt: c_count, or pcount
+// when rows are split into parts; zeroed before the launch).
+__global__ __launch_bounds__(256) void k_stack_count_wide(int32_t nbr, const int64_t *a_rp,
+                                                          const int32_t *a_ci, const int64_t *b_rp,
+                                                          const int32_t *b_ci, const int64_t *c_rp,
+                                                          const int32_t *c_ci, int64_t *cnt,
+                                                          int32_t *c_row, int32_t *missing, int P) {
+    const int part = blockIdx.y;
+    const int nw = blockDim.x / kWave;
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        const int64_t p0 = c_rp[row], p1 = c_rp[row + 1];
+        for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) c_row[p] = row;
+        int64_t pa0, pa1;
+        a_part(a_rp, row, part, P, &pa0, &pa1);
+        for (int64_t pa = pa0 + wave_id(); pa < pa1; pa += nw) {
+            const int32_t kb = a_ci[pa];
+            for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
+                const int64_t c = find_col(c_ci, p0, p1, b_ci[q]);
+                if (c >= 0) atomicAdd((unsigned long long *)&cnt[P == 1 ? c : c * P + part], 1ull);
+                else *missing = 1;
+            }
+        }
+    }
+}
+
 // P > 1: per C block, the part counts become the part's first position in
 // the run (exclusive prefix in part order) and c_count their total.
 __global__ __launch_bounds__(256) void k_part_offsets(int64_t nnzb, int P, int64_t *pcount,
@@ -204,6 +242,42 @@ __global__ void k_gather_class_begin(const int64_t *hoff, const int64_t *hoff_p,
     for (int cl = threadIdx.x; cl <= ncl; cl += blockDim.x) {
         out[cl] = hoff[(int64_t)cl * ntiles];
         out[ncl + 1 + cl] = hoff_p[(int64_t)cl * ntiles];
+    }
+}
+
+// k_stack_fill for C with more block columns than the LDS map holds: the C
+// block by binary search, each (block, part)'s next position in a global
+// cursor cur[(c - c0) P + part] (zeroed before the launch).  Within one K a
+// block is hit at most once per part, and a barrier separates consecutive
+// K, so the cursors need no atomics and the runs stay in K order.
+__global__ __launch_bounds__(256) void k_stack_fill_wide(int32_t row0, int32_t row1, int P,
+                                                         const int64_t *poff, int64_t c0,
+                                                         const int64_t *a_rp, const int32_t *a_ci,
+                                                         const int64_t *a_off, const int64_t *b_rp,
+                                                         const int32_t *b_ci, const int64_t *b_off,
+                                                         const int32_t *kbs, const int64_t *c_rp,
+                                                         const int32_t *c_ci, const int64_t *run_of_c,
+                                                         const int64_t *run_ptr, int64_t *cur,
+                                                         ulonglong2 *prods) {
+    const int part = blockIdx.y;
+    for (int32_t row = row0 + (int32_t)blockIdx.x; row < row1; row += gridDim.x) {
+        const int64_t p0 = c_rp[row], p1 = c_rp[row + 1];
+        int64_t pa0, pa1;
+        a_part(a_rp, row, part, P, &pa0, &pa1);
+        for (int64_t pa = pa0; pa < pa1; ++pa) {
+            const int32_t kb = a_ci[pa];
+            const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
+            for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
+                const int64_t c = find_col(c_ci, p0, p1, b_ci[q]);
+                if (c < 0) continue;
+                const int64_t k = (c - c0) * P + part;
+                const int64_t first = P == 1 ? 0 : poff[c * P + part];
+                const int64_t pos = run_ptr[run_of_c[c]] + first + cur[k];
+                cur[k] += 1;
+                prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
+            }
+            __syncthreads();
+        }
     }
 }
 
@@ -360,10 +434,6 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
                 Stacks &st, hipStream_t s) {
     const int32_t nbr = C->nbr, nbc = C->nbc;
     const int64_t nnzb = C->nnzb;
-    if (nbc > kMaxStackCols) {
-        set_error(BSMM_ENOTSUP, "stack path supports at most %d block columns", kMaxStackCols);
-        return BSMM_ENOTSUP;
-    }
     std::vector<int32_t> rsi, csi;
     size_classes(C->rbs, st.row_sizes, rsi);
     size_classes(C->cbs, st.col_sizes, csi);
@@ -399,12 +469,21 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
     BSMM_HIP(hipMemcpyAsync(st.d_csi.p, csi.data(), sizeof(int32_t) * nbc, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, st.missing.as<int32_t>());
     BSMM_TRY(launch_check("zero_i32"));
-    const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
-    hipLaunchKernelGGL(k_stack_count, dim3(grid_rows(nbr), st.kparts), dim3(256), map_lds, s, nbr, nbc,
-                       A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
-                       C->d_row_ptr(), C->d_col_ind(), st.c_count.as<int64_t>(),
-                       st.c_row.as<int32_t>(), st.missing.as<int32_t>(), st.kparts,
-                       st.pcount.as<int64_t>());
+    if (nbc > kMaxStackCols) {
+        int64_t *cnt = st.kparts > 1 ? st.pcount.as<int64_t>() : st.c_count.as<int64_t>();
+        BSMM_TRY(fill_zero((double *)cnt, nnzb * st.kparts, s));
+        hipLaunchKernelGGL(k_stack_count_wide, dim3(grid_rows(nbr), st.kparts), dim3(256), 0, s, nbr,
+                           A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
+                           C->d_row_ptr(), C->d_col_ind(), cnt, st.c_row.as<int32_t>(),
+                           st.missing.as<int32_t>(), st.kparts);
+    } else {
+        const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
+        hipLaunchKernelGGL(k_stack_count, dim3(grid_rows(nbr), st.kparts), dim3(256), map_lds, s, nbr,
+                           nbc, A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
+                           C->d_row_ptr(), C->d_col_ind(), st.c_count.as<int64_t>(),
+                           st.c_row.as<int32_t>(), st.missing.as<int32_t>(), st.kparts,
+                           st.pcount.as<int64_t>());
+    }
     BSMM_TRY(launch_check("stack_count"));
     if (st.kparts == 1) return BSMM_OK;
     hipLaunchKernelGGL(k_part_offsets, dim3(grid_of(nnzb, 256)), dim3(256), 0, s, nnzb, st.kparts,
@@ -541,7 +620,20 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     for (int cl = 0; cl < ncl; ++cl)
         if (st.class_begin[cl + 1] > st.class_begin[cl]) st.class_active[cl] = 1;
     BSMM_TRY(scan_exclusive_i64(run_cnt.as<int64_t>(), st.run_ptr.as<int64_t>(), st.n_runs, s));
-    if (nprod > 0) {
+    if (nprod > 0 && nbc > kMaxStackCols) {
+        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
+        DevBuf cur;
+        BSMM_TRY(cur.reserve(sizeof(int64_t) * nblk * st.kparts, s));
+        BSMM_TRY(fill_zero(cur.as<double>(), nblk * st.kparts, s));
+        hipLaunchKernelGGL(k_stack_fill_wide, dim3(grid_rows(r1 - r0), st.kparts), dim3(256), 0, s, r0, r1,
+                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), c0, A->d_row_ptr(),
+                           A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(), B->d_col_ind(),
+                           B->d_blk_off(), B->d_rbs(), C->d_row_ptr(), C->d_col_ind(),
+                           (const int64_t *)st.run_of_c.as<int64_t>(),
+                           (const int64_t *)st.run_ptr.as<int64_t>(), cur.as<int64_t>(),
+                           st.prods.as<ulonglong2>());
+        BSMM_TRY(launch_check("stack_fill_wide"));
+    } else if (nprod > 0) {
         BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
         // LDS: the column map, then per slot a 64-bit next position (rows of
         // at most cap slots) or a 32-bit count; at most 64 KB.

@@ -268,16 +268,31 @@ def _tall_skinny_sparse(seed):
     return make_matrix(rng, ms, ks, 0.5), make_matrix(rng, ks, ns, 0.5)
 
 
-@pytest.mark.parametrize("workload", ["banded", "tall_skinny"])
+def _wide_c(seed, nbr, nbk, occ_a, occ_b, nbc=9000):
+    """C with more block columns (9000, sizes 1-3) than the stack builder's
+    LDS column map holds (8192): the count and fill phases search C's rows
+    in global memory instead."""
+    rng = rng_of(seed)
+    sizes = np.array([1, 2, 3], np.int32)
+    ms, ks, ns = (rng.choice(sizes, size=x) for x in (nbr, nbk, nbc))
+    return make_matrix(rng, ms, ks, occ_a), make_matrix(rng, ks, ns, occ_b)
+
+
+@pytest.mark.parametrize("workload", ["banded", "tall_skinny", "wide", "wide_tall_skinny"])
 def test_stack_contents_exact(workload):
     """The stacks hold exactly the (I,K,J) products of the block patterns,
     runs ordered by class then C block, K ascending inside a run (also when
-    long A rows are counted and filled in parts by several workgroups)."""
+    long A rows are counted and filled in parts by several workgroups, and
+    when C has more block columns than the LDS column map holds)."""
     b = lib()
     if workload == "banded":
         A, B = banded_uneven(seed=9, occupancy=0.1, target=600)
-    else:
+    elif workload == "tall_skinny":
         A, B = _tall_skinny_sparse(seed=19)
+    elif workload == "wide":
+        A, B = _wide_c(seed=23, nbr=40, nbk=300, occ_a=0.1, occ_b=0.02)
+    else:
+        A, B = _wide_c(seed=29, nbr=3, nbk=700, occ_a=0.5, occ_b=0.01, nbc=8500)
     R = orc.multiply(1.0, A, B, 0.0)
     MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
     MC = b.Matrix.from_blocks(R)
