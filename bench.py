@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP64-equiv GFLOP/s of local C+=A·B, tuned/emulated vs plain, rel err≤1e-12"
 PEAK_FP64_TFLOPS = 78.6       # MI355X FP64 matrix and vector peak
+PEAK_HBM_GBS = 8000.0         # MI355X HBM3E bandwidth
 PEAK_FP32_TFLOPS = 157.3      # MI355X FP32 matrix and vector peak
 HEADLINE_OCC = 0.30
 HEADLINE_EPS = 1e-10
@@ -111,6 +112,20 @@ def mfma_padding(A, B):
     F = 2.0 * float(np.sum(kbs * a_m * b_n))
     issued = 2.0 * float(np.sum(16 * np.ceil(kbs / 16) * a_mp * b_np))
     return F, issued
+
+
+def stream_bytes(A, B):
+    """Bytes of the products' operands read once per product, with no reuse
+    between products: sum over the block products of 8 (m k + k n), summed
+    per K as in mfma_padding."""
+    rbs, kbs, cbs = (np.asarray(x, np.int64) for x in (A.rbs, A.cbs, B.cbs))
+    a_rows = np.repeat(np.arange(len(rbs)), np.diff(A.row_ptr))
+    a_cnt = np.bincount(A.col_ind, minlength=len(kbs))
+    a_m = np.bincount(A.col_ind, weights=rbs[a_rows], minlength=len(kbs))
+    b_rows = np.repeat(np.arange(len(kbs)), np.diff(B.row_ptr))
+    b_cnt = np.bincount(b_rows, minlength=len(kbs))
+    b_n = np.bincount(b_rows, weights=cbs[B.col_ind], minlength=len(kbs))
+    return 8.0 * float(np.sum(kbs * (a_m * b_cnt + a_cnt * b_n)))
 
 
 def rows_slice(torch, M, r0, r1):
@@ -207,6 +222,9 @@ def headline(bsmm, torch, stream, args):
     MA.close()
     MB.close()
     res["F"], res["issued"] = F, issued
+    res["stream_bytes"] = stream_bytes(A, B)
+    # Algorithmic bytes: A and B read once, the filtered C written once.
+    res["b_alg"] = 8.0 * (A.data.size + B.data.size + MC.info()[3])
     res["A"], res["B"] = A, B
     return res
 
@@ -753,7 +771,17 @@ def main():
                 "launches": tuned["stack_launches"],
                 "traffic": tr.get("bytes_per_launch") if tr else None,
                 "mfma_issued_over_algorithmic": round(res["issued"] / F, 4),
-                "mfma_issue_frac": round(res["issued"] / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4)}
+                "mfma_issue_frac": round(res["issued"] / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                # The roofline time max(F / FP64 peak, B_alg / HBM) with A and B
+                # read once; and the streaming bound with no reuse between
+                # products (operands read once per product), the bound this
+                # kernel's design can reach.
+                "b_alg_bytes": res["b_alg"],
+                "t_roof_ms": round(max(F / (PEAK_FP64_TFLOPS * 1e12), res["b_alg"] / (PEAK_HBM_GBS * 1e9)) * 1e3,
+                                   3),
+                "no_reuse_stream_bytes": res["stream_bytes"],
+                "no_reuse_stream_tbs": round(res["stream_bytes"] / (k_ms * 1e-3) / 1e12, 3),
+                "no_reuse_stream_frac": round(res["stream_bytes"] / (PEAK_HBM_GBS * 1e9) / (k_ms * 1e-3), 4)}
 
     peaks = bsmm.bsmm_measure_peaks()
     peaks = {"fp64_mfma_tflops": round(peaks["fp64_mfma"], 2), "fp32_mfma_tflops": round(peaks["fp32_mfma"], 2),
