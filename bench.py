@@ -369,13 +369,24 @@ def extras_banded(bsmm, torch, stream, args, orc, threads):
         U, V = banded_uneven(seed=0, occupancy=occ, target=50000)
         MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
         r = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
+        sb = stream_bytes(U, V)
+        r["no_reuse_stream_bytes"] = sb
         for kern in ("plain", "tuned"):
             set_opts(bsmm, path="stack", stack_kernel=kern)
             MW = bsmm.Matrix.empty(U.rbs, V.cbs)
+            bsmm.bsmm_set_option("time_kernels", "1")
+            bsmm.bsmm_kernel_times(reset=True)
             t = timed_calls(torch, lambda: bsmm.multiply(1.0, MU, MV, 0.0, MW, HEADLINE_EPS, stream), 2,
                             args.reps)
+            _, _, s_ms, s_n = bsmm.bsmm_kernel_times(reset=True)
+            bsmm.bsmm_set_option("time_kernels", "0")
             st = bsmm.bsmm_last_stats()
             r[kern] = dict(t, gflops=gflops(st["flops"], t["median_ms"]))
+            # Stack kernel time per multiply (warm-up and timed calls alike)
+            # and the operand stream it reads against the HBM bandwidth.
+            k_ms = s_ms / (2 + args.reps)
+            r[kern]["stack_kernel_ms"] = round(k_ms, 4)
+            r[kern]["no_reuse_stream_frac"] = round(sb / (PEAK_HBM_GBS * 1e9) / (k_ms * 1e-3), 4)
             r["flops_per_multiply"] = st["flops"]
             r["products"] = st["n_products"]
             r["classes"] = st["n_classes"]
