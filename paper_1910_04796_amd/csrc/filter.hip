@@ -12,11 +12,20 @@ namespace {
 // FP64 for either element type).
 template <class T>
 __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *blk_off,
-                                                   const T *data, double eps2,
+                                                   const T *data, const double *pre, double eps2,
                                                    int64_t *keep, int64_t *keep_elems) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
         const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
+        const double given = pre ? pre[b] : -1.0;
+        if (given >= 0.0) {  // computed by the kernel that wrote the block
+            if (lane_id() == 0) {
+                const int64_t k = (given < eps2) ? 0 : 1;
+                keep[b] = k;
+                keep_elems[b] = k ? len : 0;
+            }
+            continue;
+        }
         // Four independent partial sums per lane keep four loads in flight.
         double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
         int64_t e = lane_id();
@@ -81,7 +90,8 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
 
 }  // namespace
 
-int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s) {
+int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s,
+                  const double *pre_norm2) {
     *nnzb_after = C->nnzb;
     if (!(eps > 0.0) || C->nnzb == 0) return BSMM_OK;
     const int64_t nnzb = C->nnzb;
@@ -92,11 +102,13 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     BSMM_TRY(epos.reserve(sizeof(int64_t) * (nnzb + 1), s));
     if (C->dtype == BSMM_F32)
         hipLaunchKernelGGL(k_norm_keep<float>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
-                           C->d_blk_off(), (const float *)C->d_raw(), eps * eps, keep.as<int64_t>(),
+                           C->d_blk_off(), (const float *)C->d_raw(), pre_norm2, eps * eps,
+                           keep.as<int64_t>(),
                            kel.as<int64_t>());
     else
         hipLaunchKernelGGL(k_norm_keep<double>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
-                           C->d_blk_off(), (const double *)C->d_raw(), eps * eps, keep.as<int64_t>(),
+                           C->d_blk_off(), (const double *)C->d_raw(), pre_norm2, eps * eps,
+                           keep.as<int64_t>(),
                            kel.as<int64_t>());
     BSMM_TRY(launch_check("norm_keep"));
     BSMM_TRY(scan_exclusive_i64(keep.as<int64_t>(), kpos.as<int64_t>(), nnzb, s));

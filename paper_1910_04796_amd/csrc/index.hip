@@ -226,6 +226,12 @@ __global__ __launch_bounds__(256) void k_fill_zero(double *p, int64_t n) {
         p[e] = 0.0;
 }
 
+__global__ __launch_bounds__(256) void k_fill_value(double *p, int64_t n, double v) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
+         e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
 __global__ __launch_bounds__(256) void k_fill_zero_u32(uint32_t *p, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n;
          e += (int64_t)gridDim.x * blockDim.x)
@@ -337,6 +343,12 @@ int fill_zero(double *p, int64_t n, hipStream_t s) {
     if (n <= 0) return BSMM_OK;
     hipLaunchKernelGGL(k_fill_zero, dim3(grid_of(n, 256, 16384)), dim3(256), 0, s, p, n);
     return launch_check("fill_zero");
+}
+
+int fill_value(double *p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return BSMM_OK;
+    hipLaunchKernelGGL(k_fill_value, dim3(grid_of(n, 256, 16384)), dim3(256), 0, s, p, n, v);
+    return launch_check("fill_value");
 }
 
 int fill_zero_bytes(void *p, size_t bytes, hipStream_t s) {

@@ -232,6 +232,7 @@ int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *
 int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hipStream_t s);
 int fill_zero(double *p, int64_t n, hipStream_t s);
 int fill_zero_bytes(void *p, size_t bytes, hipStream_t s);
+int fill_value(double *p, int64_t n, double v, hipStream_t s);
 
 // ---------------------------------------------------------------- stacks
 // A product entry keeps A's element offset in 48 bits and k in 16 bits.
@@ -340,7 +341,16 @@ struct SmmArgs {
     unsigned long long *next;
     int sched_mode;
     int sched_chunk;        // schedule entries taken per wave at a time
+    // Scheduled kernel, when the multiply filters: squared Frobenius norm of
+    // every finished C block, norm2[run_cblk[r]] (run_cblk: C block of run r).
+    double *norm2;
+    const int64_t *run_cblk;
 };
+// Squared block norms the scheduled kernel writes for the filter during the
+// current multiply on this thread (nullptr: none); set around the numeric
+// phase by the multiply.
+void set_norm_sink(double *norm2);
+double *norm_sink();
 // A planned launch: kernel, shape-dependent arguments, block size, LDS.
 struct SmmLaunch {
     void *fn = nullptr;
@@ -417,7 +427,10 @@ int emul_multiply(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s 
 int64_t emul_chunk(int S);
 
 // ---------------------------------------------------------------- filter
-int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s);
+// pre_norm2 (nullable): squared block norms already computed (negative:
+// not computed), used in place of reading those blocks.
+int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s,
+                  const double *pre_norm2 = nullptr);
 
 // ------------------------------------------------------- fixed pattern
 // C <- beta*C + alpha*A*B into C's existing pattern and buffers, with every

@@ -175,8 +175,16 @@ struct Plan {
     int path = 0;
     Stacks st;
     StackExec ex;
+    DevBuf norm2;  // squared block norms the planned launches write (filtering multiplies)
 };
 void free_plan(Plan *p) { delete p; }
+
+// Sets the norm sink for the numeric phase of one multiply and clears it
+// again on every way out.
+struct NormSinkScope {
+    explicit NormSinkScope(double *p) { set_norm_sink(p); }
+    ~NormSinkScope() { set_norm_sink(nullptr); }
+};
 
 // Limits of the stack path, checked on the host before any work is queued:
 // a product entry carries k in 16 bits and the count and fill phases map
@@ -275,9 +283,16 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
     const bool hit = o.plan_cache && pl && pl->A == A && pl->B == B && pl->va == A->version &&
                      pl->vb == B->version && pl->vc == C->version && pl->alpha == alpha &&
                      pl->beta == beta && pl->key == plan_key(o);
+    // Filtering stack multiplies: the scheduled kernel writes the squared
+    // norms of the blocks it finishes, the filter reads the rest.
+    const double *pre_norm2 = nullptr;
     if (hit) {
         // Same patterns, buffers and options as the planned multiply: C's
         // pattern already holds the product, the stacks are still valid.
+        if (eps > 0.0 && pl->norm2.p) {
+            BSMM_TRY(fill_value(pl->norm2.as<double>(), C->nnzb, -1.0, s));
+            pre_norm2 = pl->norm2.as<double>();
+        }
         BSMM_TRY(numeric(pl->path, A, B, C, alpha, beta, o, pl->st, pl->ex, true,
                          &stt.n_row_panels, s));
         stt.path = pl->path;
@@ -304,8 +319,20 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         const int path = (alpha == 0.0 || tot.nprod == 0) ? 0 : o.path == 3 ? 3 : dense ? 2 : 1;
         auto *p = new Plan();
         p->st.n_prod = tot.nprod;
-        const int status = numeric(path, A, B, C, alpha, beta, o, p->st, p->ex, false,
-                                   &stt.n_row_panels, s);
+        if (eps > 0.0 && path == 1 && C->nnzb > 0) {
+            int st = p->norm2.reserve(sizeof(double) * (size_t)C->nnzb, s);
+            if (st == BSMM_OK) st = fill_value(p->norm2.as<double>(), C->nnzb, -1.0, s);
+            if (st != BSMM_OK) {
+                delete p;
+                return st;
+            }
+            pre_norm2 = p->norm2.as<double>();
+        }
+        int status;
+        {
+            NormSinkScope sink(const_cast<double *>(pre_norm2));
+            status = numeric(path, A, B, C, alpha, beta, o, p->st, p->ex, false, &stt.n_row_panels, s);
+        }
         if (status != BSMM_OK) {
             delete p;
             return status;
@@ -329,11 +356,17 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
             p->path = path;
             C->plan = p;
         } else {
+            // The norms outlive the plan until the filter has read them.
+            DevBuf norms = std::move(p->norm2);
             delete p;
+            int64_t after = C->nnzb;
+            BSMM_TRY(filter_blocks(C, eps, &after, s, pre_norm2));
+            stt.c_nnzb_after = after;
+            return BSMM_OK;
         }
     }
     int64_t after = C->nnzb;
-    BSMM_TRY(filter_blocks(C, eps, &after, s));
+    BSMM_TRY(filter_blocks(C, eps, &after, s, pre_norm2));
     stt.c_nnzb_after = after;
     return BSMM_OK;
 }

@@ -232,6 +232,34 @@ __device__ __forceinline__ void mfma_store(T *c, int m, int n,
             }
 }
 
+// mfma_store (C = beta C + alpha acc) that also returns, on every lane,
+// the squared Frobenius norm of the stored block (summed in FP64: each
+// lane's elements in order, then across the wave in a fixed order).
+template <class T, int MT, int NT>
+__device__ __forceinline__ double mfma_store_sumsq(T *c, int m, int n,
+                                                   const typename Mfma<T>::acc_t (&acc)[MT][NT],
+                                                   T alpha, T beta) {
+    const int lane = lane_id();
+    const int lr = lane & 15, lk = lane >> 4;
+    double ss = 0.0;
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = 16 * i + Mfma<T>::row(e, lk), col = 16 * j + lr;
+                if (row < m && col < n) {
+                    T *dst = c + (int64_t)col * m + row;
+                    const T prod = alpha * acc[i][j][e];
+                    const T v = (beta == T(0)) ? prod : fma(beta, *dst, prod);
+                    *dst = v;
+                    ss = fma((double)v, (double)v, ss);
+                }
+            }
+    return wave_sum(ss);
+}
+
 template <class T, int MT, int NT>
 __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
@@ -268,8 +296,10 @@ template <class T, int MT, int NT>
 __device__ __forceinline__ void sched_run(const SmmArgs &p, int64_t r, int m, int n) {
     typename Mfma<T>::acc_t acc[MT][NT];
     mfma_products<T, MT, NT>(p, m, n, p.run_ptr[r], p.run_ptr[r + 1], acc);
-    mfma_store<T, MT, NT>(static_cast<T *>(p.C) + p.run_coff[r], m, n, acc, false, (T)p.alpha,
-                          (T)p.beta);
+    // One store path: the norm is summed whether or not the filter wants it.
+    const double ss = mfma_store_sumsq<T, MT, NT>(static_cast<T *>(p.C) + p.run_coff[r], m, n, acc,
+                                                  (T)p.alpha, (T)p.beta);
+    if (p.norm2 && lane_id() == 0) p.norm2[p.run_cblk[r]] = ss;
 }
 
 constexpr int kXcds = 8;
@@ -390,6 +420,8 @@ template <class T> SmmKernel kernel_for(int tm, int tn) {
     }
 }
 
+thread_local double *t_norm_sink = nullptr;
+
 bool is_sched_kernel(const void *fn) {
     return fn == (const void *)k_smm_mfma_sched<double> || fn == (const void *)k_smm_mfma_sched<float>;
 }
@@ -397,6 +429,10 @@ bool is_sched_kernel(const void *fn) {
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per workgroup
 
 }  // namespace
+
+void set_norm_sink(double *norm2) { t_norm_sink = norm2; }
+double *norm_sink() { return t_norm_sink; }
+
 
 // Plain parameter rule: the smallest square register tile T (1..8) for
 // which ceil(m/T) * ceil(n/T) <= 64 lanes (blocks above 64 use T = 8 and
@@ -689,6 +725,8 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
         L.args.n_sched = st.n_sched;
         L.args.next = st.sched_next.as<unsigned long long>();
         L.args.sched_mode = options().stack_sched;
+        L.args.norm2 = norm_sink();
+        L.args.run_cblk = st.run_cblk.as<int64_t>();
         // About 32 products per counter update: runs of one product go
         // 16 at a time, runs of 32 or more one at a time.
         const int64_t mean_len = std::max<int64_t>(1, sched_prods / sched_runs);

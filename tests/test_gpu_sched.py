@@ -105,3 +105,44 @@ def test_sched_short_runs_chunked_and_small_fallback():
     X, st = _run(A, B, tile=32, sched="dynamic", params="16 16 0 4")
     assert st["n_runs"] < 4096 and st["n_sched_runs"] == 0
     check_against_oracle(X, R, TOL)
+
+
+def _eps_in_gap(R):
+    """A threshold that drops about half of the blocks of R, in the widest
+    relative gap between neighbouring squared block norms there."""
+    s = np.sort(orc.block_sumsq(R))
+    lo, hi = len(s) * 2 // 5, len(s) * 3 // 5
+    gaps = s[lo + 1:hi + 1] / np.maximum(s[lo:hi], 1e-300)
+    i = lo + int(np.argmax(gaps))
+    assert s[i + 1] > s[i] * (1 + 1e-9)
+    return float(np.sqrt(np.sqrt(s[i] * s[i + 1])))
+
+
+@pytest.mark.parametrize("beta", [0.0, 0.75])
+def test_sched_norms_feed_the_filter(beta):
+    """With a filter, the scheduled kernel hands the squared norms of the
+    blocks it writes to the filter (blocks of other classes are measured by
+    the filter itself): same kept blocks and bits as the per-class launches,
+    whose blocks the filter measures; also through plan-cache replays with
+    a filter that keeps every block."""
+    b = lib()
+    A, B = banded_uneven(seed=61, occupancy=0.3, target=2500)
+    Cin = make_matrix(rng_of(62), A.rbs, B.cbs, 0.4) if beta else None
+    eps = _eps_in_gap(orc.multiply(1.0, A, B, beta, Cin))
+    R = orc.multiply(1.0, A, B, beta, Cin, filter_eps=eps)
+    Xc, stc = _run(A, B, beta=beta, Cin=Cin, eps=eps, tile=0, params="16 16 0 2")
+    Xs, sts = _run(A, B, beta=beta, Cin=Cin, eps=eps, tile=8, sched="dynamic", params="16 16 0 2")
+    assert sts["n_sched_runs"] == sts["n_runs"] and 0 < sts["c_nnzb_after"] < sts["c_nnzb_before"]
+    check_against_oracle(Xs, Xc, 0.0)
+    check_against_oracle(Xs, R, TOL)
+    if beta:
+        return
+    # A threshold below every norm keeps C's pattern, so the repeats replay
+    # the plan, whose launches write the norms into the plan's buffer.
+    b.bsmm_set_option("plan_cache", "1")
+    try:
+        Xr, st = _run(A, B, eps=1e-150, tile=8, sched="dynamic", params="16 16 0 2", repeat=3)
+    finally:
+        b.bsmm_set_option("plan_cache", "0")
+    assert st["c_nnzb_after"] == st["c_nnzb_before"]
+    check_against_oracle(Xr, orc.multiply(1.0, A, B, 0.0), TOL)
