@@ -128,6 +128,59 @@ def stream_bytes(A, B):
     return 8.0 * float(np.sum(kbs * (a_m * b_cnt + a_cnt * b_n)))
 
 
+def block_norms(M, chunk=1 << 26):
+    """Frobenius norm of every block of a host block-CSR matrix (squares
+    summed per block, in pieces of about `chunk` elements)."""
+    sizes = np.asarray(M.rbs, np.int64)[np.repeat(np.arange(len(M.rbs)), np.diff(M.row_ptr))] * \
+        np.asarray(M.cbs, np.int64)[np.asarray(M.col_ind)]
+    start = np.concatenate([[0], np.cumsum(sizes)])
+    out = np.empty(len(sizes))
+    data = np.asarray(M.data)
+    b0 = 0
+    while b0 < len(sizes):
+        b1 = int(np.searchsorted(start, start[b0] + chunk, side="right"))
+        b1 = min(max(b1 - 1, b0 + 1), len(sizes))
+        seg = data[start[b0]:start[b1]]
+        out[b0:b1] = np.add.reduceat(seg * seg, start[b0:b1] - start[b0])
+        b0 = b1
+    return np.sqrt(out)
+
+
+def screened_work(A, B, alpha, eps):
+    """The work of the C blocks that the library's norm-bound screen keeps
+    (option "prescreen": a block stays unless |alpha| sum_K ||A_IK||
+    ||B_KJ|| grown by the rounding margin is below eps), estimated on the
+    host with dense block-row x block-column matrices: products, flops,
+    MFMA-issued flops (m, n, k rounded up to 16) and the no-reuse operand
+    stream of those blocks, and the number of blocks screened."""
+    nbr, nbk, nbc = len(A.rbs), len(A.cbs), len(B.cbs)
+    a_rows = np.repeat(np.arange(nbr), np.diff(A.row_ptr))
+    b_rows = np.repeat(np.arange(nbk), np.diff(B.row_ptr))
+    MA = np.zeros((nbr, nbk))
+    MA[a_rows, A.col_ind] = 1.0
+    MB = np.zeros((nbk, nbc))
+    MB[b_rows, B.col_ind] = 1.0
+    NA = np.zeros((nbr, nbk))
+    NA[a_rows, A.col_ind] = block_norms(A)
+    NB = np.zeros((nbk, nbc))
+    NB[b_rows, B.col_ind] = block_norms(B)
+    bound = abs(alpha) * (NA @ NB)
+    del NA, NB
+    margin = max(1e-6, 4.0 * (float(np.sum(A.cbs)) + 4.0) * 2.0 ** -53)
+    keep = ~((bound * (1.0 + margin) < eps) & (bound < 1e150))
+    m, k, n = (np.asarray(x, np.float64) for x in (A.rbs, A.cbs, B.cbs))
+    pad = lambda x: 16.0 * np.ceil(x / 16.0)
+    P = MA @ MB
+    KP = (MA * k) @ MB
+    KPp = (MA * pad(k)) @ MB
+    reached = P > 0
+    return {"products_run": int(round(P[keep].sum())),
+            "flops_run": 2.0 * float((np.outer(m, n) * KP)[keep].sum()),
+            "issued_run": 2.0 * float((np.outer(pad(m), pad(n)) * KPp)[keep].sum()),
+            "stream_run": 8.0 * float(((m[:, None] + n[None, :]) * KP)[keep].sum()),
+            "screened_blocks": int((reached & ~keep).sum())}
+
+
 def rows_slice(torch, M, r0, r1):
     """Block rows [r0, r1) of a matrix on the device as a host block-CSR
     (the data go through a device buffer, only the rows reach the host)."""
@@ -218,11 +271,25 @@ def headline(bsmm, torch, stream, args):
     res["plain"] = dict(t, gflops=gflops(F, t["median_ms"]))
     log(f"plain: {t['median_ms']:.3f} ms (median of {args.plain_reps})")
     res["C_plain"] = MP
+    # The same tuned multiply with the norm-bound screen off: every block of
+    # the product pattern is formed and the filter alone drops.
+    set_opts(bsmm, stack_kernel="tuned")
+    bsmm.bsmm_set_option("prescreen", "0")
+    MN = bsmm.Matrix.empty(A.rbs, B.cbs)
+    t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MN, HEADLINE_EPS, stream), 1,
+                    args.plain_reps)
+    bsmm.bsmm_set_option("prescreen", "1")
+    res["tuned_without_prescreen"] = dict(t, gflops=gflops(F, t["median_ms"]))
+    log(f"tuned without the screen: {t['median_ms']:.3f} ms (median of {args.plain_reps})")
+    MN.close()
     set_opts(bsmm, path="auto", stack_kernel="plain")
     MA.close()
     MB.close()
     res["F"], res["issued"] = F, issued
     res["stream_bytes"] = stream_bytes(A, B)
+    res["screen"] = screened_work(A, B, 1.0, HEADLINE_EPS)
+    log(f"screen (host estimate): {res['screen']['screened_blocks']} blocks, "
+        f"{res['screen']['products_run']} of {st['n_products']} products run (library: {st['n_products_run']})")
     # Algorithmic bytes: A and B read once, the filtered C written once.
     res["b_alg"] = 8.0 * (A.data.size + B.data.size + MC.info()[3])
     res["A"], res["B"] = A, B
@@ -369,8 +436,10 @@ def extras_banded(bsmm, torch, stream, args, orc, threads):
         U, V = banded_uneven(seed=0, occupancy=occ, target=50000)
         MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
         r = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
-        sb = stream_bytes(U, V)
+        scr = screened_work(U, V, 1.0, HEADLINE_EPS)
+        sb = scr["stream_run"]
         r["no_reuse_stream_bytes"] = sb
+        r["no_reuse_stream_bytes_all_products"] = stream_bytes(U, V)
         for kern in ("plain", "tuned"):
             set_opts(bsmm, path="stack", stack_kernel=kern)
             MW = bsmm.Matrix.empty(U.rbs, V.cbs)
@@ -389,6 +458,8 @@ def extras_banded(bsmm, torch, stream, args, orc, threads):
             r[kern]["no_reuse_stream_frac"] = round(sb / (PEAK_HBM_GBS * 1e9) / (k_ms * 1e-3), 4)
             r["flops_per_multiply"] = st["flops"]
             r["products"] = st["n_products"]
+            r["products_run"] = st["n_products_run"]
+            r["screened_c_blocks"] = st["n_screened"]
             r["classes"] = st["n_classes"]
             if orc is not None and kern == "tuned":
                 nb = len(U.rbs)
@@ -774,15 +845,21 @@ def main():
     st = res["stats"]
     tuned = res["tuned"]
     k_ms = tuned["stack_kernel_ms"]
-    achieved = F / (k_ms * 1e-3) / 1e12
+    scr = res["screen"]
+    # The kernel's own rate counts the products it ran (the screen skips the
+    # products of blocks that the filter would drop); `value` counts every
+    # product of A*B, the work of the operation whose result it delivers.
+    F_run = scr["flops_run"]
+    achieved = F_run / (k_ms * 1e-3) / 1e12
     tr = profile_json("smm_sched_banded30_traffic.json", "paper_1910_04796_amd/csrc/smm.hip")
     roofline = {"bound": "mfma", "kernel": "k_smm_mfma_sched (tuned stack launch)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "kernel_ms": k_ms,
                 "launches": tuned["stack_launches"],
                 "traffic": tr.get("bytes_per_launch") if tr else None,
-                "mfma_issued_over_algorithmic": round(res["issued"] / F, 4),
-                "mfma_issue_frac": round(res["issued"] / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+                "flops_run": F_run,
+                "mfma_issued_over_algorithmic": round(scr["issued_run"] / F_run, 4),
+                "mfma_issue_frac": round(scr["issued_run"] / (k_ms * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
                 # The roofline time max(F / FP64 peak, B_alg / HBM) with A and B
                 # read once; and the streaming bound with no reuse between
                 # products (operands read once per product), the bound this
@@ -790,9 +867,10 @@ def main():
                 "b_alg_bytes": res["b_alg"],
                 "t_roof_ms": round(max(F / (PEAK_FP64_TFLOPS * 1e12), res["b_alg"] / (PEAK_HBM_GBS * 1e9)) * 1e3,
                                    3),
-                "no_reuse_stream_bytes": res["stream_bytes"],
-                "no_reuse_stream_tbs": round(res["stream_bytes"] / (k_ms * 1e-3) / 1e12, 3),
-                "no_reuse_stream_frac": round(res["stream_bytes"] / (PEAK_HBM_GBS * 1e9) / (k_ms * 1e-3), 4)}
+                "no_reuse_stream_bytes": scr["stream_run"],
+                "no_reuse_stream_bytes_all_products": res["stream_bytes"],
+                "no_reuse_stream_tbs": round(scr["stream_run"] / (k_ms * 1e-3) / 1e12, 3),
+                "no_reuse_stream_frac": round(scr["stream_run"] / (PEAK_HBM_GBS * 1e9) / (k_ms * 1e-3), 4)}
 
     peaks = bsmm.bsmm_measure_peaks()
     peaks = {"fp64_mfma_tflops": round(peaks["fp64_mfma"], 2), "fp32_mfma_tflops": round(peaks["fp32_mfma"], 2),
@@ -848,6 +926,8 @@ def main():
                    "path": "tuned stacks: tuning database parameters, classes on the scheduled FP64 MFMA "
                            "small-block kernel in one hipGraph",
                    "flops_per_step": F, "products": st["n_products"], "runs": st["n_runs"],
+                   "products_run": st["n_products_run"], "flops_run": F_run,
+                   "screened_c_blocks": st["n_screened"],
                    "classes": st["n_classes"], "c_blocks_before_filter": st["c_nnzb_before"],
                    "c_blocks_after_filter": st["c_nnzb_after"]},
         "roofline": roofline,
@@ -857,6 +937,7 @@ def main():
         "rel_err_mode": f"sampled: block rows {sample[0]}..{sample[1] - 1}" if sample else None,
         "plain": dict(res["plain"], rel_err=rel_errs["plain"] if rel_errs else None),
         "tuned_speedup_vs_plain": round(res["plain"]["median_ms"] / ms, 3),
+        "tuned_without_prescreen": res["tuned_without_prescreen"],
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

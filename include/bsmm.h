@@ -227,6 +227,13 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
                  hipGraph).  Without hiprtc, or when a compilation fails,
                  the precompiled kernels run.  "0" (default): precompiled
                  kernels only
+   "prescreen"   "1" (default): a filtering multiply (filter_eps >= 1e-150)
+                 on the stack path leaves out of C's new pattern every
+                 block whose norm bound |alpha| sum_K ||A_IK||_F ||B_KJ||_F
+                 + |beta| ||C_IJ||_F, grown by a margin for rounding, lies
+                 below filter_eps, and skips its products: such blocks
+                 always fail the filter, so C is the same as with "0",
+                 which forms every block of the product pattern first
    "stack_sched" order in which the scheduled launch's waves take runs:
                  "dynamic" (default; a run counter, several short runs per
                  update) or "static" (fixed strides, numbered XCD by XCD)
@@ -267,19 +274,20 @@ const char *bsmm_last_error(void);
 
 /*
  * Facts about the last bsmm_multiply on the calling thread, for tests and
- * benchmarks: which path ran, how many block products and C-block runs the
- * stacks held, how many shape classes, the algorithmic FP64 flop count
- * (sum of 2*m*n*k over the block products), and the C block count before
- * and after the filter.
+ * benchmarks: which path ran, how many block products A*B has and how many
+ * were computed, how many C-block runs the stacks held, how many shape
+ * classes, the algorithmic FP64 flop count of A*B (sum of 2*m*n*k over its
+ * block products), the C blocks the norm-bound screen left out, and the C
+ * block count before and after the filter.
  */
 typedef struct bsmm_multiply_stats {
     int32_t path;          /* 1 = stack, 2 = dense (merged panels)          */
     int32_t n_classes;     /* shape classes (m, n) holding at least one run */
-    int64_t n_products;    /* block products (a, b, c) in the stacks        */
+    int64_t n_products;    /* block products (I, K, J) of A*B               */
     int64_t n_runs;        /* C blocks receiving at least one product       */
-    int64_t c_nnzb_before; /* C blocks before the filter                    */
+    int64_t c_nnzb_before; /* C blocks before the filter (after the screen) */
     int64_t c_nnzb_after;  /* C blocks after the filter                     */
-    double flops;          /* sum of 2*m*n*k over the block products        */
+    double flops;          /* sum of 2*m*n*k over the block products of A*B */
     int64_t n_row_panels;  /* stack path: C block-row panels the stacks were
                               built and run in (option "stack_panel"); 0 on
                               the other paths                               */
@@ -287,6 +295,11 @@ typedef struct bsmm_multiply_stats {
                               launch (tuned path, option "stack_tile")      */
     int64_t n_jit_classes; /* shape classes run on run-time compiled
                               kernels (tuned path, option "jit")            */
+    int64_t n_screened;    /* C blocks left out by the norm-bound screen
+                              (option "prescreen"); their products are
+                              not computed                                  */
+    int64_t n_products_run; /* block products computed (n_products less
+                              those of screened blocks; 0 on path 0)        */
 } bsmm_multiply_stats;
 int bsmm_last_stats(bsmm_multiply_stats *out);
 

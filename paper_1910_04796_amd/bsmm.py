@@ -59,7 +59,8 @@ class bsmm_multiply_stats(ctypes.Structure):
                 ("n_products", ctypes.c_int64), ("n_runs", ctypes.c_int64),
                 ("c_nnzb_before", ctypes.c_int64), ("c_nnzb_after", ctypes.c_int64),
                 ("flops", ctypes.c_double), ("n_row_panels", ctypes.c_int64),
-                ("n_sched_runs", ctypes.c_int64), ("n_jit_classes", ctypes.c_int64)]
+                ("n_sched_runs", ctypes.c_int64), ("n_jit_classes", ctypes.c_int64),
+                ("n_screened", ctypes.c_int64), ("n_products_run", ctypes.c_int64)]
 
 
 _lib.bsmm_create_matrix.argtypes = [_i32, _i32p, _i32, _i32p, _i64, _i64p, _i32p, _vp, ctypes.c_int,

@@ -88,7 +88,57 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
     }
 }
 
+// One wave per block: the block's Frobenius norm in FP64, for the norm
+// bound of the symbolic screen.  Away from the ends of the exponent range
+// it is summed as max|x| * sqrt(sum (x / max|x|)^2), so that no square
+// under- or overflows (relative rounding error below len * 2^-52); for
+// max|x| below 2^-900 or above 2^900 it is the upper bound
+// sqrt(len) * max|x|.  A NaN element gives NaN, an infinite one infinity.
+template <class T>
+__global__ __launch_bounds__(256) void k_block_norm(int64_t nnzb, const int64_t *blk_off,
+                                                    const T *data, double *out) {
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
+        const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
+        double mx = 0.0;
+        int nan = 0;
+        for (int64_t e = lane_id(); e < len; e += kWave) {
+            const double v = fabs((double)data[o + e]);
+            nan |= v != v;
+            mx = v > mx ? v : mx;
+        }
+        mx = wave_max(mx);
+        nan = __any(nan);
+        double nrm;
+        if (nan) {
+            nrm = __builtin_nan("");
+        } else if (mx == 0.0 || mx > 0x1p900 || mx < 0x1p-900) {
+            nrm = mx * sqrt((double)len);  // also 0 and infinity
+        } else {
+            const double r = 1.0 / mx;
+            double ss = 0.0;
+            for (int64_t e = lane_id(); e < len; e += kWave) {
+                const double v = (double)data[o + e] * r;
+                ss = fma(v, v, ss);
+            }
+            nrm = mx * sqrt(wave_sum(ss));
+        }
+        if (lane_id() == 0) out[b] = nrm;
+    }
+}
+
 }  // namespace
+
+int block_norms(const bsmm_matrix_s *M, double *d_out, hipStream_t s) {
+    if (M->nnzb == 0) return BSMM_OK;
+    if (M->dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_block_norm<float>, dim3(grid_of(M->nnzb, 4)), dim3(256), 0, s, M->nnzb,
+                           M->d_blk_off(), (const float *)M->d_raw(), d_out);
+    else
+        hipLaunchKernelGGL(k_block_norm<double>, dim3(grid_of(M->nnzb, 4)), dim3(256), 0, s, M->nnzb,
+                           M->d_blk_off(), (const double *)M->d_raw(), d_out);
+    return launch_check("block_norm");
+}
 
 int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t s,
                   const double *pre_norm2) {

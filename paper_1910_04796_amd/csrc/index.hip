@@ -155,6 +155,125 @@ __global__ __launch_bounds__(kRowThreads) void k_symbolic_fill(
     }
 }
 
+// ------------------------------------------------------ symbolic screen
+// A C block whose norm bound |alpha| sum_K ||A_IK|| ||B_KJ|| + |beta| ||C_IJ||
+// (Frobenius norms: triangle inequality and ||X Y|| <= ||X|| ||Y||) lies
+// below eps is certain to fail the filter, so it is left out of the pattern
+// and its products are never formed.  grow = 1 + margin, the margin
+// covering the rounding of the computed block (at most about n u relative
+// to the bound for n accumulated terms), of the norms and of the bound.
+// Bounds of 1e150 and above are kept (their squared norm could overflow),
+// and so are NaN and infinite ones.
+__device__ __forceinline__ bool screened_out(double bound, double eps, double grow) {
+    return bound * grow < eps && bound < 1e150;
+}
+
+// k_symbolic_count with the screen: per block row, the column bitmap and
+// the bound of every column in LDS; the kept columns go to bits (nwords
+// 32-bit words per row) for the fill, with the counts of the kept blocks,
+// of the screened ones and of the old C blocks screened.  Products and
+// flops count every (I,K,J) of A*B.
+__global__ __launch_bounds__(kRowThreads) void k_symbolic_count_screen(
+    int32_t nbr, int32_t nbc, const int64_t *a_rp, const int32_t *a_ci, const int64_t *b_rp,
+    const int32_t *b_ci, const int64_t *c_rp, const int32_t *c_ci, const int32_t *rbs,
+    const int32_t *kbs, const int32_t *cbs, const double *a_nrm, const double *b_nrm,
+    const double *c_nrm, double alpha_abs, double beta_abs, double eps, double grow, uint32_t *bits,
+    int64_t *row_nnz, int64_t *row_elems, int64_t *row_prod, double *row_flops,
+    int64_t *row_screened, int64_t *row_old_screened) {
+    extern __shared__ double bnd[];  // nbc bounds, then the bitmap
+    uint32_t *bm = reinterpret_cast<uint32_t *>(bnd + nbc);
+    __shared__ int64_t red_i[16];
+    __shared__ double red_d[16];
+    const int nwords = (nbc + 31) >> 5;
+    const int nw = blockDim.x / kWave;
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        for (int w = threadIdx.x; w < nwords; w += blockDim.x) bm[w] = 0u;
+        for (int j = threadIdx.x; j < nbc; j += blockDim.x) bnd[j] = 0.0;
+        __syncthreads();
+        if (c_rp)
+            for (int64_t p = c_rp[row] + threadIdx.x; p < c_rp[row + 1]; p += blockDim.x) {
+                const int32_t j = c_ci[p];
+                atomicOr(&bm[j >> 5], 1u << (j & 31));
+                if (c_nrm) atomicAdd(&bnd[j], beta_abs * c_nrm[p]);
+            }
+        int64_t np = 0;
+        double kn = 0.0;
+        for (int64_t pa = a_rp[row] + wave_id(); pa < a_rp[row + 1]; pa += nw) {
+            const int32_t kb = a_ci[pa];
+            const double k = (double)kbs[kb], na = alpha_abs * a_nrm[pa];
+            for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
+                const int32_t j = b_ci[q];
+                atomicOr(&bm[j >> 5], 1u << (j & 31));
+                atomicAdd(&bnd[j], na * b_nrm[q]);
+                np += 1;
+                kn += k * (double)cbs[j];
+            }
+        }
+        __syncthreads();
+        int64_t cnt = 0, cols = 0, scr = 0, old_scr = 0;
+        for (int w = threadIdx.x; w < nwords; w += blockDim.x) {
+            const uint32_t all = bm[w];
+            uint32_t keep = all, rest = all;
+            while (rest) {
+                const int b = __ffs(rest) - 1;
+                rest &= rest - 1;
+                const int j = (w << 5) + b;
+                if (screened_out(bnd[j], eps, grow)) keep &= ~(1u << b);
+                else cols += cbs[j];
+            }
+            cnt += __popc(keep);
+            scr += __popc(all) - __popc(keep);
+            bits[(int64_t)row * nwords + w] = keep;
+        }
+        if (c_rp)
+            for (int64_t p = c_rp[row] + threadIdx.x; p < c_rp[row + 1]; p += blockDim.x)
+                if (screened_out(bnd[c_ci[p]], eps, grow)) old_scr += 1;
+        cnt = block_sum(cnt, red_i);
+        cols = block_sum(cols, red_i);
+        scr = block_sum(scr, red_i);
+        old_scr = block_sum(old_scr, red_i);
+        np = block_sum(np, red_i);
+        kn = block_sum(kn, red_d);
+        if (threadIdx.x == 0) {
+            const int64_t m = rbs[row];
+            row_nnz[row] = cnt;
+            row_elems[row] = m * cols;
+            row_prod[row] = np;
+            row_flops[row] = 2.0 * (double)m * kn;
+            row_screened[row] = scr;
+            row_old_screened[row] = old_scr;
+        }
+        __syncthreads();  // bounds and bitmap are cleared for the next row
+    }
+}
+
+// The kept columns of every row (bits of k_symbolic_count_screen), in
+// ascending order.
+__global__ __launch_bounds__(kRowThreads) void k_symbolic_fill_bits(int32_t nbr, int32_t nwords,
+                                                                    const uint32_t *bits,
+                                                                    const int64_t *new_rp,
+                                                                    int32_t *new_ci) {
+    __shared__ int64_t red[16];
+    for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
+        int64_t out = new_rp[row];
+        for (int w0 = 0; w0 < nwords; w0 += blockDim.x) {
+            const int w = w0 + threadIdx.x;
+            const uint32_t word = w < nwords ? bits[(int64_t)row * nwords + w] : 0u;
+            int64_t total;
+            const int64_t pos = out + block_exclusive_scan((int64_t)__popc(word), red, &total);
+            uint32_t b = word;
+            int64_t k = 0;
+            while (b) {
+                const int bit = __ffs(b) - 1;
+                b &= b - 1;
+                new_ci[pos + k] = (w << 5) + bit;
+                ++k;
+            }
+            out += total;
+        }
+    }
+}
+
 __global__ __launch_bounds__(256) void k_full_pattern(int32_t nbr, int32_t nbc, int64_t *rp,
                                                       int32_t *ci, int64_t *row_elems,
                                                       const int32_t *rbs, int64_t ncols) {
@@ -300,6 +419,35 @@ int symbolic_fill(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_mat
                        has_c ? C->d_row_ptr() : nullptr, has_c ? C->d_col_ind() : nullptr,
                        B->d_rbs(), B->d_cbs(), d_new_row_ptr, d_new_col_ind);
     return launch_check("symbolic_fill");
+}
+
+int symbolic_count_screen(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                          const ScreenNorms &sn, uint32_t *d_bits, int64_t *d_row_nnz,
+                          int64_t *d_row_elems, int64_t *d_row_prod, double *d_row_flops,
+                          int64_t *d_row_screened, int64_t *d_row_old_screened, hipStream_t s) {
+    if (A->nbr == 0) return BSMM_OK;
+    const int32_t nbc = B->nbc;
+    if (nbc > kScreenMaxCols) {
+        set_error(BSMM_ENOTSUP, "symbolic screen: more than %d block columns", kScreenMaxCols);
+        return BSMM_ENOTSUP;
+    }
+    const size_t lds = sizeof(double) * (size_t)nbc + sizeof(uint32_t) * (size_t)((nbc + 31) / 32 + 1);
+    const bool has_c = C && C->nnzb > 0;
+    hipLaunchKernelGGL(k_symbolic_count_screen, dim3(grid_rows(A->nbr)), dim3(kRowThreads), lds, s,
+                       A->nbr, nbc, A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
+                       has_c ? C->d_row_ptr() : nullptr, has_c ? C->d_col_ind() : nullptr,
+                       A->d_rbs(), B->d_rbs(), B->d_cbs(), sn.a, sn.b, has_c ? sn.c : nullptr,
+                       sn.alpha_abs, sn.beta_abs, sn.eps, 1.0 + sn.margin, d_bits, d_row_nnz, d_row_elems,
+                       d_row_prod, d_row_flops, d_row_screened, d_row_old_screened);
+    return launch_check("symbolic_count_screen");
+}
+
+int symbolic_fill_bits(int32_t nbr, int32_t nbc, const uint32_t *d_bits, const int64_t *d_new_row_ptr,
+                       int32_t *d_new_col_ind, hipStream_t s) {
+    if (nbr == 0) return BSMM_OK;
+    hipLaunchKernelGGL(k_symbolic_fill_bits, dim3(grid_rows(nbr)), dim3(kRowThreads), 0, s, nbr,
+                       (nbc + 31) / 32, d_bits, d_new_row_ptr, d_new_col_ind);
+    return launch_check("symbolic_fill_bits");
 }
 
 int full_pattern(int32_t nbr, int32_t nbc, int64_t ncols, int64_t *d_row_ptr,

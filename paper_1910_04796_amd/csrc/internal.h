@@ -62,6 +62,7 @@ struct Options {
     int jit = 0;           // tuned path: run-time compiled kernels for classes of one product depth
     int stack_tile = 32;   // tuned path: > 0 runs MFMA classes in one launch, tiles of this many blocks
     int stack_sched = 1;   // scheduled kernel: 0 static XCD-aware striding, 1 dynamic run counter
+    int prescreen = 1;     // stack path with eps > 0: leave out C blocks whose norm bound is below eps
 };
 Options &options();
 
@@ -214,7 +215,26 @@ int build_block_offsets(const int32_t *d_rbs, const int32_t *d_cbs, int32_t nbr,
 struct SymbolicTotals {
     int64_t nnzb = 0, nelems = 0, nprod = 0;
     double flops = 0.0;
+    bool screen = false;      // the norm-bound screen chose the pattern
+    int64_t screened = 0;     // C blocks left out by the screen
+    int64_t old_screened = 0; // of them, blocks of the old C pattern
 };
+// Inputs of the symbolic screen: per-block Frobenius norms of A, B and (for
+// beta != 0) the old C, |alpha|, |beta|, the filter threshold and the
+// relative margin left for rounding.
+struct ScreenNorms {
+    const double *a = nullptr, *b = nullptr, *c = nullptr;
+    double alpha_abs = 0.0, beta_abs = 0.0, eps = 0.0, margin = 0.0;
+};
+// Widest C (block columns) the screen handles: a bound per column in LDS.
+constexpr int32_t kScreenMaxCols = 7680;
+int block_norms(const bsmm_matrix_s *M, double *d_out, hipStream_t s);
+int symbolic_count_screen(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                          const ScreenNorms &sn, uint32_t *d_bits, int64_t *d_row_nnz,
+                          int64_t *d_row_elems, int64_t *d_row_prod, double *d_row_flops,
+                          int64_t *d_row_screened, int64_t *d_row_old_screened, hipStream_t s);
+int symbolic_fill_bits(int32_t nbr, int32_t nbc, const uint32_t *d_bits, const int64_t *d_new_row_ptr,
+                       int32_t *d_new_col_ind, hipStream_t s);
 int symbolic_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
                    int64_t *d_row_nnz, int64_t *d_row_elems, int64_t *d_row_prod,
                    double *d_row_flops, hipStream_t s);
@@ -258,6 +278,7 @@ struct Stacks {
     DevBuf c_row;      // int32[C.nnzb]   block row of every C block
     DevBuf run_of_c;   // int64[C.nnzb]   run of every C block in its panel, or -1
     DevBuf d_rsi, d_csi, missing;     // size-class index of rows / columns; pattern flag
+    bool screened = false;            // C's pattern came from the screen: products of left-out blocks are skipped
     int kparts = 1;                   // parts per A block row in count and fill
     DevBuf pcount;                    // int64[C.nnzb * kparts]: first position of each part (kparts > 1)
     DevBuf sched;                     // uint64[n_sched]: scheduled runs (run << 16 | m << 8 | n)
@@ -288,7 +309,8 @@ int stack_class_run_lengths(const bsmm_matrix_s *C, const Stacks &st, std::vecto
 int build_schedule(const bsmm_matrix_s *C, Stacks &st, const std::vector<char> &eligible, int tile,
                    hipStream_t s);
 // After stack_count: the runs and products of C block rows [r0, r1) (C
-// blocks [c0, c1), nprod products), replacing the previous panel's.
+// blocks [c0, c1), at most nprod products), replacing the previous panel's;
+// st.n_prod is set to the count held.
 int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
                Stacks &st, int32_t r0, int32_t r1, int64_t c0, int64_t c1, int64_t nprod,
                hipStream_t s);

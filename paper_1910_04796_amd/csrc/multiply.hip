@@ -9,6 +9,7 @@
 //      products grouped by shape -> batched small-block kernels;
 //   3. filter.
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 
 #include "dev_util.h"
@@ -21,30 +22,40 @@ bsmm_multiply_stats &stats();
 
 namespace {
 
-// Sums of the per-row symbolic counts: out_i[0..2] (nnz, elems, products),
-// out_d[0] (flops).
+// Sums of the per-row symbolic counts: out_i[0..4] (nnz, elems, products,
+// and with the screen the screened blocks and screened old blocks), out_d[0]
+// (flops).
 __global__ __launch_bounds__(256) void k_row_totals(int32_t nbr, const int64_t *nnz,
                                                     const int64_t *elems, const int64_t *prod,
-                                                    const double *flops, int64_t *out_i,
+                                                    const double *flops, const int64_t *scr,
+                                                    const int64_t *old_scr, int64_t *out_i,
                                                     double *out_d) {
     __shared__ int64_t ri[16];
     __shared__ double rd[16];
-    int64_t a = 0, b = 0, c = 0;
+    int64_t a = 0, b = 0, c = 0, e = 0, f = 0;
     double d = 0.0;
     for (int64_t i = threadIdx.x; i < nbr; i += blockDim.x) {
         a += nnz[i];
         b += elems[i];
         c += prod[i];
         d += flops[i];
+        if (scr) {
+            e += scr[i];
+            f += old_scr[i];
+        }
     }
     a = block_sum(a, ri);
     b = block_sum(b, ri);
     c = block_sum(c, ri);
+    e = block_sum(e, ri);
+    f = block_sum(f, ri);
     d = block_sum(d, rd);
     if (threadIdx.x == 0) {
         out_i[0] = a;
         out_i[1] = b;
         out_i[2] = c;
+        out_i[3] = e;
+        out_i[4] = f;
         out_d[0] = d;
     }
 }
@@ -53,15 +64,90 @@ struct NewPattern {
     DevBuf rp, ci, off, data;
 };
 
+// Symbolic phase with the norm-bound screen: block norms of A, B and (beta
+// != 0) the old C, the count with the screen, then the fill from its
+// bitmap.  The new pattern is (old pattern U product pattern) minus the
+// screened blocks, so it may also lose old blocks.
+int symbolic_screened(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, const ScreenNorms &req,
+                      SymbolicTotals *tot, bool *changed, NewPattern &np, DevBuf &row_elems,
+                      hipStream_t s) {
+    const int32_t nbr = A->nbr, nbc = B->nbc;
+    const int64_t nwords = (nbc + 31) / 32;
+    ScreenNorms sn = req;
+    DevBuf an, bn, cn, bits, rnnz, rprod, rflops, rscr, rold, sums_i, sums_d;
+    BSMM_TRY(an.reserve(sizeof(double) * (A->nnzb + 1), s));
+    BSMM_TRY(bn.reserve(sizeof(double) * (B->nnzb + 1), s));
+    BSMM_TRY(block_norms(A, an.as<double>(), s));
+    BSMM_TRY(block_norms(B, bn.as<double>(), s));
+    sn.a = an.as<double>();
+    sn.b = bn.as<double>();
+    sn.c = nullptr;
+    if (sn.beta_abs != 0.0 && C->nnzb > 0) {
+        BSMM_TRY(cn.reserve(sizeof(double) * (C->nnzb + 1), s));
+        BSMM_TRY(block_norms(C, cn.as<double>(), s));
+        sn.c = cn.as<double>();
+    }
+    BSMM_TRY(row_elems.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(bits.reserve(sizeof(uint32_t) * nbr * nwords, s));
+    BSMM_TRY(rnnz.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(rprod.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(rflops.reserve(sizeof(double) * (nbr + 1), s));
+    BSMM_TRY(rscr.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(rold.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(sums_i.reserve(sizeof(int64_t) * 6, s));
+    BSMM_TRY(sums_d.reserve(sizeof(double) * 2, s));
+    BSMM_TRY(symbolic_count_screen(A, B, C, sn, bits.as<uint32_t>(), rnnz.as<int64_t>(),
+                                   row_elems.as<int64_t>(), rprod.as<int64_t>(), rflops.as<double>(),
+                                   rscr.as<int64_t>(), rold.as<int64_t>(), s));
+    hipLaunchKernelGGL(k_row_totals, dim3(1), dim3(256), 0, s, nbr,
+                       (const int64_t *)rnnz.as<int64_t>(), (const int64_t *)row_elems.as<int64_t>(),
+                       (const int64_t *)rprod.as<int64_t>(), (const double *)rflops.as<double>(),
+                       (const int64_t *)rscr.as<int64_t>(), (const int64_t *)rold.as<int64_t>(),
+                       sums_i.as<int64_t>(), sums_d.as<double>());
+    BSMM_TRY(launch_check("row_totals"));
+    int64_t hi[5];
+    double hd[1];
+    BSMM_HIP(hipMemcpyAsync(hi, sums_i.p, sizeof(hi), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipMemcpyAsync(hd, sums_d.p, sizeof(hd), hipMemcpyDeviceToHost, s));
+    BSMM_HIP(hipStreamSynchronize(s));
+    tot->nnzb = hi[0];
+    tot->nelems = hi[1];
+    tot->nprod = hi[2];
+    tot->flops = hd[0];
+    tot->screen = true;
+    tot->screened = hi[3];
+    tot->old_screened = hi[4];
+    if (tot->nnzb > (int64_t)INT32_MAX || tot->nelems >= (int64_t(1) << 47)) {
+        set_error(BSMM_ERANGE, "result too large (%lld blocks, %lld elements)",
+                  (long long)tot->nnzb, (long long)tot->nelems);
+        return BSMM_ERANGE;
+    }
+    // Unchanged exactly when no old block was screened (the new pattern then
+    // contains the old one) and the counts agree.
+    if (tot->old_screened == 0 && tot->nnzb == C->nnzb) return BSMM_OK;
+    *changed = true;
+    BSMM_TRY(np.rp.reserve(sizeof(int64_t) * (nbr + 1), s));
+    BSMM_TRY(np.ci.reserve(sizeof(int32_t) * (tot->nnzb + 1), s));
+    BSMM_TRY(scan_exclusive_i64(rnnz.as<int64_t>(), np.rp.as<int64_t>(), nbr, s));
+    return symbolic_fill_bits(nbr, nbc, bits.as<uint32_t>(), np.rp.as<int64_t>(), np.ci.as<int32_t>(), s);
+}
+
 // Symbolic phase.  On return *tot holds the new C sizes, the product count
-// and the algorithmic flops; if the pattern grows, np holds the new index
-// (and row element totals in row_elems).
+// and the algorithmic flops of A*B; if the pattern changes, np holds the new
+// index (and row element totals in row_elems).  With `screen` (filtering
+// stack multiplies), C blocks whose norm bound lies below eps are left out
+// of the new pattern.
 int symbolic(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, SymbolicTotals *tot,
-             bool *changed, NewPattern &np, DevBuf &row_elems, hipStream_t s) {
+             bool *changed, NewPattern &np, DevBuf &row_elems, hipStream_t s,
+             const ScreenNorms *screen = nullptr) {
     const int32_t nbr = A->nbr, nbk = A->nbc, nbc = B->nbc;
     *changed = false;
     if (nbr == 0 || nbc == 0) return BSMM_OK;
     const bool closed_form = A->full() && B->full() && nbk > 0;
+    // The screen's bitmap: one bit per (I, J), at most 256 MB.
+    const int64_t nwords = (nbc + 31) / 32;
+    if (screen && !closed_form && nbc <= kScreenMaxCols && (int64_t)nbr * nwords <= (int64_t(1) << 26))
+        return symbolic_screened(A, B, C, *screen, tot, changed, np, row_elems, s);
     BSMM_TRY(row_elems.reserve(sizeof(int64_t) * (nbr + 1), s));
     if (closed_form) {
         // Every (I,K,J) is a product: the new pattern is every block.
@@ -87,14 +173,15 @@ int symbolic(bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, SymbolicTotal
     BSMM_TRY(rnnz.reserve(sizeof(int64_t) * (nbr + 1), s));
     BSMM_TRY(rprod.reserve(sizeof(int64_t) * (nbr + 1), s));
     BSMM_TRY(rflops.reserve(sizeof(double) * (nbr + 1), s));
-    BSMM_TRY(sums_i.reserve(sizeof(int64_t) * 4, s));
+    BSMM_TRY(sums_i.reserve(sizeof(int64_t) * 6, s));
     BSMM_TRY(sums_d.reserve(sizeof(double) * 2, s));
     BSMM_TRY(symbolic_count(A, B, C, rnnz.as<int64_t>(), row_elems.as<int64_t>(),
                             rprod.as<int64_t>(), rflops.as<double>(), s));
     hipLaunchKernelGGL(k_row_totals, dim3(1), dim3(256), 0, s, nbr,
                        (const int64_t *)rnnz.as<int64_t>(), (const int64_t *)row_elems.as<int64_t>(),
                        (const int64_t *)rprod.as<int64_t>(), (const double *)rflops.as<double>(),
-                       sums_i.as<int64_t>(), sums_d.as<double>());
+                       (const int64_t *)nullptr, (const int64_t *)nullptr, sums_i.as<int64_t>(),
+                       sums_d.as<double>());
     BSMM_TRY(launch_check("row_totals"));
     int64_t hi[3];
     double hd[1];
@@ -155,10 +242,10 @@ int active_classes(const Stacks &st) {
 
 // Options that change what a plan computes.
 std::string plan_key(const Options &o) {
-    char buf[128];
-    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
+    char buf[160];
+    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
              (long long)o.stack_chunk, (long long)o.stack_panel, o.emul_slices, o.forced[0],
-             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched, o.jit);
+             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched, o.jit, o.prescreen);
     return std::string(buf) + o.tune_db + "|" + o.mlp_weights;
 }
 
@@ -171,6 +258,7 @@ struct Plan {
     uint64_t va = 0, vb = 0, vc = 0;
     std::string key;
     double alpha = 0.0, beta = 0.0;
+    double eps = 0.0;  // filter threshold the screen used (tot.screen)
     SymbolicTotals tot;
     int path = 0;
     Stacks st;
@@ -185,6 +273,29 @@ struct NormSinkScope {
     explicit NormSinkScope(double *p) { set_norm_sink(p); }
     ~NormSinkScope() { set_norm_sink(nullptr); }
 };
+
+// Whether a multiply screens its new C pattern by the norm bound (filtering
+// stack multiplies with option "prescreen"), and with which inputs.  The
+// margin bounds the rounding of a computed block relative to the bound:
+// at most about n u for n accumulated terms (n at most A's column count),
+// taken four times over and never below 1e-6.  Thresholds below 1e-150
+// are left alone (their square, which the filter compares with, loses
+// precision), and so are margins above 1/4 (FP32 sums of very long rows).
+bool screen_request(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
+                    double alpha, double beta, double eps, const Options &o, ScreenNorms *sn) {
+    const bool stack = o.path == 1 || (o.path == 0 && !(A->full() && B->full()));
+    if (!o.prescreen || !stack || !(eps >= 1e-150) || alpha == 0.0 || !std::isfinite(alpha) ||
+        !std::isfinite(beta))
+        return false;
+    const double u = C->dtype == BSMM_F32 ? 0x1p-24 : 0x1p-53;
+    const double margin = std::max(1e-6, 4.0 * ((double)A->cols() + 4.0) * u);
+    if (margin > 0.25) return false;
+    sn->alpha_abs = std::fabs(alpha);
+    sn->beta_abs = std::fabs(beta);
+    sn->eps = eps;
+    sn->margin = margin;
+    return true;
+}
 
 // Limits of the stack path, checked on the host before any work is queued:
 // a product entry carries k in 16 bits and the count and fill phases map
@@ -280,9 +391,11 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
     stt = bsmm_multiply_stats{};
     const Options &o = options();
     Plan *pl = C->plan;
+    // A screened pattern holds only for the threshold it was screened with.
     const bool hit = o.plan_cache && pl && pl->A == A && pl->B == B && pl->va == A->version &&
                      pl->vb == B->version && pl->vc == C->version && pl->alpha == alpha &&
-                     pl->beta == beta && pl->key == plan_key(o);
+                     pl->beta == beta && pl->key == plan_key(o) &&
+                     (!pl->tot.screen || pl->eps == eps);
     // Filtering stack multiplies: the scheduled kernel writes the squared
     // norms of the blocks it finishes, the filter reads the rest.
     const double *pre_norm2 = nullptr;
@@ -297,6 +410,8 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
                          &stt.n_row_panels, s));
         stt.path = pl->path;
         stt.c_nnzb_before = C->nnzb;
+        stt.n_screened = pl->tot.screened;
+        stt.n_products_run = pl->st.n_prod;
         stt.n_products = pl->tot.nprod;
         stt.flops = pl->tot.flops;
         stt.n_runs = pl->st.n_runs;
@@ -310,15 +425,19 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         bool changed = false;
         NewPattern np;
         DevBuf row_elems;
-        BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s));
+        ScreenNorms sn;
+        const bool screen = screen_request(A, B, C, alpha, beta, eps, o, &sn);
+        BSMM_TRY(symbolic(A, B, C, &tot, &changed, np, row_elems, s, screen ? &sn : nullptr));
         if (changed) BSMM_TRY(install_pattern(C, tot, np, row_elems, beta, s));
         stt.c_nnzb_before = C->nnzb;
+        stt.n_screened = tot.screened;
         stt.n_products = tot.nprod;
         stt.flops = tot.flops;
         const bool dense = o.path == 2 || (o.path == 0 && A->full() && B->full());
         const int path = (alpha == 0.0 || tot.nprod == 0) ? 0 : o.path == 3 ? 3 : dense ? 2 : 1;
         auto *p = new Plan();
         p->st.n_prod = tot.nprod;
+        p->st.screened = tot.screen;
         if (eps > 0.0 && path == 1 && C->nnzb > 0) {
             int st = p->norm2.reserve(sizeof(double) * (size_t)C->nnzb, s);
             if (st == BSMM_OK) st = fill_value(p->norm2.as<double>(), C->nnzb, -1.0, s);
@@ -339,6 +458,7 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
         }
         stt.path = path;
         stt.n_runs = p->st.n_runs;
+        stt.n_products_run = path == 1 ? p->st.n_prod : path == 0 ? 0 : tot.nprod;
         stt.n_sched_runs = p->st.n_sched;
         stt.n_jit_classes = p->st.n_jit;
         stt.n_classes = active_classes(p->st);
@@ -352,6 +472,7 @@ int multiply_impl(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, double beta,
             p->key = plan_key(o);
             p->alpha = alpha;
             p->beta = beta;
+            p->eps = eps;
             p->tot = tot;
             p->path = path;
             C->plan = p;
@@ -400,6 +521,7 @@ int multiply_fixed_pattern(double alpha, bsmm_matrix_s *A, bsmm_matrix_s *B, dou
     stt.path = path;
     stt.c_nnzb_before = stt.c_nnzb_after = C->nnzb;
     stt.n_products = tot.nprod;
+    stt.n_products_run = path == 1 ? st.n_prod : path == 0 ? 0 : tot.nprod;
     stt.flops = tot.flops;
     stt.n_runs = st.n_runs;
     stt.n_sched_runs = st.n_sched;

@@ -47,6 +47,9 @@ __device__ __forceinline__ void a_part(const int64_t *a_rp, int32_t row, int par
 // Workgroup (row, part): products per C block of the row from the part's
 // share of A's block row (P > 1 splits long A rows of few-row products;
 // the part counts go to pcount[c * P + part], else straight to c_count).
+// A product whose C block is not in the pattern sets *missing, unless
+// missing is null (a pattern from the symbolic screen leaves such blocks
+// out on purpose; their products are skipped here and in the fill).
 __global__ __launch_bounds__(256) void k_stack_count(int32_t nbr, int32_t nbc, const int64_t *a_rp,
                                                      const int32_t *a_ci, const int64_t *b_rp,
                                                      const int32_t *b_ci, const int64_t *c_rp,
@@ -75,7 +78,7 @@ __global__ __launch_bounds__(256) void k_stack_count(int32_t nbr, int32_t nbc, c
             for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
                 const int32_t s = map[b_ci[q]];
                 if (s >= 0) atomicAdd(&cnt[s], 1);
-                else *missing = 1;
+                else if (missing) *missing = 1;
             }
         }
         __syncthreads();
@@ -120,7 +123,7 @@ __global__ __launch_bounds__(256) void k_stack_count_wide(int32_t nbr, const int
             for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
                 const int64_t c = find_col(c_ci, p0, p1, b_ci[q]);
                 if (c >= 0) atomicAdd((unsigned long long *)&cnt[P == 1 ? c : c * P + part], 1ull);
-                else *missing = 1;
+                else if (missing) *missing = 1;
             }
         }
     }
@@ -475,13 +478,13 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
         hipLaunchKernelGGL(k_stack_count_wide, dim3(grid_rows(nbr), st.kparts), dim3(256), 0, s, nbr,
                            A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
                            C->d_row_ptr(), C->d_col_ind(), cnt, st.c_row.as<int32_t>(),
-                           st.missing.as<int32_t>(), st.kparts);
+                           st.screened ? nullptr : st.missing.as<int32_t>(), st.kparts);
     } else {
         const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
         hipLaunchKernelGGL(k_stack_count, dim3(grid_rows(nbr), st.kparts), dim3(256), map_lds, s, nbr,
                            nbc, A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
                            C->d_row_ptr(), C->d_col_ind(), st.c_count.as<int64_t>(),
-                           st.c_row.as<int32_t>(), st.missing.as<int32_t>(), st.kparts,
+                           st.c_row.as<int32_t>(), st.screened ? nullptr : st.missing.as<int32_t>(), st.kparts,
                            st.pcount.as<int64_t>());
     }
     BSMM_TRY(launch_check("stack_count"));
@@ -586,7 +589,7 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     st.class_begin.assign(ncl + 1, 0);
     st.class_prod_begin.assign(ncl + 1, 0);
     st.n_runs = 0;
-    st.n_prod = nprod;
+    st.n_prod = 0;
     if (r1 <= r0 || nblk <= 0) return BSMM_OK;
 
     DevBuf run_cnt;
@@ -617,11 +620,12 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     st.class_begin.assign(both.begin(), both.begin() + ncl + 1);
     st.class_prod_begin.assign(both.begin() + ncl + 1, both.end());
     st.n_runs = st.class_begin[ncl];
+    st.n_prod = st.class_prod_begin[ncl];  // below nprod when the screen left blocks out
     for (int cl = 0; cl < ncl; ++cl)
         if (st.class_begin[cl + 1] > st.class_begin[cl]) st.class_active[cl] = 1;
     BSMM_TRY(scan_exclusive_i64(run_cnt.as<int64_t>(), st.run_ptr.as<int64_t>(), st.n_runs, s));
-    if (nprod > 0 && nbc > kMaxStackCols) {
-        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
+    if (st.n_prod > 0 && nbc > kMaxStackCols) {
+        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * st.n_prod, s));
         DevBuf cur;
         BSMM_TRY(cur.reserve(sizeof(int64_t) * nblk * st.kparts, s));
         BSMM_TRY(fill_zero(cur.as<double>(), nblk * st.kparts, s));
@@ -633,8 +637,8 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
                            (const int64_t *)st.run_ptr.as<int64_t>(), cur.as<int64_t>(),
                            st.prods.as<ulonglong2>());
         BSMM_TRY(launch_check("stack_fill_wide"));
-    } else if (nprod > 0) {
-        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * nprod, s));
+    } else if (st.n_prod > 0) {
+        BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * st.n_prod, s));
         // LDS: the column map, then per slot a 64-bit next position (rows of
         // at most cap slots) or a 32-bit count; at most 64 KB.
         const int64_t nbc_pad = (nbc + 1) & ~1;
