@@ -83,15 +83,20 @@ def gflops(F, ms):
     return round(F / (ms * 1e-3) / 1e9, 1)
 
 
-def profile_json(name, src):
+def profile_json(name, src, products_run=None):
     """A committed counter summary, valid only while the kernel source is
-    unchanged since the counters were taken."""
+    unchanged since the counters were taken (and, when given, the launch ran
+    the same number of block products)."""
     path = os.path.join(ROOT, "profiles", name)
     try:
         with open(path) as f:
             t = json.load(f)
         sha = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-        return t if t.get("source_sha256") == sha else None
+        if t.get("source_sha256") != sha:
+            return None
+        if products_run is not None and t.get("products_run") != products_run:
+            return None
+        return t
     except (OSError, ValueError):
         return None
 
@@ -273,15 +278,16 @@ def headline(bsmm, torch, stream, args):
     res["C_plain"] = MP
     # The same tuned multiply with the norm-bound screen off: every block of
     # the product pattern is formed and the filter alone drops.
-    set_opts(bsmm, stack_kernel="tuned")
-    bsmm.bsmm_set_option("prescreen", "0")
-    MN = bsmm.Matrix.empty(A.rbs, B.cbs)
-    t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MN, HEADLINE_EPS, stream), 1,
-                    args.plain_reps)
-    bsmm.bsmm_set_option("prescreen", "1")
-    res["tuned_without_prescreen"] = dict(t, gflops=gflops(F, t["median_ms"]))
-    log(f"tuned without the screen: {t['median_ms']:.3f} ms (median of {args.plain_reps})")
-    MN.close()
+    if not args.no_unscreened:
+        set_opts(bsmm, stack_kernel="tuned")
+        bsmm.bsmm_set_option("prescreen", "0")
+        MN = bsmm.Matrix.empty(A.rbs, B.cbs)
+        t = timed_calls(torch, lambda: bsmm.multiply(1.0, MA, MB, 0.0, MN, HEADLINE_EPS, stream), 1,
+                        args.plain_reps)
+        bsmm.bsmm_set_option("prescreen", "1")
+        res["tuned_without_prescreen"] = dict(t, gflops=gflops(F, t["median_ms"]))
+        log(f"tuned without the screen: {t['median_ms']:.3f} ms (median of {args.plain_reps})")
+        MN.close()
     set_opts(bsmm, path="auto", stack_kernel="plain")
     MA.close()
     MB.close()
@@ -761,6 +767,8 @@ def main():
     ap.add_argument("--plain-reps", type=int, default=3, help="repetitions of the plain headline leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
+    ap.add_argument("--no-unscreened", action="store_true",
+                    help="skip the headline leg with the norm-bound screen off (counter runs)")
     ap.add_argument("--all-configs", action="store_true",
                     help="also run the rectangular dense and sparse split-precision workloads")
     ap.add_argument("--paper-workloads", default="",
@@ -851,7 +859,8 @@ def main():
     # product of A*B, the work of the operation whose result it delivers.
     F_run = scr["flops_run"]
     achieved = F_run / (k_ms * 1e-3) / 1e12
-    tr = profile_json("smm_sched_banded30_traffic.json", "paper_1910_04796_amd/csrc/smm.hip")
+    tr = profile_json("smm_sched_banded30_traffic.json", "paper_1910_04796_amd/csrc/smm.hip",
+                      st["n_products_run"])
     roofline = {"bound": "mfma", "kernel": "k_smm_mfma_sched (tuned stack launch)",
                 "achieved": round(achieved, 3), "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(achieved / PEAK_FP64_TFLOPS, 4), "kernel_ms": k_ms,
@@ -937,7 +946,7 @@ def main():
         "rel_err_mode": f"sampled: block rows {sample[0]}..{sample[1] - 1}" if sample else None,
         "plain": dict(res["plain"], rel_err=rel_errs["plain"] if rel_errs else None),
         "tuned_speedup_vs_plain": round(res["plain"]["median_ms"] / ms, 3),
-        "tuned_without_prescreen": res["tuned_without_prescreen"],
+        "tuned_without_prescreen": res.get("tuned_without_prescreen"),
         "extras": extras,
     }
     print(json.dumps(out), flush=True)

@@ -89,39 +89,44 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
 }
 
 // One wave per block: the block's Frobenius norm in FP64, for the norm
-// bound of the symbolic screen.  Away from the ends of the exponent range
-// it is summed as max|x| * sqrt(sum (x / max|x|)^2), so that no square
-// under- or overflows (relative rounding error below len * 2^-52); for
-// max|x| below 2^-900 or above 2^900 it is the upper bound
-// sqrt(len) * max|x|.  A NaN element gives NaN, an infinite one infinity.
+// bound of the symbolic screen.  One pass sums the squares and finds
+// max|x|; when max|x| lies in [2^-500, 2^500] no square overflows and the
+// ones that underflow are negligible beside max|x|^2, so sqrt(sum) stands
+// (relative rounding error below len * 2^-52).  Otherwise a second pass
+// sums (x / max|x|)^2, and for max|x| below 2^-900 or above 2^900 the
+// upper bound sqrt(len) * max|x| is taken.  A NaN element gives NaN, an
+// infinite one infinity.
 template <class T>
 __global__ __launch_bounds__(256) void k_block_norm(int64_t nnzb, const int64_t *blk_off,
                                                     const T *data, double *out) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
         const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
-        double mx = 0.0;
+        double mx = 0.0, ss = 0.0;
         int nan = 0;
         for (int64_t e = lane_id(); e < len; e += kWave) {
-            const double v = fabs((double)data[o + e]);
+            const double x = (double)data[o + e], v = fabs(x);
             nan |= v != v;
             mx = v > mx ? v : mx;
+            ss = fma(x, x, ss);
         }
         mx = wave_max(mx);
         nan = __any(nan);
         double nrm;
         if (nan) {
             nrm = __builtin_nan("");
+        } else if (mx >= 0x1p-500 && mx <= 0x1p500) {
+            nrm = sqrt(wave_sum(ss));
         } else if (mx == 0.0 || mx > 0x1p900 || mx < 0x1p-900) {
             nrm = mx * sqrt((double)len);  // also 0 and infinity
         } else {
             const double r = 1.0 / mx;
-            double ss = 0.0;
+            double sc = 0.0;
             for (int64_t e = lane_id(); e < len; e += kWave) {
                 const double v = (double)data[o + e] * r;
-                ss = fma(v, v, ss);
+                sc = fma(v, v, sc);
             }
-            nrm = mx * sqrt(wave_sum(ss));
+            nrm = mx * sqrt(wave_sum(sc));
         }
         if (lane_id() == 0) out[b] = nrm;
     }

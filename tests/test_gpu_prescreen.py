@@ -86,6 +86,21 @@ def test_screen_keeps_non_finite():
     check_against_oracle(X1, X0, 0.0)
 
 
+def test_screen_extreme_magnitudes():
+    """A blocks scaled to 1e-200, 1e-280 and 1e200: block norms outside
+    [2^-500, 2^500] take the scaled second pass or the sqrt(len) max bound,
+    and bounds of 1e150 and above keep their blocks; same bits as without
+    the screen."""
+    A, B = _steep(78)
+    sizes = orc.block_sizes(A.rbs, A.cbs, A.row_ptr, A.col_ind)
+    rng = rng_of(79)
+    scale = rng.choice([1.0, 1e-200, 1e-280, 1e200], len(sizes), p=[0.7, 0.1, 0.1, 0.1])
+    A = BlockCSR(A.rbs, A.cbs, A.row_ptr, A.col_ind, np.asarray(A.data) * np.repeat(scale, sizes))
+    (X1, st1), (X0, _) = _both(1.0, A, B)
+    assert st1["n_screened"] > 0
+    check_against_oracle(X1, X0, 0.0)
+
+
 @pytest.mark.parametrize("eps,screens", [(np.inf, True), (1e-200, False), (0.0, False)])
 def test_screen_thresholds(eps, screens):
     """eps = inf drops every finite block either way; thresholds below
