@@ -181,3 +181,70 @@ def test_screen_plan_cache_threshold():
     R = orc.multiply(1.0, A, B, 0.0, filter_eps=1e-40)
     assert len(R.col_ind) > len(orc.multiply(1.0, A, B, 0.0, filter_eps=1e-10).col_ind)
     check_against_oracle(X, R, TOL)
+
+
+def _with_options(opts, fn):
+    b = lib()
+    saved = {k: b.bsmm_get_option(k) for k in opts}
+    try:
+        for k, v in opts.items():
+            b.bsmm_set_option(k, v)
+        return fn()
+    finally:
+        for k, v in saved.items():
+            b.bsmm_set_option(k, v)
+
+
+@pytest.mark.parametrize("kernel", ["plain", "tuned"])
+def test_screen_row_panels(kernel):
+    """Stacks built in row panels over a screened pattern: the panel split
+    counts only the products run; same bits as whole, unscreened stacks."""
+    A, B = _steep(80, target=2500)
+    (X0, st0), _ = _both(1.0, A, B, kernel=kernel)
+    (X1, st1), (X2, _) = _with_options({"stack_panel": "2000"}, lambda: _both(1.0, A, B, kernel=kernel))
+    assert st1["n_row_panels"] > 1 and st1["n_screened"] == st0["n_screened"] > 0
+    assert st1["n_products_run"] == st0["n_products_run"]
+    check_against_oracle(X1, X0, 0.0)
+    check_against_oracle(X2, X0, 0.0)
+
+
+def test_screen_split_long_rows():
+    """Few C block rows with long A rows (count and fill split every A row
+    into parts) and magnitudes 10^-i / 10^-j per block row / column, so that
+    the blocks far from the corner are screened; integer-scaled values keep
+    the comparison exact against the unscreened multiply."""
+    rng = rng_of(81)
+    ms = np.full(12, 4, np.int32)
+    ks = rng.choice(np.array([4, 5, 7], np.int32), 1500)
+    ns = np.full(12, 4, np.int32)
+    A = make_matrix(rng, ms, ks, 0.6)
+    B = make_matrix(rng, ks, ns, 0.6)
+    ra = np.repeat(np.arange(len(ms)), np.diff(np.asarray(A.row_ptr)))
+    A.data = np.asarray(A.data) * np.repeat(10.0 ** (-2.0 * ra), orc.block_sizes(A.rbs, A.cbs, A.row_ptr, A.col_ind))
+    cb = np.asarray(B.col_ind)
+    B.data = np.asarray(B.data) * np.repeat(10.0 ** (-2.0 * cb), orc.block_sizes(B.rbs, B.cbs, B.row_ptr, B.col_ind))
+    for kernel in ("plain", "tuned"):
+        (X1, st1), (X0, _) = _both(1.0, A, B, kernel=kernel)
+        assert st1["n_screened"] > 0
+        check_against_oracle(X1, X0, 0.0)
+        check_against_oracle(X1, orc.multiply(1.0, A, B, 0.0, filter_eps=1e-10), TOL)
+
+
+def test_screen_jit_classes():
+    """One product depth (every A block column 13 wide): the classes run on
+    kernels compiled at run time, over a screened pattern."""
+    A, B = banded_uneven(seed=82, occupancy=0.3, target=2600, decay=3.0, choices=(13,))
+    (X1, st1), (X0, _) = _with_options({"jit": "1", "stack_params": "16 16 0 4"},
+                                       lambda: _both(1.0, A, B, kernel="tuned"))
+    assert st1["n_screened"] > 0 and st1["n_jit_classes"] > 0
+    check_against_oracle(X1, X0, 0.0)
+    check_against_oracle(X1, orc.multiply(1.0, A, B, 0.0, filter_eps=1e-10), TOL)
+
+
+def test_screen_plain_with_beta():
+    A, B = _steep(83, target=2000)
+    Cin = make_matrix(rng_of(84), A.rbs, B.cbs, 0.2)
+    (X1, st1), (X0, _) = _both(2.0, A, B, -0.5, Cin, kernel="plain")
+    assert st1["n_screened"] > 0
+    check_against_oracle(X1, X0, 0.0)
+    check_against_oracle(X1, orc.multiply(2.0, A, B, -0.5, Cin, filter_eps=1e-10), TOL)
