@@ -302,6 +302,7 @@ extern "C" int bsmm_create_matrix_typed(int32_t nbr, const int32_t *row_blk_size
     M->col_off = col_off;
     M->nnzb = nnzb;
     M->nelems = acc;
+    M->storage = acc;
     M->max_rbs = nbr ? *std::max_element(M->rbs.begin(), M->rbs.end()) : 0;
     M->max_cbs = nbc ? *std::max_element(M->cbs.begin(), M->cbs.end()) : 0;
     M->last_stream = s;
@@ -439,9 +440,25 @@ extern "C" int bsmm_copy_out_typed(bsmm_matrix m, int64_t *blk_row_ptr, int32_t 
     if (blk_col_ind && m->nnzb > 0)
         BSMM_HIP(hipMemcpyAsync(blk_col_ind, m->d_col_ind(), sizeof(int32_t) * m->nnzb,
                                 hipMemcpyDeviceToHost, s));
-    if (data && m->nelems > 0)
+    DevBuf packed, packed_off;
+    if (data && m->nelems > 0 && m->holes) {
+        // Storage with gaps left by a filter: the blocks are gathered into
+        // packed CSR order (straight into a device destination).
+        BSMM_TRY(packed_off.reserve(sizeof(int64_t) * (m->nnzb + 1), s));
+        BSMM_TRY(build_block_offsets(m->d_rbs(), m->d_cbs(), m->nbr, m->d_row_ptr(), m->d_col_ind(),
+                                     m->nnzb, packed_off.as<int64_t>(), nullptr, s));
+        void *dst = data;
+        if (!data_on_device) {
+            BSMM_TRY(packed.reserve(m->esize() * m->nelems, s));
+            dst = packed.p;
+        }
+        BSMM_TRY(relayout(m, m->d_row_ptr(), m->d_col_ind(), packed_off.as<int64_t>(), dst, s));
+        if (!data_on_device)
+            BSMM_HIP(hipMemcpyAsync(data, packed.p, m->esize() * m->nelems, hipMemcpyDeviceToHost, s));
+    } else if (data && m->nelems > 0) {
         BSMM_HIP(hipMemcpyAsync(data, m->d_raw(), m->esize() * m->nelems,
                                 data_on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+    }
     BSMM_HIP(hipStreamSynchronize(s));
     m->last_stream = s;
     return BSMM_OK;

@@ -1,6 +1,7 @@
 // filter.hip -- post-multiply block filter: drop every C block whose squared
 // Frobenius norm is strictly below eps^2 (a NaN norm keeps the block), then
-// compact C's index and data.
+// compact C's index; the kept blocks' data stay in place (the dropped
+// blocks leave gaps) unless most of the storage would be gaps.
 #include "dev_util.h"
 #include "internal.h"
 
@@ -8,15 +9,24 @@ namespace bsmm {
 
 namespace {
 
+// Elements of block b: from the offsets of packed storage, else (blk_row
+// non-null) from the block's row and column sizes.
+__device__ __forceinline__ int64_t block_len(int64_t b, const int64_t *blk_off, const int32_t *blk_row,
+                                             const int32_t *rbs, const int32_t *cbs, const int32_t *ci) {
+    return blk_row ? (int64_t)rbs[blk_row[b]] * cbs[ci[b]] : blk_off[b + 1] - blk_off[b];
+}
+
 // One wave per block: keep flag and kept element count (squares summed in
 // FP64 for either element type).
 template <class T>
 __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *blk_off,
+                                                   const int32_t *blk_row, const int32_t *rbs,
+                                                   const int32_t *cbs, const int32_t *ci,
                                                    const T *data, const double *pre, double eps2,
                                                    int64_t *keep, int64_t *keep_elems) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
-        const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
+        const int64_t o = blk_off[b], len = block_len(b, blk_off, blk_row, rbs, cbs, ci);
         const double given = pre ? pre[b] : -1.0;
         if (given >= 0.0) {  // computed by the kernel that wrote the block
             if (lane_id() == 0) {
@@ -60,17 +70,32 @@ __global__ __launch_bounds__(256) void k_new_row_ptr(int32_t nbr, int64_t nnzb, 
     }
 }
 
-// One wave per old block: kept blocks move to their new place.
+// One thread per old block: the kept blocks' column indices and data
+// offsets move to their new index positions; the data stay in place.
+__global__ __launch_bounds__(256) void k_keep_index(int64_t nnzb, const int32_t *ci,
+                                                    const int64_t *blk_off, const int64_t *kpos,
+                                                    int32_t *new_ci, int64_t *new_off) {
+    for (int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nnzb;
+         b += (int64_t)gridDim.x * blockDim.x) {
+        if (kpos[b + 1] == kpos[b]) continue;  // dropped
+        new_ci[kpos[b]] = ci[b];
+        new_off[kpos[b]] = blk_off[b];
+    }
+}
+
+// One wave per old block: kept blocks move to their packed place (len:
+// kept element counts, zero for dropped blocks).
 template <class T>
 __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci,
-                                                 const int64_t *blk_off, const T *data,
-                                                 const int64_t *kpos, const int64_t *epos,
-                                                 int32_t *new_ci, int64_t *new_off, T *new_data) {
+                                                 const int64_t *blk_off, const int64_t *kept_len,
+                                                 const T *data, const int64_t *kpos,
+                                                 const int64_t *epos, int32_t *new_ci,
+                                                 int64_t *new_off, T *new_data) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
         if (kpos[b + 1] == kpos[b]) continue;  // dropped
         const int64_t nb = kpos[b];
-        const int64_t o = blk_off[b], len = blk_off[b + 1] - o, no = epos[b];
+        const int64_t o = blk_off[b], len = kept_len[b], no = epos[b];
         if (lane_id() == 0) {
             new_ci[nb] = ci[b];
             new_off[nb] = no;
@@ -98,10 +123,12 @@ __global__ __launch_bounds__(256) void k_compact(int64_t nnzb, const int32_t *ci
 // infinite one infinity.
 template <class T>
 __global__ __launch_bounds__(256) void k_block_norm(int64_t nnzb, const int64_t *blk_off,
+                                                    const int32_t *blk_row, const int32_t *rbs,
+                                                    const int32_t *cbs, const int32_t *ci,
                                                     const T *data, double *out) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
-        const int64_t o = blk_off[b], len = blk_off[b + 1] - o;
+        const int64_t o = blk_off[b], len = block_len(b, blk_off, blk_row, rbs, cbs, ci);
         double mx = 0.0, ss = 0.0;
         int nan = 0;
         for (int64_t e = lane_id(); e < len; e += kWave) {
@@ -136,12 +163,17 @@ __global__ __launch_bounds__(256) void k_block_norm(int64_t nnzb, const int64_t 
 
 int block_norms(const bsmm_matrix_s *M, double *d_out, hipStream_t s) {
     if (M->nnzb == 0) return BSMM_OK;
+    DevBuf rows;
+    BSMM_TRY(block_rows(M, rows, s));
+    const int32_t *r = rows.as<int32_t>();
     if (M->dtype == BSMM_F32)
         hipLaunchKernelGGL(k_block_norm<float>, dim3(grid_of(M->nnzb, 4)), dim3(256), 0, s, M->nnzb,
-                           M->d_blk_off(), (const float *)M->d_raw(), d_out);
+                           M->d_blk_off(), r, M->d_rbs(), M->d_cbs(), M->d_col_ind(),
+                           (const float *)M->d_raw(), d_out);
     else
         hipLaunchKernelGGL(k_block_norm<double>, dim3(grid_of(M->nnzb, 4)), dim3(256), 0, s, M->nnzb,
-                           M->d_blk_off(), (const double *)M->d_raw(), d_out);
+                           M->d_blk_off(), r, M->d_rbs(), M->d_cbs(), M->d_col_ind(),
+                           (const double *)M->d_raw(), d_out);
     return launch_check("block_norm");
 }
 
@@ -150,20 +182,22 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     *nnzb_after = C->nnzb;
     if (!(eps > 0.0) || C->nnzb == 0) return BSMM_OK;
     const int64_t nnzb = C->nnzb;
-    DevBuf keep, kel, kpos, epos;
+    DevBuf keep, kel, kpos, epos, rows;
     BSMM_TRY(keep.reserve(sizeof(int64_t) * (nnzb + 1), s));
     BSMM_TRY(kel.reserve(sizeof(int64_t) * (nnzb + 1), s));
     BSMM_TRY(kpos.reserve(sizeof(int64_t) * (nnzb + 1), s));
     BSMM_TRY(epos.reserve(sizeof(int64_t) * (nnzb + 1), s));
+    BSMM_TRY(block_rows(C, rows, s));
+    const int32_t *r = rows.as<int32_t>();
     if (C->dtype == BSMM_F32)
         hipLaunchKernelGGL(k_norm_keep<float>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
-                           C->d_blk_off(), (const float *)C->d_raw(), pre_norm2, eps * eps,
-                           keep.as<int64_t>(),
+                           C->d_blk_off(), r, C->d_rbs(), C->d_cbs(), C->d_col_ind(),
+                           (const float *)C->d_raw(), pre_norm2, eps * eps, keep.as<int64_t>(),
                            kel.as<int64_t>());
     else
         hipLaunchKernelGGL(k_norm_keep<double>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
-                           C->d_blk_off(), (const double *)C->d_raw(), pre_norm2, eps * eps,
-                           keep.as<int64_t>(),
+                           C->d_blk_off(), r, C->d_rbs(), C->d_cbs(), C->d_col_ind(),
+                           (const double *)C->d_raw(), pre_norm2, eps * eps, keep.as<int64_t>(),
                            kel.as<int64_t>());
     BSMM_TRY(launch_check("norm_keep"));
     BSMM_TRY(scan_exclusive_i64(keep.as<int64_t>(), kpos.as<int64_t>(), nnzb, s));
@@ -178,30 +212,45 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     *nnzb_after = new_nnzb;
     if (new_nnzb == nnzb) return BSMM_OK;
 
+    // The index always shrinks; the data move only when the gaps would be
+    // most of the storage (memory back), otherwise they stay in place.
+    const bool pack = new_elems < C->storage / 2;
     DevBuf n_rp, n_ci, n_off, n_data;
     BSMM_TRY(n_rp.reserve(sizeof(int64_t) * (C->nbr + 1), s));
     BSMM_TRY(n_ci.reserve(sizeof(int32_t) * (new_nnzb + 1), s));
     BSMM_TRY(n_off.reserve(sizeof(int64_t) * (new_nnzb + 1), s));
-    BSMM_TRY(n_data.reserve(C->esize() * (new_elems + 1), s));
+    if (pack) BSMM_TRY(n_data.reserve(C->esize() * (new_elems + 1), s));
     hipLaunchKernelGGL(k_new_row_ptr, dim3(grid_of(C->nbr + 1, 256)), dim3(256), 0, s, C->nbr,
                        nnzb, C->d_row_ptr(), (const int64_t *)kpos.as<int64_t>(), n_rp.as<int64_t>(),
-                       n_off.as<int64_t>(), new_elems);
+                       n_off.as<int64_t>(), pack ? new_elems : C->storage);
     BSMM_TRY(launch_check("new_row_ptr"));
-    if (C->dtype == BSMM_F32)
+    if (!pack) {
+        hipLaunchKernelGGL(k_keep_index, dim3(grid_of(nnzb, 256)), dim3(256), 0, s, nnzb,
+                           C->d_col_ind(), C->d_blk_off(), (const int64_t *)kpos.as<int64_t>(),
+                           n_ci.as<int32_t>(), n_off.as<int64_t>());
+        BSMM_TRY(launch_check("keep_index"));
+    } else if (C->dtype == BSMM_F32) {
         hipLaunchKernelGGL(k_compact<float>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
-                           C->d_col_ind(), C->d_blk_off(), (const float *)C->d_raw(),
-                           (const int64_t *)kpos.as<int64_t>(), (const int64_t *)epos.as<int64_t>(),
-                           n_ci.as<int32_t>(), n_off.as<int64_t>(), n_data.as<float>());
-    else
+                           C->d_col_ind(), C->d_blk_off(), (const int64_t *)kel.as<int64_t>(),
+                           (const float *)C->d_raw(), (const int64_t *)kpos.as<int64_t>(),
+                           (const int64_t *)epos.as<int64_t>(), n_ci.as<int32_t>(), n_off.as<int64_t>(),
+                           n_data.as<float>());
+    } else {
         hipLaunchKernelGGL(k_compact<double>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
-                           C->d_col_ind(), C->d_blk_off(), (const double *)C->d_raw(),
-                           (const int64_t *)kpos.as<int64_t>(), (const int64_t *)epos.as<int64_t>(),
-                           n_ci.as<int32_t>(), n_off.as<int64_t>(), n_data.as<double>());
-    BSMM_TRY(launch_check("compact"));
+                           C->d_col_ind(), C->d_blk_off(), (const int64_t *)kel.as<int64_t>(),
+                           (const double *)C->d_raw(), (const int64_t *)kpos.as<int64_t>(),
+                           (const int64_t *)epos.as<int64_t>(), n_ci.as<int32_t>(), n_off.as<int64_t>(),
+                           n_data.as<double>());
+    }
+    if (pack) BSMM_TRY(launch_check("compact"));
     C->b_row_ptr = std::move(n_rp);
     C->b_col_ind = std::move(n_ci);
     C->b_blk_off = std::move(n_off);
-    C->b_data = std::move(n_data);
+    if (pack) {
+        C->b_data = std::move(n_data);
+        C->storage = new_elems;
+    }
+    C->holes = !pack;
     C->nnzb = new_nnzb;
     C->nelems = new_elems;
     C->version = next_version();

@@ -322,16 +322,25 @@ __global__ __launch_bounds__(256) void k_relayout(int32_t nbr, const int32_t *rb
     }
 }
 
+// Block row of every block: one workgroup per block row.
+__global__ __launch_bounds__(256) void k_block_rows(int32_t nbr, const int64_t *rp, int32_t *row) {
+    for (int32_t r = blockIdx.x; r < nbr; r += gridDim.x)
+        for (int64_t p = rp[r] + threadIdx.x; p < rp[r + 1]; p += blockDim.x) row[p] = r;
+}
+
 // One wave per block: data *= beta, or zeros when beta == 0, for the blocks
-// whose flag is zero.
+// whose flag is zero.  With gaps in the storage (blk_row non-null) a block's
+// size comes from its block sizes, else from the offsets.
 template <class T>
 __global__ __launch_bounds__(256) void k_scale_blocks(int64_t nnzb, const int64_t *blk_off,
+                                                      const int32_t *blk_row, const int32_t *rbs,
+                                                      const int32_t *cbs, const int32_t *ci,
                                                       const int64_t *flags, T beta, T *data) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
         if (flags && flags[b] != 0) continue;
         T *d = data + blk_off[b];
-        const int64_t len = blk_off[b + 1] - blk_off[b];
+        const int64_t len = blk_row ? (int64_t)rbs[blk_row[b]] * cbs[ci[b]] : blk_off[b + 1] - blk_off[b];
         if (beta == T(0))
             for (int64_t e = lane_id(); e < len; e += kWave) d[e] = T(0);
         else
@@ -476,14 +485,27 @@ int relayout(const bsmm_matrix_s *Cold, const int64_t *d_new_rp, const int32_t *
     return launch_check("relayout");
 }
 
+int block_rows(const bsmm_matrix_s *M, DevBuf &out, hipStream_t s) {
+    if (!M->holes || M->nnzb == 0) return BSMM_OK;
+    BSMM_TRY(out.reserve(sizeof(int32_t) * M->nnzb, s));
+    hipLaunchKernelGGL(k_block_rows, dim3(grid_rows(M->nbr)), dim3(256), 0, s, M->nbr, M->d_row_ptr(),
+                       out.as<int32_t>());
+    return launch_check("block_rows");
+}
+
 int scale_blocks(const bsmm_matrix_s *C, const int64_t *d_flags, double beta, hipStream_t s) {
     if (C->nnzb == 0) return BSMM_OK;
+    DevBuf rows;
+    BSMM_TRY(block_rows(C, rows, s));
+    const int32_t *r = rows.as<int32_t>();
     if (C->dtype == BSMM_F32)
         hipLaunchKernelGGL(k_scale_blocks<float>, dim3(grid_of(C->nnzb, 4)), dim3(256), 0, s, C->nnzb,
-                           C->d_blk_off(), d_flags, (float)beta, (float *)C->d_raw());
+                           C->d_blk_off(), r, C->d_rbs(), C->d_cbs(), C->d_col_ind(), d_flags,
+                           (float)beta, (float *)C->d_raw());
     else
         hipLaunchKernelGGL(k_scale_blocks<double>, dim3(grid_of(C->nnzb, 4)), dim3(256), 0, s,
-                           C->nnzb, C->d_blk_off(), d_flags, beta, (double *)C->d_raw());
+                           C->nnzb, C->d_blk_off(), r, C->d_rbs(), C->d_cbs(), C->d_col_ind(), d_flags,
+                           beta, (double *)C->d_raw());
     return launch_check("scale_blocks");
 }
 

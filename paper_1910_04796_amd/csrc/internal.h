@@ -166,8 +166,14 @@ struct bsmm_matrix_s {
     int32_t nbr = 0, nbc = 0;
     std::vector<int32_t> rbs, cbs;          // host copies of the block sizes
     std::vector<int64_t> row_off, col_off;  // host element offsets (nbr+1, nbc+1)
-    int64_t nnzb = 0, nelems = 0;
+    int64_t nnzb = 0, nelems = 0;        // nelems: elements of the stored blocks
     int32_t max_rbs = 0, max_cbs = 0;
+    // Block b's data starts at blk_off[b] and holds rbs(row) * cbs(col)
+    // elements, column-major; blocks are in CSR order.  The storage is
+    // packed (blk_off[b + 1] - blk_off[b] is the block's size) except after
+    // a filter that dropped blocks: their space stays behind as unused gaps
+    // until the pattern next changes (holes = true; blk_off[nnzb] is then
+    // the end of the storage, not nelems).
     int device = 0;
     int dtype = BSMM_F64;          // element type of the block data
     hipStream_t last_stream = nullptr;
@@ -193,6 +199,8 @@ struct bsmm_matrix_s {
     int64_t rows() const { return row_off.empty() ? 0 : row_off.back(); }
     int64_t cols() const { return col_off.empty() ? 0 : col_off.back(); }
     bool full() const { return nnzb == (int64_t)nbr * (int64_t)nbc; }
+    bool holes = false;
+    int64_t storage = 0;  // elements the data buffer holds (blk_off[nnzb])
 };
 
 namespace bsmm {
@@ -229,6 +237,10 @@ struct ScreenNorms {
 // Widest C (block columns) the screen handles: a bound per column in LDS.
 constexpr int32_t kScreenMaxCols = 7680;
 int block_norms(const bsmm_matrix_s *M, double *d_out, hipStream_t s);
+// Block row of every block (int32[nnzb]) of a matrix with gaps in its
+// storage, where offsets do not give block sizes; out stays empty (null)
+// for packed storage.
+int block_rows(const bsmm_matrix_s *M, DevBuf &out, hipStream_t s);
 int symbolic_count_screen(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix_s *C,
                           const ScreenNorms &sn, uint32_t *d_bits, int64_t *d_row_nnz,
                           int64_t *d_row_elems, int64_t *d_row_prod, double *d_row_flops,

@@ -230,6 +230,8 @@ int install_pattern(bsmm_matrix_s *C, const SymbolicTotals &tot, NewPattern &np,
     C->b_data = std::move(np.data);
     C->nnzb = tot.nnzb;
     C->nelems = tot.nelems;
+    C->storage = tot.nelems;
+    C->holes = false;
     C->version = next_version();
     return BSMM_OK;
 }
