@@ -16,8 +16,11 @@ __device__ __forceinline__ int64_t block_len(int64_t b, const int64_t *blk_off, 
     return blk_row ? (int64_t)rbs[blk_row[b]] * cbs[ci[b]] : blk_off[b + 1] - blk_off[b];
 }
 
-// One wave per block: keep flag and kept element count (squares summed in
-// FP64 for either element type).
+// Keep flag and kept element count of every block.  A wave takes 64
+// consecutive blocks, one per lane: a block whose squared norm the
+// small-block kernel handed over (pre[b] >= 0, or NaN) is decided by its
+// lane; the others are summed by the whole wave, one block at a time
+// (squares summed in FP64 for either element type).
 template <class T>
 __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *blk_off,
                                                    const int32_t *blk_row, const int32_t *rbs,
@@ -25,35 +28,38 @@ __global__ __launch_bounds__(256) void k_norm_keep(int64_t nnzb, const int64_t *
                                                    const T *data, const double *pre, double eps2,
                                                    int64_t *keep, int64_t *keep_elems) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t b = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); b < nnzb; b += waves) {
-        const int64_t o = blk_off[b], len = block_len(b, blk_off, blk_row, rbs, cbs, ci);
-        const double given = pre ? pre[b] : -1.0;
-        if (given >= 0.0) {  // computed by the kernel that wrote the block
-            if (lane_id() == 0) {
-                const int64_t k = (given < eps2) ? 0 : 1;
-                keep[b] = k;
-                keep_elems[b] = k ? len : 0;
+    for (int64_t base = ((int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id()) * kWave; base < nnzb;
+         base += waves * kWave) {
+        const int64_t b = base + lane_id();
+        const bool in = b < nnzb;
+        const int64_t len = in ? block_len(b, blk_off, blk_row, rbs, cbs, ci) : 0;
+        double ss = in && pre ? pre[b] : -1.0;
+        uint64_t need = __ballot(in && ss < 0.0);
+        while (need) {
+            const int l = __ffsll((unsigned long long)need) - 1;
+            need &= need - 1;
+            const int64_t bb = base + l;
+            const int64_t o = blk_off[bb], n = block_len(bb, blk_off, blk_row, rbs, cbs, ci);
+            // Four independent partial sums per lane keep four loads in flight.
+            double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+            int64_t e = lane_id();
+            for (; e + 3 * kWave < n; e += 4 * kWave) {
+                const double x0 = (double)data[o + e], x1 = (double)data[o + e + kWave];
+                const double x2 = (double)data[o + e + 2 * kWave], x3 = (double)data[o + e + 3 * kWave];
+                s0 = fma(x0, x0, s0);
+                s1 = fma(x1, x1, s1);
+                s2 = fma(x2, x2, s2);
+                s3 = fma(x3, x3, s3);
             }
-            continue;
+            for (; e < n; e += kWave) {
+                const double x = (double)data[o + e];
+                s0 = fma(x, x, s0);
+            }
+            const double sum = wave_sum((s0 + s1) + (s2 + s3));
+            if (lane_id() == l) ss = sum;
         }
-        // Four independent partial sums per lane keep four loads in flight.
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int64_t e = lane_id();
-        for (; e + 3 * kWave < len; e += 4 * kWave) {
-            const double x0 = (double)data[o + e], x1 = (double)data[o + e + kWave];
-            const double x2 = (double)data[o + e + 2 * kWave], x3 = (double)data[o + e + 3 * kWave];
-            s0 = fma(x0, x0, s0);
-            s1 = fma(x1, x1, s1);
-            s2 = fma(x2, x2, s2);
-            s3 = fma(x3, x3, s3);
-        }
-        for (; e < len; e += kWave) {
-            const double x = (double)data[o + e];
-            s0 = fma(x, x, s0);
-        }
-        double s = wave_sum((s0 + s1) + (s2 + s3));
-        if (lane_id() == 0) {
-            const int64_t k = (s < eps2) ? 0 : 1;
+        if (in) {
+            const int64_t k = (ss < eps2) ? 0 : 1;  // a NaN norm keeps the block
             keep[b] = k;
             keep_elems[b] = k ? len : 0;
         }
@@ -190,12 +196,12 @@ int filter_blocks(bsmm_matrix_s *C, double eps, int64_t *nnzb_after, hipStream_t
     BSMM_TRY(block_rows(C, rows, s));
     const int32_t *r = rows.as<int32_t>();
     if (C->dtype == BSMM_F32)
-        hipLaunchKernelGGL(k_norm_keep<float>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
+        hipLaunchKernelGGL(k_norm_keep<float>, dim3(grid_of(ceil_div(nnzb, kWave), 4)), dim3(256), 0, s, nnzb,
                            C->d_blk_off(), r, C->d_rbs(), C->d_cbs(), C->d_col_ind(),
                            (const float *)C->d_raw(), pre_norm2, eps * eps, keep.as<int64_t>(),
                            kel.as<int64_t>());
     else
-        hipLaunchKernelGGL(k_norm_keep<double>, dim3(grid_of(nnzb, 4)), dim3(256), 0, s, nnzb,
+        hipLaunchKernelGGL(k_norm_keep<double>, dim3(grid_of(ceil_div(nnzb, kWave), 4)), dim3(256), 0, s, nnzb,
                            C->d_blk_off(), r, C->d_rbs(), C->d_cbs(), C->d_col_ind(),
                            (const double *)C->d_raw(), pre_norm2, eps * eps, keep.as<int64_t>(),
                            kel.as<int64_t>());
