@@ -166,8 +166,12 @@ int bsmm_matrix_info(bsmm_matrix m, int32_t *nbr, int32_t *nbc, int64_t *nnzb,
 /*
  * Copies a matrix out: blk_row_ptr (host int64[nbr+1]), blk_col_ind (host
  * int32[nnzb]) and data (FP64[nelems], host or device as data_on_device
- * says).  Any output pointer may be NULL to skip that part.  Synchronous
- * with respect to the host for host outputs.
+ * says), the blocks packed in CSR order, each column-major.  Any output
+ * pointer may be NULL to skip that part.  Synchronous with respect to the
+ * host for host outputs.  (Inside the library a filtered matrix may keep
+ * its blocks at their old places with unused space between them; the copy
+ * gathers them, through a temporary device buffer of nelems elements for
+ * host outputs.)
  */
 int bsmm_copy_out(bsmm_matrix m, int64_t *blk_row_ptr, int32_t *blk_col_ind,
                   double *data, int data_on_device, void *stream);
