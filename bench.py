@@ -434,11 +434,11 @@ def extras_wide(bsmm, torch, stream, args, orc, threads):
     return out
 
 
-def extras_banded(bsmm, torch, stream, args, orc, threads):
+def extras_banded(bsmm, torch, stream, args, orc, threads, occs=(0.01, 0.10)):
     """Banded uneven blocks at 1 % and 10 %: plain vs tuned stacks."""
     from synth import banded_uneven
     out = {}
-    for occ in (0.01, 0.10):
+    for occ in occs:
         U, V = banded_uneven(seed=0, occupancy=occ, target=50000)
         MU, MV = bsmm.Matrix.from_blocks(U), bsmm.Matrix.from_blocks(V)
         r = {"N": int(np.sum(U.rbs)), "blocks_A": int(U.nnzb)}
@@ -745,7 +745,7 @@ def paper_workloads(bsmm, torch, stream, names, threads, blocks=None):
     return out
 
 
-EXTRA_LEGS = ("dense", "wide", "banded", "tiny", "f32", "learned", "all_configs")
+EXTRA_LEGS = ("dense", "wide", "banded", "banded1", "banded10", "tiny", "f32", "learned", "all_configs")
 
 
 def add_all_configs_errors(orc, out, keep, threads):
@@ -833,6 +833,9 @@ def main():
                 extras["emulated_wide_dense_16384"] = extras_wide(bsmm, torch, stream, args, None, threads)
             elif name == "banded":
                 extras.update(extras_banded(bsmm, torch, stream, args, None, threads))
+            elif name in ("banded1", "banded10"):
+                occ = 0.01 if name == "banded1" else 0.10
+                extras.update(extras_banded(bsmm, torch, stream, args, None, threads, (occ,)))
             elif name == "tiny":
                 extras["sparse_460_b23_latency"] = extras_tiny(bsmm, torch, stream, args)
             elif name == "f32":
