@@ -119,10 +119,14 @@ int bsmm_matrix_dtype(bsmm_matrix m, int32_t *dtype);
  *   The new pattern of C is the old pattern united with every (I,J) for
  *   which some K has A(I,K) and B(K,J) stored.  Then, if filter_eps > 0,
  *   every C block whose squared Frobenius norm is strictly below
- *   filter_eps^2 is removed (a NaN norm keeps the block).
+ *   filter_eps^2 is removed (a NaN norm keeps the block); blocks that a
+ *   norm bound proves will be removed may be left out before their
+ *   products are formed (option "prescreen"), with the same result.
  *   A == B is allowed; C must differ from both.
- * The call blocks the host once to read the size of the new C pattern and
- * once more when the filter removes blocks; the rest is stream-ordered.
+ * The call blocks the host to read the size of the new C pattern, on the
+ * stack path the run and product counts of the shape classes, and, when
+ * filter_eps > 0, the number of blocks the filter keeps; the rest is
+ * stream-ordered.
  * Errors: EINVAL (nulls, C aliasing A or B, filter_eps < 0 or NaN, element
  * types that differ), ESHAPE, ERANGE, ENOMEM, ENOTSUP (incl. option "path"
  * "emul" on FP32 matrices), EDEVICE.  On EINVAL/ESHAPE nothing is modified.
