@@ -242,6 +242,11 @@ int bsmm_set_allocator(bsmm_alloc_fn alloc, bsmm_dealloc_fn dealloc, void *ctx);
                  below filter_eps, and skips its products: such blocks
                  always fail the filter, so C is the same as with "0",
                  which forms every block of the product pattern first
+   "stack_at"    scheduled launch: "1" reads A's blocks from row-major
+                 copies made for the multiply (one vector load per four k
+                 values), "0" reads them in place, "auto" (default) copies
+                 for FP32 matrices only; the same bits either way (not in
+                 bsmm_multiply_noalloc, which makes no copies)
    "stack_sched" order in which the scheduled launch's waves take runs:
                  "dynamic" (default; a run counter, several short runs per
                  update) or "static" (fixed strides, numbered XCD by XCD)

@@ -520,6 +520,11 @@ extern "C" int bsmm_set_option(const char *key, const char *value) {
         if (v == "0") o.jit = 0;
         else if (v == "1") o.jit = 1;
         else goto bad;
+    } else if (k == "stack_at") {
+        if (v == "auto") o.stack_at = -1;
+        else if (v == "0") o.stack_at = 0;
+        else if (v == "1") o.stack_at = 1;
+        else goto bad;
     } else if (k == "prescreen") {
         if (v == "0") o.prescreen = 0;
         else if (v == "1") o.prescreen = 1;
@@ -591,6 +596,7 @@ extern "C" int bsmm_get_option(const char *key, char *buf, size_t len) {
     else if (k == "stack_sched") v = o.stack_sched ? "dynamic" : "static";
     else if (k == "jit") v = std::to_string(o.jit);
     else if (k == "prescreen") v = std::to_string(o.prescreen);
+    else if (k == "stack_at") v = o.stack_at < 0 ? "auto" : std::to_string(o.stack_at);
     else if (k == "tune_db") v = o.tune_db;
     else if (k == "time_kernels") v = std::to_string(o.time_kernels);
     else if (k == "verbose") v = std::to_string(o.verbose);

@@ -63,6 +63,7 @@ struct Options {
     int stack_tile = 32;   // tuned path: > 0 runs MFMA classes in one launch, tiles of this many blocks
     int stack_sched = 1;   // scheduled kernel: 0 static XCD-aware striding, 1 dynamic run counter
     int prescreen = 1;     // stack path with eps > 0: leave out C blocks whose norm bound is below eps
+    int stack_at = -1;     // scheduled launch reads A's blocks transposed: 1 on, 0 off, -1 FP32 only
 };
 Options &options();
 
@@ -291,6 +292,8 @@ struct Stacks {
     DevBuf run_of_c;   // int64[C.nnzb]   run of every C block in its panel, or -1
     DevBuf d_rsi, d_csi, missing;     // size-class index of rows / columns; pattern flag
     bool screened = false;            // C's pattern came from the screen: products of left-out blocks are skipped
+    DevBuf a_t;                       // A's blocks transposed, for the scheduled launch (option stack_at)
+    bool a_t_fresh = false;           // a_t holds this multiply's A (later row panels reuse it)
     int kparts = 1;                   // parts per A block row in count and fill
     DevBuf pcount;                    // int64[C.nnzb * kparts]: first position of each part (kparts > 1)
     DevBuf sched;                     // uint64[n_sched]: scheduled runs (run << 16 | m << 8 | n)
@@ -379,6 +382,9 @@ struct SmmArgs {
     // every finished C block, norm2[run_cblk[r]] (run_cblk: C block of run r).
     double *norm2;
     const int64_t *run_cblk;
+    // Scheduled kernel reading A's blocks transposed (row-major copies at
+    // the same offsets), or null.
+    const void *A_t;
 };
 // Squared block norms the scheduled kernel writes for the filter during the
 // current multiply on this thread (nullptr: none); set around the numeric
@@ -410,6 +416,7 @@ void retire_graph(hipGraphExec_t exec, hipEvent_t done);
 struct StackExec {
     LaunchList launches;
     std::vector<DevBuf> parts;  // partial blocks of split launches
+    bool reads_a_t = false;     // a launch reads the stacks' transposed copy of A
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;  // recorded after every launch of exec
     StackExec() = default;

@@ -245,9 +245,10 @@ int active_classes(const Stacks &st) {
 // Options that change what a plan computes.
 std::string plan_key(const Options &o) {
     char buf[160];
-    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
+    snprintf(buf, sizeof buf, "%d %d %lld %lld %d %d %d %d %d %d %d %d %d %d|", o.path, o.stack_kernel,
              (long long)o.stack_chunk, (long long)o.stack_panel, o.emul_slices, o.forced[0],
-             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched, o.jit, o.prescreen);
+             o.forced[1], o.forced[2], o.forced[3], o.stack_tile, o.stack_sched, o.jit, o.prescreen,
+             o.stack_at);
     return std::string(buf) + o.tune_db + "|" + o.mlp_weights;
 }
 
@@ -370,6 +371,7 @@ int numeric(int path, bsmm_matrix_s *A, bsmm_matrix_s *B, bsmm_matrix_s *C, doub
     case 2:
         return dense_multiply(A, B, C, alpha, beta, s);
     default:
+        st.a_t_fresh = false;  // A's transposed copy, if any, is made anew
         if (replay) {
             BSMM_TRY(replay_stacks(ex, A, B, C, st, alpha, beta, s));
             *n_panels = 1;

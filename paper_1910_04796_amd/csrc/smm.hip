@@ -148,7 +148,7 @@ __global__ __launch_bounds__(256) void k_smm_valu(SmmArgs p) {
 // operands at row (or column) l % 16 and k = l / 16 of the step.
 // Products [q0, q1) of one run into the MT x NT accumulator tiles of an
 // m x n C block.
-template <class T, int MT, int NT>
+template <class T, int MT, int NT, bool AT = false>
 __device__ __forceinline__ void mfma_products(const SmmArgs &p, int m, int n, int64_t q0, int64_t q1,
                                               typename Mfma<T>::acc_t (&acc)[MT][NT]) {
     const int lane = lane_id();
@@ -157,7 +157,7 @@ __device__ __forceinline__ void mfma_products(const SmmArgs &p, int m, int n, in
     for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = Mfma<T>::zero();
-    const T *A = static_cast<const T *>(p.A);
+    const T *A = static_cast<const T *>(AT ? p.A_t : p.A);
     const T *B = static_cast<const T *>(p.B);
     // The next product's descriptor is loaded one product ahead.
     ulonglong2 nxt = q0 < q1 ? p.prods[q0] : make_ulonglong2(0ull, 0ull);
@@ -177,9 +177,23 @@ __device__ __forceinline__ void mfma_products(const SmmArgs &p, int m, int n, in
 #pragma unroll
             for (int i = 0; i < MT; ++i) {
                 const int row = 16 * i + lr;
+                if (AT) {
+                    // Row-major copy: the four k values of a row are adjacent.
+                    const T *ar = a + (int64_t)row * k + kb;
+                    if (row < m && kb + 3 < k) {
+                        T v[4];
+                        Mfma<T>::load4(ar, v);
 #pragma unroll
-                for (int s = 0; s < 4; ++s)
-                    af[s][i] = (row < m && kb + s < k) ? a[(int64_t)(kb + s) * m + row] : T(0);
+                        for (int s = 0; s < 4; ++s) af[s][i] = v[s];
+                    } else {
+#pragma unroll
+                        for (int s = 0; s < 4; ++s) af[s][i] = (row < m && kb + s < k) ? ar[s] : T(0);
+                    }
+                } else {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        af[s][i] = (row < m && kb + s < k) ? a[(int64_t)(kb + s) * m + row] : T(0);
+                }
             }
 #pragma unroll
             for (int j = 0; j < NT; ++j) {
@@ -292,10 +306,10 @@ __global__ __launch_bounds__(256) void k_smm_mfma(SmmArgs p) {
 // m << 8 | n.  Static mode: wave slots are numbered XCD by XCD (workgroup g
 // runs on XCD g % 8), so each XCD takes a contiguous part of every window
 // of in-flight runs; dynamic mode: waves take the next run from a counter.
-template <class T, int MT, int NT>
+template <class T, int MT, int NT, bool AT>
 __device__ __forceinline__ void sched_run(const SmmArgs &p, int64_t r, int m, int n) {
     typename Mfma<T>::acc_t acc[MT][NT];
-    mfma_products<T, MT, NT>(p, m, n, p.run_ptr[r], p.run_ptr[r + 1], acc);
+    mfma_products<T, MT, NT, AT>(p, m, n, p.run_ptr[r], p.run_ptr[r + 1], acc);
     // One store path: the norm is summed whether or not the filter wants it.
     const double ss = mfma_store_sumsq<T, MT, NT>(static_cast<T *>(p.C) + p.run_coff[r], m, n, acc,
                                                   (T)p.alpha, (T)p.beta);
@@ -306,8 +320,8 @@ constexpr int kXcds = 8;
 // Fewest runs for which the MFMA classes go through the scheduled launch.
 constexpr int64_t kSchedMinRuns = 4096;
 
-template <class T>
-__global__ __launch_bounds__(256, 4) void k_smm_mfma_sched(SmmArgs p) {
+template <class T, bool AT>
+__device__ __forceinline__ void sched_loop(const SmmArgs &p) {
     const int wpw = blockDim.x / kWave;
     const int64_t waves = (int64_t)gridDim.x * wpw;
     // A wave takes `chunk` consecutive entries at a time (short runs: fewer
@@ -330,11 +344,11 @@ __global__ __launch_bounds__(256, 4) void k_smm_mfma_sched(SmmArgs p) {
             const int64_t r = (int64_t)(e >> 16);
             const int m = (int)((e >> 8) & 255), n = (int)(e & 255);
             if (m > 16) {
-                if (n > 16) sched_run<T, 2, 2>(p, r, m, n);
-                else sched_run<T, 2, 1>(p, r, m, n);
+                if (n > 16) sched_run<T, 2, 2, AT>(p, r, m, n);
+                else sched_run<T, 2, 1, AT>(p, r, m, n);
             } else {
-                if (n > 16) sched_run<T, 1, 2>(p, r, m, n);
-                else sched_run<T, 1, 1>(p, r, m, n);
+                if (n > 16) sched_run<T, 1, 2, AT>(p, r, m, n);
+                else sched_run<T, 1, 1, AT>(p, r, m, n);
             }
         }
         if (p.sched_mode == 0) {
@@ -343,6 +357,37 @@ __global__ __launch_bounds__(256, 4) void k_smm_mfma_sched(SmmArgs p) {
             unsigned long long t = 0;
             if (lane_id() == 0) t = atomicAdd(p.next, (unsigned long long)chunk);
             it = (int64_t)__shfl(t, 0, kWave);
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256, 4) void k_smm_mfma_sched(SmmArgs p) {
+    sched_loop<T, false>(p);
+}
+
+// The scheduled launch reading A's blocks from their row-major copies.
+template <class T>
+__global__ __launch_bounds__(256, 4) void k_smm_mfma_sched_at(SmmArgs p) {
+    sched_loop<T, true>(p);
+}
+
+// Row-major copies of A's blocks at the blocks' own offsets: one workgroup
+// per block row, consecutive lanes write consecutive elements of a row.
+template <class T>
+__global__ __launch_bounds__(256) void k_transpose_blocks(int32_t nbr, const int64_t *rp, const int32_t *ci,
+                                                          const int32_t *rbs, const int32_t *cbs,
+                                                          const int64_t *blk_off, const T *src, T *dst) {
+    for (int32_t r = blockIdx.x; r < nbr; r += gridDim.x) {
+        const int m = rbs[r];
+        for (int64_t p = rp[r]; p < rp[r + 1]; ++p) {
+            const int k = cbs[ci[p]];
+            const T *sb = src + blk_off[p];
+            T *db = dst + blk_off[p];
+            for (int e = threadIdx.x; e < m * k; e += blockDim.x) {
+                const int i = e / k, j = e - i * k;
+                db[e] = sb[(int64_t)j * m + i];
+            }
         }
     }
 }
@@ -423,7 +468,8 @@ template <class T> SmmKernel kernel_for(int tm, int tn) {
 thread_local double *t_norm_sink = nullptr;
 
 bool is_sched_kernel(const void *fn) {
-    return fn == (const void *)k_smm_mfma_sched<double> || fn == (const void *)k_smm_mfma_sched<float>;
+    return fn == (const void *)k_smm_mfma_sched<double> || fn == (const void *)k_smm_mfma_sched<float> ||
+           fn == (const void *)k_smm_mfma_sched_at<double> || fn == (const void *)k_smm_mfma_sched_at<float>;
 }
 
 constexpr int kLdsBudget = 64 * 1024;  // bytes of LDS per workgroup
@@ -614,6 +660,22 @@ static int split_for(int64_t runs, int64_t prods, int m, int n, size_t esize) {
     return (int)std::max<int64_t>(S, 1);
 }
 
+// Row-major copies of A's blocks into st.a_t (the A data of this call: a
+// replayed plan copies again, since A's values may have changed).
+static int transpose_a(const bsmm_matrix_s *A, const Stacks &st, hipStream_t s) {
+    BSMM_TRY(const_cast<DevBuf &>(st.a_t).reserve(A->esize() * (size_t)(A->storage + 1), s));
+    if (A->nnzb == 0) return BSMM_OK;
+    if (A->dtype == BSMM_F32)
+        hipLaunchKernelGGL(k_transpose_blocks<float>, dim3(grid_rows(A->nbr)), dim3(256), 0, s, A->nbr,
+                           A->d_row_ptr(), A->d_col_ind(), A->d_rbs(), A->d_cbs(), A->d_blk_off(),
+                           (const float *)A->d_raw(), st.a_t.as<float>());
+    else
+        hipLaunchKernelGGL(k_transpose_blocks<double>, dim3(grid_rows(A->nbr)), dim3(256), 0, s, A->nbr,
+                           A->d_row_ptr(), A->d_col_ind(), A->d_rbs(), A->d_cbs(), A->d_blk_off(),
+                           (const double *)A->d_raw(), st.a_t.as<double>());
+    return launch_check("transpose_blocks");
+}
+
 int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C, Stacks &st,
                double alpha, double beta, hipStream_t s, StackExec *ex) {
     ex->launches.clear();
@@ -716,7 +778,24 @@ int run_stacks(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
     if (sched_on && sched_runs > 0) {
         BSMM_TRY(build_schedule(C, st, eligible, options().stack_tile, s));
         SmmLaunch L;
-        L.fn = C->dtype == BSMM_F32 ? (void *)k_smm_mfma_sched<float> : (void *)k_smm_mfma_sched<double>;
+        // FP32 loads are instruction-bound: A's blocks are read from
+        // row-major copies (one 16-byte load for four k values instead of
+        // four 4-byte loads; banded 10 % FP32 kernel 54.5 -> 51.8 ms).  FP64
+        // is bound by the fabric, where the copies' strided rows coalesce
+        // worse (headline kernel 669 -> 718 ms), so it reads A in place.
+        const int at_opt = options().stack_at;
+        // (Not with a scratch arena: the copy is as large as A.)
+        const bool at = (at_opt == 1 || (at_opt < 0 && C->dtype == BSMM_F32)) && !scratch_arena();
+        if (at && !st.a_t_fresh) {
+            BSMM_TRY(transpose_a(A, st, s));
+            st.a_t_fresh = true;
+        }
+        ex->reads_a_t = at;
+        if (C->dtype == BSMM_F32)
+            L.fn = at ? (void *)k_smm_mfma_sched_at<float> : (void *)k_smm_mfma_sched<float>;
+        else
+            L.fn = at ? (void *)k_smm_mfma_sched_at<double> : (void *)k_smm_mfma_sched<double>;
+        L.args.A_t = at ? st.a_t.p : nullptr;
         L.dtype = C->dtype;
         L.args.L = kWave;
         L.args.G = 1;
@@ -780,6 +859,8 @@ void retire_graph(hipGraphExec_t exec, hipEvent_t done) {
 
 int replay_stacks(const StackExec &ex, const bsmm_matrix_s *A, const bsmm_matrix_s *B,
                   bsmm_matrix_s *C, const Stacks &st, double alpha, double beta, hipStream_t s) {
+    // Same buffer (the launches hold its address), this call's A values.
+    if (ex.reads_a_t) BSMM_TRY(transpose_a(A, st, s));
     if (ex.exec) {
         {
             KernelTimer kt(1, s);
