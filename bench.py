@@ -657,7 +657,11 @@ PAPER_SHAPES = {"square_63360": (63360, 63360, 63360),
                 "rect_1408x1408x1982464": (1408, 1408, 1982464),
                 # the first tenth of the square product's C rows (every C row
                 # of a dense product costs the same in both modes)
-                "square_63360_rows_6336": (6336, 63360, 63360)}
+                "square_63360_rows_6336": (6336, 63360, 63360),
+                # its first 176 C rows (44 block rows of 4, 8 of 22): the one
+                # share of the product in blocks of 4 that the blocked mode
+                # can hold (1.1e10 block products)
+                "square_63360_rows_176": (176, 63360, 63360)}
 # Blocked mode is skipped above this many block products (the square
 # product in blocks of 22 has 2.4e10; its first tenth of rows took 3.7 s).
 BLOCKED_MAX_PRODUCTS = 3e10
@@ -675,8 +679,9 @@ def paper_workloads(bsmm, torch, stream, names, threads, blocks=None):
     itself the timing.  The square product also runs in blocks of 4,
     densified only (the paper quotes that block size for its comparison
     with a dense library; blocked, it would hold about 4e12 block
-    products).  Every result is checked against the reference on two
-    sampled block rows."""
+    products); its first 176 rows run in blocks of 22 and 4 in both modes.
+    Every result is checked against the reference on two sampled block
+    rows."""
     from oracle import oracle as orc
     from synth import BlockCSR, pattern_full, rng_of, values_uniform
     out = {}
@@ -690,7 +695,7 @@ def paper_workloads(bsmm, torch, stream, names, threads, blocks=None):
         res = {"M": M, "N": Nn, "K": K, "flops_per_multiply": F}
         # The paper's square product also in blocks of 4 (its comparison with
         # a dense library); blocked mode there is far beyond the stack cap.
-        sizes = (64, 22, 4) if name == "square_63360" else (64, 22)
+        sizes = {"square_63360": (64, 22, 4), "square_63360_rows_176": (22, 4)}.get(name, (64, 22))
         if blocks:
             sizes = tuple(b for b in sizes if b in blocks)
         for bs in sizes:
@@ -740,6 +745,10 @@ def paper_workloads(bsmm, torch, stream, names, threads, blocks=None):
                                                   4)
         if "b4" in res and "b64" in res:
             res["densified_b4_over_b64"] = round(res["b4"]["densified"]["ms"] / res["b64"]["densified"]["ms"], 4)
+        if "b4" in res and "b22" in res:
+            for mode in ("densified", "blocked"):
+                if "ms" in res["b4"][mode] and "ms" in res["b22"][mode]:
+                    res[f"{mode}_b4_over_b22"] = round(res["b4"][mode]["ms"] / res["b22"][mode]["ms"], 4)
         out[name] = res
         del a_vals, b_vals
     return out
