@@ -460,12 +460,21 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
     BSMM_TRY(st.c_row.reserve(sizeof(int32_t) * nnzb, s));
     BSMM_TRY(st.c_count.reserve(sizeof(int64_t) * nnzb, s));
     BSMM_TRY(st.missing.reserve(sizeof(int32_t), s));
-    // Few C block rows with long A rows (tall-and-skinny products): split
+    // Few C block rows with long A rows (tall-and-skinny products, or a
+    // product whose stacks are built in row panels of few rows each): split
     // every A row into P parts so that about 1024 workgroups count and fill.
+    // A panel holds about nbr * cap / n_prod rows when the products exceed
+    // the cap; the per-part counts stay within 2^28 entries.
     st.kparts = 1;
-    if (nbr < 256 && A->nnzb > 0) {
+    const int64_t cap = options().stack_panel;
+    int64_t rows = nbr;
+    if (cap > 0 && st.n_prod > cap)
+        rows = std::max<int64_t>(1, (int64_t)((double)nbr * (double)cap / (double)st.n_prod));
+    if (rows < 256 && A->nnzb > 0) {
         const int64_t per_row = A->nnzb / nbr;
-        st.kparts = (int)std::min<int64_t>(ceil_div(1024, nbr), std::max<int64_t>(1, per_row / 64));
+        int64_t P = std::min<int64_t>(ceil_div(1024, rows), std::max<int64_t>(1, per_row / 64));
+        P = std::min<int64_t>(P, std::max<int64_t>(1, (int64_t(1) << 28) / nnzb));
+        st.kparts = (int)P;
     }
     if (st.kparts > 1) BSMM_TRY(st.pcount.reserve(sizeof(int64_t) * nnzb * st.kparts, s));
     BSMM_HIP(hipMemcpyAsync(st.d_rsi.p, rsi.data(), sizeof(int32_t) * nbr, hipMemcpyHostToDevice, s));

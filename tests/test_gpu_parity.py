@@ -407,6 +407,31 @@ def test_stack_row_panels_no_plan_reuse():
     check_against_oracle(X, orc.multiply(1.75, A, B, 0.0), TOL)
 
 
+def test_stack_row_panels_split_rows_bitwise():
+    """Row panels of few block rows each split long A rows into parts (more
+    workgroups per panel): 300 block rows of about 160 A blocks, panels of
+    about 10 rows, so each row is counted and filled in 2 parts, where the
+    whole stacks take 1.  Parts are contiguous K ranges placed in order, so
+    the runs keep their K order and the bits equal those of whole stacks."""
+    b = lib()
+    rng = rng_of(44)
+    s = np.array([1, 2, 3, 5], np.int32)
+    ms, ks, ns = (rng.choice(s, size=x) for x in (300, 400, 200))
+    A = make_matrix(rng, ms, ks, 0.4, values="int")
+    B = make_matrix(rng, ks, ns, 0.05, values="int")
+    assert len(A.col_ind) // 300 >= 128
+    X1, st1 = gpu_multiply(1.0, A, B, 0.0, path="stack", kernel="plain")
+    assert st1["n_row_panels"] == 1
+    b.bsmm_set_option("stack_panel", str(st1["n_products"] // 30))
+    try:
+        X2, st2 = gpu_multiply(1.0, A, B, 0.0, path="stack", kernel="plain")
+    finally:
+        b.bsmm_set_option("stack_panel", "1073741824")
+    assert st2["n_row_panels"] >= 30
+    check_against_oracle(X2, X1, 0.0)
+    check_against_oracle(X2, orc.multiply(1.0, A, B, 0.0), 0.0)
+
+
 def test_run_to_run_deterministic():
     A, B = banded_uneven(seed=6, occupancy=0.3, target=800)
     X1, _ = gpu_multiply(1.0, A, B, 0.0)
