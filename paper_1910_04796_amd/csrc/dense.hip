@@ -37,11 +37,11 @@ template <> struct Vec2<float> { typedef float __attribute__((ext_vector_type(2)
 constexpr int BM = 128, BN = 128;
 constexpr int kGroupM = 8;
 
-// Merge: one wave per block (block row found by binary search in the row
-// pointer), copying the column-major block into the column-major panel
+// Merge of blocks of 64 elements or more: one wave per block (block row
+// found by binary search in the row pointer), copying the column-major block into the column-major panel
 // (ld = panel rows); consecutive lanes write consecutive rows of a column.
 template <class T>
-__global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const int32_t *rbs,
+__global__ __launch_bounds__(256) void k_merge_block(int32_t nbr, int64_t nnzb, const int32_t *rbs,
                                                const int32_t *cbs, const int64_t *row_off,
                                                const int64_t *col_off, const int64_t *rp,
                                                const int32_t *ci, const int64_t *blk_off,
@@ -73,6 +73,74 @@ __global__ __launch_bounds__(256) void k_merge(int32_t nbr, int64_t nnzb, const 
             for (int64_t e = lane_id(); e < len; e += kWave)
                 panel[(c0 + e / m) * ld + r0 + e % m] = src[e];
         }
+    }
+}
+
+// Merge of blocks of fewer than 64 elements (where one wave per block would
+// leave most lanes idle): one wave per chunk of 64 consecutive blocks.
+// Lane l takes block
+// p0 + l (its block row by binary search in the row pointer, all lanes at
+// once), and a running sum of the block lengths over the wave lays the
+// chunk's elements out in one flat range; the wave walks that range 64
+// elements at a time, each lane stepping forward through the 64 running
+// sums in LDS to its block, and copies from the column-major block into
+// the column-major panel (ld = panel rows).
+constexpr int kMergeWaves = 4;
+template <class T>
+__global__ __launch_bounds__(kMergeWaves * kWave) void k_merge_chunk(int32_t nbr, int64_t nnzb, const int32_t *rbs,
+                                                              const int32_t *cbs, const int64_t *row_off,
+                                                              const int64_t *col_off, const int64_t *rp,
+                                                              const int32_t *ci, const int64_t *blk_off,
+                                                              const T *data, T *panel, int64_t ld) {
+    __shared__ int64_t s_end[kMergeWaves][kWave], s_src[kMergeWaves][kWave], s_dst[kMergeWaves][kWave];
+    __shared__ int32_t s_m[kMergeWaves][kWave];
+    const int w = wave_id(), l = lane_id();
+    const int64_t step = (int64_t)gridDim.x * kMergeWaves * kWave;
+    for (int64_t p0 = ((int64_t)blockIdx.x * kMergeWaves + w) * kWave; p0 < nnzb; p0 += step) {
+        const int64_t p = p0 + l;
+        int64_t len = 0, src = 0, dst = 0;
+        int m = 1;
+        if (p < nnzb) {
+            int32_t lo = 0, hi = nbr;  // row = last lo with rp[lo] <= p
+            while (hi - lo > 1) {
+                const int32_t mid = (lo + hi) >> 1;
+                if (rp[mid] <= p) lo = mid;
+                else hi = mid;
+            }
+            m = rbs[lo];
+            const int32_t j = ci[p];
+            len = (int64_t)m * cbs[j];
+            src = blk_off[p];
+            dst = col_off[j] * ld + row_off[lo];
+        }
+        int64_t end = len;  // inclusive running sum over the wave
+        for (int d = 1; d < kWave; d <<= 1) {
+            const int64_t v = __shfl_up(end, d, kWave);
+            if (l >= d) end += v;
+        }
+        s_end[w][l] = end;
+        s_src[w][l] = src;
+        s_dst[w][l] = dst;
+        s_m[w][l] = m;
+        wave_lds_sync();
+        const int64_t total = __shfl(end, kWave - 1, kWave);
+        int b = 0;  // first block whose running sum exceeds e (e only grows)
+        for (int64_t e = l; e < total; e += kWave) {
+            while (s_end[w][b] <= e) ++b;
+            const int64_t off = e - (b ? s_end[w][b - 1] : 0);
+            const int mb = s_m[w][b];
+            int64_t jj, ii;
+            if (off < (1 << 20) && mb < 4096) {
+                int r;
+                jj = divmod_small((int)off, mb, 1.0f / (float)mb, &r);
+                ii = r;
+            } else {
+                jj = off / mb;
+                ii = off - jj * mb;
+            }
+            panel[s_dst[w][b] + jj * ld + ii] = data[s_src[w][b] + off];
+        }
+        wave_lds_sync();  // every lane has read the chunk before it is replaced
     }
 }
 
@@ -316,6 +384,23 @@ int cu_count() {
 
 namespace {
 
+// Merges M's blocks into a column-major panel (ld = panel rows): blocks of
+// fewer than 64 elements in chunks of 64 blocks per wave, larger blocks one
+// wave per block.
+template <class T>
+int merge_panel(const bsmm_matrix_s *M, T *panel, int64_t ld, const char *what, hipStream_t s) {
+    if ((int64_t)M->max_rbs * M->max_cbs < kWave)
+        hipLaunchKernelGGL(k_merge_chunk<T>, dim3(grid_of(M->nnzb, kMergeWaves * kWave)),
+                           dim3(kMergeWaves * kWave), 0, s, M->nbr, M->nnzb, M->d_rbs(), M->d_cbs(),
+                           M->d_row_off(), M->d_col_off(), M->d_row_ptr(), M->d_col_ind(), M->d_blk_off(),
+                           (const T *)M->d_raw(), panel, ld);
+    else
+        hipLaunchKernelGGL(k_merge_block<T>, dim3(grid_of(M->nnzb, 4)), dim3(256), 0, s, M->nbr, M->nnzb,
+                           M->d_rbs(), M->d_cbs(), M->d_row_off(), M->d_col_off(), M->d_row_ptr(),
+                           M->d_col_ind(), M->d_blk_off(), (const T *)M->d_raw(), panel, ld);
+    return launch_check(what);
+}
+
 template <class T>
 int dense_multiply_t(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix_s *C,
                      double alpha, double beta, hipStream_t s) {
@@ -335,20 +420,8 @@ int dense_multiply_t(const bsmm_matrix_s *A, const bsmm_matrix_s *B, bsmm_matrix
     // Panels need zeros where blocks are absent and in the padding.
     if (!A->full() || Mp != M || Kp != K) BSMM_TRY(fill_zero_bytes(ap.p, sizeof(T) * Mp * Kp, s));
     if (!B->full() || Kp != K || Np != N) BSMM_TRY(fill_zero_bytes(bp.p, sizeof(T) * Kp * Np, s));
-    if (A->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge<T>, dim3(grid_of(A->nnzb, 4)), dim3(256), 0, s, A->nbr, A->nnzb,
-                           A->d_rbs(), A->d_cbs(),
-                           A->d_row_off(), A->d_col_off(), A->d_row_ptr(), A->d_col_ind(),
-                           A->d_blk_off(), (const T *)A->d_raw(), ap.as<T>(), Mp);
-        BSMM_TRY(launch_check("merge_A"));
-    }
-    if (B->nnzb > 0) {
-        hipLaunchKernelGGL(k_merge<T>, dim3(grid_of(B->nnzb, 4)), dim3(256), 0, s, B->nbr, B->nnzb,
-                           B->d_rbs(), B->d_cbs(),
-                           B->d_row_off(), B->d_col_off(), B->d_row_ptr(), B->d_col_ind(),
-                           B->d_blk_off(), (const T *)B->d_raw(), bp.as<T>(), Kp);
-        BSMM_TRY(launch_check("merge_B"));
-    }
+    if (A->nnzb > 0) BSMM_TRY(merge_panel<T>(A, ap.as<T>(), Mp, "merge_A", s));
+    if (B->nnzb > 0) BSMM_TRY(merge_panel<T>(B, bp.as<T>(), Kp, "merge_B", s));
     const int32_t *d_cmap = nullptr;
     if (!C->full()) {
         const int64_t cells = (int64_t)C->nbr * C->nbc;

@@ -110,6 +110,25 @@ def test_dense_path_small(n, bs):
         check_against_oracle(X, R, TOL)
 
 
+@pytest.mark.parametrize("occ", [1.0, 0.6])
+def test_dense_path_small_blocks(occ):
+    """Blocks of fewer than 64 elements are merged 64 blocks per wave:
+    uneven sizes up to 7 x 7, a ragged last chunk of blocks, and a partly
+    occupied pattern (zero-filled gaps in the panels); integer entries give
+    the exact result."""
+    rng = rng_of(88)
+    s = np.array([1, 2, 3, 5, 7], np.int32)
+    rbs, kbs, cbs = (rng.choice(s, size=x) for x in (37, 101, 23))
+    A = make_matrix(rng, rbs, kbs, occ, values="int")
+    B = make_matrix(rng, kbs, cbs, occ, values="int")
+    Cin = make_matrix(rng, rbs, cbs, 1.0, values="int")
+    assert len(B.col_ind) % 64 != 0
+    R = orc.multiply(2.0, A, B, -1.0, Cin)
+    X, st = gpu_multiply(2.0, A, B, -1.0, Cin, path="dense")
+    assert st["path"] == 2
+    check_against_oracle(X, R, 0.0)
+
+
 @pytest.mark.parametrize("kb", ["16", "32"])
 def test_dense_tall_skinny_split_k(kb):
     """Few output tiles and a long k (the paper's tall-and-skinny shape, in
