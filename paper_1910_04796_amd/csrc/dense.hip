@@ -38,14 +38,15 @@ constexpr int BM = 128, BN = 128;
 constexpr int kGroupM = 8;
 
 // Merge of blocks of 64 elements or more: one wave per block (block row
-// found by binary search in the row pointer), copying the column-major block into the column-major panel
-// (ld = panel rows); consecutive lanes write consecutive rows of a column.
+// found by binary search in the row pointer), copying the column-major
+// block into the column-major panel (ld = panel rows); consecutive lanes
+// write consecutive rows of a column.
 template <class T>
 __global__ __launch_bounds__(256) void k_merge_block(int32_t nbr, int64_t nnzb, const int32_t *rbs,
-                                               const int32_t *cbs, const int64_t *row_off,
-                                               const int64_t *col_off, const int64_t *rp,
-                                               const int32_t *ci, const int64_t *blk_off,
-                                               const T *data, T *panel, int64_t ld) {
+                                                     const int32_t *cbs, const int64_t *row_off,
+                                                     const int64_t *col_off, const int64_t *rp,
+                                                     const int32_t *ci, const int64_t *blk_off,
+                                                     const T *data, T *panel, int64_t ld) {
     const int64_t waves = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t p = (int64_t)blockIdx.x * (blockDim.x / kWave) + wave_id(); p < nnzb; p += waves) {
         int32_t lo = 0, hi = nbr;  // row = last lo with rp[lo] <= p
@@ -76,22 +77,20 @@ __global__ __launch_bounds__(256) void k_merge_block(int32_t nbr, int64_t nnzb, 
     }
 }
 
-// Merge of blocks of fewer than 64 elements (where one wave per block would
-// leave most lanes idle): one wave per chunk of 64 consecutive blocks.
-// Lane l takes block
-// p0 + l (its block row by binary search in the row pointer, all lanes at
-// once), and a running sum of the block lengths over the wave lays the
-// chunk's elements out in one flat range; the wave walks that range 64
-// elements at a time, each lane stepping forward through the 64 running
-// sums in LDS to its block, and copies from the column-major block into
-// the column-major panel (ld = panel rows).
+// Merge of blocks of fewer than 64 elements, where one wave per block would
+// leave most lanes idle: one wave per chunk of 64 consecutive blocks.  Lane
+// l takes block p0 + l (its block row by binary search in the row pointer,
+// all lanes at once), and a running sum of the block lengths over the wave
+// lays the chunk's elements out in one flat range; the wave walks that
+// range 64 elements at a time, each lane stepping forward through the 64
+// running sums in LDS to its block, and copies from the column-major block
+// into the column-major panel (ld = panel rows).
 constexpr int kMergeWaves = 4;
 template <class T>
-__global__ __launch_bounds__(kMergeWaves * kWave) void k_merge_chunk(int32_t nbr, int64_t nnzb, const int32_t *rbs,
-                                                              const int32_t *cbs, const int64_t *row_off,
-                                                              const int64_t *col_off, const int64_t *rp,
-                                                              const int32_t *ci, const int64_t *blk_off,
-                                                              const T *data, T *panel, int64_t ld) {
+__global__ __launch_bounds__(kMergeWaves * kWave) void k_merge_chunk(
+    int32_t nbr, int64_t nnzb, const int32_t *rbs, const int32_t *cbs, const int64_t *row_off,
+    const int64_t *col_off, const int64_t *rp, const int32_t *ci, const int64_t *blk_off, const T *data,
+    T *panel, int64_t ld) {
     __shared__ int64_t s_end[kMergeWaves][kWave], s_src[kMergeWaves][kWave], s_dst[kMergeWaves][kWave];
     __shared__ int32_t s_m[kMergeWaves][kWave];
     const int w = wave_id(), l = lane_id();
