@@ -270,9 +270,11 @@ int fill_value(double *p, int64_t n, double v, hipStream_t s);
 // ---------------------------------------------------------------- stacks
 // A product entry keeps A's element offset in 48 bits and k in 16 bits.
 constexpr int kMaxStackK = 0xFFFF;
-// Block columns of C the count and fill phases map in LDS (64 KB); wider C
-// rows are searched in global memory instead.
+// Block columns of C the count and fill phases map in LDS (64 KB) at once;
+// wider C rows are mapped in windows of kStackWin block columns, each B
+// block row's share of every window found once per multiply.
 constexpr int kMaxStackCols = 8192;
+constexpr int kStackWin = 4096;
 // Product stacks of C += A*B, grouped by shape class (m, n).
 struct Stacks {
     int64_t n_runs = 0, n_prod = 0;
@@ -296,6 +298,8 @@ struct Stacks {
     bool a_t_fresh = false;           // a_t holds this multiply's A (later row panels reuse it)
     int kparts = 1;                   // parts per A block row in count and fill
     DevBuf pcount;                    // int64[C.nnzb * kparts]: first position of each part (kparts > 1)
+    int nwin = 0;                     // column windows of a C wider than kMaxStackCols (else 0)
+    DevBuf b_split;                   // int64[B.nbr * (nwin + 1)]: first entry of each B row in each window
     DevBuf sched;                     // uint64[n_sched]: scheduled runs (run << 16 | m << 8 | n)
     int64_t n_sched = 0;
     DevBuf sched_next;                // uint64 run counter of the dynamic schedule

@@ -91,40 +91,86 @@ __global__ __launch_bounds__(256) void k_stack_count(int32_t nbr, int32_t nbc, c
     }
 }
 
-// Position of block column j in C's row [lo, hi) (sorted), or -1.
-__device__ __forceinline__ int64_t find_col(const int32_t *ci, int64_t lo, int64_t hi, int32_t j) {
-    const int64_t end = hi;
+// First position in [lo, hi) of the sorted column indices ci whose column
+// is at least j (hi if none).
+__device__ __forceinline__ int64_t lower_col(const int32_t *ci, int64_t lo, int64_t hi, int64_t j) {
     while (lo < hi) {
         const int64_t mid = lo + (hi - lo) / 2;
-        if (ci[mid] < j) lo = mid + 1;
+        if ((int64_t)ci[mid] < j) lo = mid + 1;
         else hi = mid;
     }
-    return lo < end && ci[lo] == j ? lo : -1;
+    return lo;
 }
 
-// k_stack_count for C with more block columns than the LDS column map
-// holds: each product's C block is found by binary search in the row's
-// column indices and counted with a global atomic (cnt: c_count, or pcount
-// when rows are split into parts; zeroed before the launch).
-__global__ __launch_bounds__(256) void k_stack_count_wide(int32_t nbr, const int64_t *a_rp,
-                                                          const int32_t *a_ci, const int64_t *b_rp,
-                                                          const int32_t *b_ci, const int64_t *c_rp,
-                                                          const int32_t *c_ci, int64_t *cnt,
-                                                          int32_t *c_row, int32_t *missing, int P) {
+// For C wider than the LDS map: split[k * (nwin + 1) + w] = first entry of
+// B block row k whose block column is at least w * kStackWin (w = 0..nwin).
+__global__ __launch_bounds__(256) void k_window_splits(int32_t nbk, int nwin, const int64_t *b_rp,
+                                                       const int32_t *b_ci, int64_t *split) {
+    const int64_t total = (int64_t)nbk * (nwin + 1);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total;
+         t += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t k = (int32_t)(t / (nwin + 1));
+        const int w = (int)(t - (int64_t)k * (nwin + 1));
+        split[t] = lower_col(b_ci, b_rp[k], b_rp[k + 1], (int64_t)w * kStackWin);
+    }
+}
+
+// The slots of C block row [p0, p1) in column window [w0, w0 + kStackWin),
+// found by the first thread and shared through LDS (a barrier follows).
+__device__ __forceinline__ void window_slots(const int32_t *c_ci, int64_t p0, int64_t p1, int32_t w0,
+                                             int64_t *s_cs) {
+    if (threadIdx.x == 0) {
+        s_cs[0] = lower_col(c_ci, p0, p1, w0);
+        s_cs[1] = lower_col(c_ci, s_cs[0], p1, (int64_t)w0 + kStackWin);
+    }
+}
+
+// k_stack_count for C with more block columns than the LDS map holds: the
+// row is counted window by window, each window's columns mapped in LDS and
+// each B row read only over its share of the window (split).
+__global__ __launch_bounds__(256) void k_stack_count_win(int32_t nbr, int nwin, const int64_t *a_rp,
+                                                         const int32_t *a_ci, const int64_t *split,
+                                                         const int32_t *b_ci, const int64_t *c_rp,
+                                                         const int32_t *c_ci, int64_t *c_count,
+                                                         int32_t *c_row, int32_t *missing, int P,
+                                                         int64_t *pcount) {
+    __shared__ int32_t map[kStackWin];
+    __shared__ int32_t cnt[kStackWin];
+    __shared__ int64_t s_cs[2];
     const int part = blockIdx.y;
     const int nw = blockDim.x / kWave;
     for (int32_t row = blockIdx.x; row < nbr; row += gridDim.x) {
         const int64_t p0 = c_rp[row], p1 = c_rp[row + 1];
-        for (int64_t p = p0 + threadIdx.x; p < p1; p += blockDim.x) c_row[p] = row;
+        for (int64_t c = p0 + threadIdx.x; c < p1; c += blockDim.x) c_row[c] = row;  // every part alike
         int64_t pa0, pa1;
         a_part(a_rp, row, part, P, &pa0, &pa1);
-        for (int64_t pa = pa0 + wave_id(); pa < pa1; pa += nw) {
-            const int32_t kb = a_ci[pa];
-            for (int64_t q = b_rp[kb] + lane_id(); q < b_rp[kb + 1]; q += kWave) {
-                const int64_t c = find_col(c_ci, p0, p1, b_ci[q]);
-                if (c >= 0) atomicAdd((unsigned long long *)&cnt[P == 1 ? c : c * P + part], 1ull);
-                else if (missing) *missing = 1;
+        for (int w = 0; w < nwin; ++w) {
+            const int32_t w0 = w * kStackWin;
+            window_slots(c_ci, p0, p1, w0, s_cs);
+            for (int j = threadIdx.x; j < kStackWin; j += blockDim.x) map[j] = -1;
+            __syncthreads();
+            const int64_t cs0 = s_cs[0];
+            const int32_t ns = (int32_t)(s_cs[1] - cs0);
+            for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+                map[c_ci[cs0 + s] - w0] = s;
+                cnt[s] = 0;
             }
+            __syncthreads();
+            for (int64_t pa = pa0 + wave_id(); pa < pa1; pa += nw) {
+                const int64_t *sp = split + (int64_t)a_ci[pa] * (nwin + 1) + w;
+                const int64_t q1 = sp[1];
+                for (int64_t q = sp[0] + lane_id(); q < q1; q += kWave) {
+                    const int32_t s = map[b_ci[q] - w0];
+                    if (s >= 0) atomicAdd(&cnt[s], 1);
+                    else if (missing) *missing = 1;
+                }
+            }
+            __syncthreads();
+            for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+                if (P == 1) c_count[cs0 + s] = cnt[s];
+                else pcount[(cs0 + s) * P + part] = cnt[s];
+            }
+            __syncthreads();  // map, counts and the window's slot range are reused
         }
     }
 }
@@ -248,38 +294,59 @@ __global__ void k_gather_class_begin(const int64_t *hoff, const int64_t *hoff_p,
     }
 }
 
-// k_stack_fill for C with more block columns than the LDS map holds: the C
-// block by binary search, each (block, part)'s next position in a global
-// cursor cur[(c - c0) P + part] (zeroed before the launch).  Within one K a
-// block is hit at most once per part, and a barrier separates consecutive
-// K, so the cursors need no atomics and the runs stay in K order.
-__global__ __launch_bounds__(256) void k_stack_fill_wide(int32_t row0, int32_t row1, int P,
-                                                         const int64_t *poff, int64_t c0,
-                                                         const int64_t *a_rp, const int32_t *a_ci,
-                                                         const int64_t *a_off, const int64_t *b_rp,
-                                                         const int32_t *b_ci, const int64_t *b_off,
-                                                         const int32_t *kbs, const int64_t *c_rp,
-                                                         const int32_t *c_ci, const int64_t *run_of_c,
-                                                         const int64_t *run_ptr, int64_t *cur,
-                                                         ulonglong2 *prods) {
+// k_stack_fill for C with more block columns than the LDS map holds: the
+// row is filled window by window (as in k_stack_count_win); each window's
+// slots keep their next write position in LDS.  Within one K a slot is hit
+// at most once, and a barrier separates consecutive K, so the runs stay in
+// K order with no atomics.
+__global__ __launch_bounds__(256) void k_stack_fill_win(int32_t row0, int32_t row1, int P,
+                                                        const int64_t *poff, int nwin,
+                                                        const int64_t *a_rp, const int32_t *a_ci,
+                                                        const int64_t *a_off, const int64_t *split,
+                                                        const int32_t *b_ci, const int64_t *b_off,
+                                                        const int32_t *kbs, const int64_t *c_rp,
+                                                        const int32_t *c_ci, const int64_t *run_of_c,
+                                                        const int64_t *run_ptr, ulonglong2 *prods) {
+    __shared__ int32_t map[kStackWin];
+    __shared__ int64_t next[kStackWin];
+    __shared__ int64_t s_cs[2];
     const int part = blockIdx.y;
     for (int32_t row = row0 + (int32_t)blockIdx.x; row < row1; row += gridDim.x) {
         const int64_t p0 = c_rp[row], p1 = c_rp[row + 1];
         int64_t pa0, pa1;
         a_part(a_rp, row, part, P, &pa0, &pa1);
-        for (int64_t pa = pa0; pa < pa1; ++pa) {
-            const int32_t kb = a_ci[pa];
-            const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
-            for (int64_t q = b_rp[kb] + threadIdx.x; q < b_rp[kb + 1]; q += blockDim.x) {
-                const int64_t c = find_col(c_ci, p0, p1, b_ci[q]);
-                if (c < 0) continue;
-                const int64_t k = (c - c0) * P + part;
+        for (int w = 0; w < nwin; ++w) {
+            const int32_t w0 = w * kStackWin;
+            window_slots(c_ci, p0, p1, w0, s_cs);
+            for (int j = threadIdx.x; j < kStackWin; j += blockDim.x) map[j] = -1;
+            __syncthreads();
+            const int64_t cs0 = s_cs[0];
+            const int32_t ns = (int32_t)(s_cs[1] - cs0);
+            for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+                const int64_t c = cs0 + s;
+                map[c_ci[c] - w0] = s;
                 const int64_t first = P == 1 ? 0 : poff[c * P + part];
-                const int64_t pos = run_ptr[run_of_c[c]] + first + cur[k];
-                cur[k] += 1;
-                prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
+                const int64_t r = run_of_c[c];
+                next[s] = r >= 0 ? run_ptr[r] + first : 0;  // r < 0: the slot receives no product
             }
             __syncthreads();
+            if (ns > 0) {  // a window without slots receives no product
+                for (int64_t pa = pa0; pa < pa1; ++pa) {
+                    const int32_t kb = a_ci[pa];
+                    const uint64_t aw = (uint64_t)a_off[pa] | ((uint64_t)kbs[kb] << 48);
+                    const int64_t *sp = split + (int64_t)kb * (nwin + 1) + w;
+                    const int64_t q1 = sp[1];
+                    for (int64_t q = sp[0] + threadIdx.x; q < q1; q += blockDim.x) {
+                        const int32_t s = map[b_ci[q] - w0];
+                        if (s < 0) continue;
+                        const int64_t pos = next[s];
+                        next[s] = pos + 1;
+                        prods[pos] = make_ulonglong2(aw, (uint64_t)b_off[q]);
+                    }
+                    __syncthreads();
+                }
+            }
+            __syncthreads();  // map, positions and the window's slot range are reused
         }
     }
 }
@@ -481,13 +548,19 @@ int stack_count(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matri
     BSMM_HIP(hipMemcpyAsync(st.d_csi.p, csi.data(), sizeof(int32_t) * nbc, hipMemcpyHostToDevice, s));
     hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(1), 0, s, st.missing.as<int32_t>());
     BSMM_TRY(launch_check("zero_i32"));
+    st.nwin = 0;
     if (nbc > kMaxStackCols) {
-        int64_t *cnt = st.kparts > 1 ? st.pcount.as<int64_t>() : st.c_count.as<int64_t>();
-        BSMM_TRY(fill_zero((double *)cnt, nnzb * st.kparts, s));
-        hipLaunchKernelGGL(k_stack_count_wide, dim3(grid_rows(nbr), st.kparts), dim3(256), 0, s, nbr,
-                           A->d_row_ptr(), A->d_col_ind(), B->d_row_ptr(), B->d_col_ind(),
-                           C->d_row_ptr(), C->d_col_ind(), cnt, st.c_row.as<int32_t>(),
-                           st.screened ? nullptr : st.missing.as<int32_t>(), st.kparts);
+        st.nwin = (int)ceil_div(nbc, kStackWin);
+        const int64_t nsplit = (int64_t)B->nbr * (st.nwin + 1);
+        BSMM_TRY(st.b_split.reserve(sizeof(int64_t) * nsplit, s));
+        hipLaunchKernelGGL(k_window_splits, dim3(grid_of(nsplit, 256)), dim3(256), 0, s, B->nbr, st.nwin,
+                           B->d_row_ptr(), B->d_col_ind(), st.b_split.as<int64_t>());
+        BSMM_TRY(launch_check("window_splits"));
+        hipLaunchKernelGGL(k_stack_count_win, dim3(grid_rows(nbr), st.kparts), dim3(256), 0, s, nbr, st.nwin,
+                           A->d_row_ptr(), A->d_col_ind(), (const int64_t *)st.b_split.as<int64_t>(),
+                           B->d_col_ind(), C->d_row_ptr(), C->d_col_ind(), st.c_count.as<int64_t>(),
+                           st.c_row.as<int32_t>(), st.screened ? nullptr : st.missing.as<int32_t>(), st.kparts,
+                           st.pcount.as<int64_t>());
     } else {
         const size_t map_lds = sizeof(int32_t) * 2 * (size_t)nbc;
         hipLaunchKernelGGL(k_stack_count, dim3(grid_rows(nbr), st.kparts), dim3(256), map_lds, s, nbr,
@@ -635,17 +708,13 @@ int stack_rows(const bsmm_matrix_s *A, const bsmm_matrix_s *B, const bsmm_matrix
     BSMM_TRY(scan_exclusive_i64(run_cnt.as<int64_t>(), st.run_ptr.as<int64_t>(), st.n_runs, s));
     if (st.n_prod > 0 && nbc > kMaxStackCols) {
         BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * st.n_prod, s));
-        DevBuf cur;
-        BSMM_TRY(cur.reserve(sizeof(int64_t) * nblk * st.kparts, s));
-        BSMM_TRY(fill_zero(cur.as<double>(), nblk * st.kparts, s));
-        hipLaunchKernelGGL(k_stack_fill_wide, dim3(grid_rows(r1 - r0), st.kparts), dim3(256), 0, s, r0, r1,
-                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), c0, A->d_row_ptr(),
-                           A->d_col_ind(), A->d_blk_off(), B->d_row_ptr(), B->d_col_ind(),
-                           B->d_blk_off(), B->d_rbs(), C->d_row_ptr(), C->d_col_ind(),
+        hipLaunchKernelGGL(k_stack_fill_win, dim3(grid_rows(r1 - r0), st.kparts), dim3(256), 0, s, r0, r1,
+                           st.kparts, (const int64_t *)st.pcount.as<int64_t>(), st.nwin, A->d_row_ptr(),
+                           A->d_col_ind(), A->d_blk_off(), (const int64_t *)st.b_split.as<int64_t>(),
+                           B->d_col_ind(), B->d_blk_off(), B->d_rbs(), C->d_row_ptr(), C->d_col_ind(),
                            (const int64_t *)st.run_of_c.as<int64_t>(),
-                           (const int64_t *)st.run_ptr.as<int64_t>(), cur.as<int64_t>(),
-                           st.prods.as<ulonglong2>());
-        BSMM_TRY(launch_check("stack_fill_wide"));
+                           (const int64_t *)st.run_ptr.as<int64_t>(), st.prods.as<ulonglong2>());
+        BSMM_TRY(launch_check("stack_fill_win"));
     } else if (st.n_prod > 0) {
         BSMM_TRY(st.prods.reserve(sizeof(ulonglong2) * st.n_prod, s));
         // LDS: the column map, then per slot a 64-bit next position (rows of

@@ -142,3 +142,38 @@ def test_noalloc_rejects_missing_pattern_and_oversize(counting):
     finally:
         MA.close()
         set_path()
+
+
+def test_noalloc_wide_c(counting):
+    """C wider than the stack builder's LDS map (9,000 block columns, counted
+    and filled in windows): the allocation-free multiply matches
+    bsmm_multiply twice in a row, and a C pattern missing one product block
+    is rejected with EINDEX before C is written."""
+    from synth import BlockCSR
+    b = lib()
+    rng = rng_of(13)
+    s = np.array([1, 2, 3], np.int32)
+    ms, ks, ns = (rng.choice(s, size=x) for x in (40, 60, 9000))
+    A = make_matrix(rng, ms, ks, 0.2)
+    B = make_matrix(rng, ks, ns, 0.01)
+    _compare(A, B, 1.0, 0.5, counting, "stack", "plain")
+    _compare(make_matrix(rng, ms[:10], ks, 0.2), B, 2.0, 0.0, counting, "stack", "plain")
+    MA, MB = b.Matrix.from_blocks(A), b.Matrix.from_blocks(B)
+    try:
+        full = _with_pattern_of(b, MA, MB, A.rbs, B.cbs, rng)
+        rp = np.asarray(full.row_ptr)
+        # drop the first stored block (row_ptr entries past its row shift by one)
+        row0 = int(np.searchsorted(rp, 0, side="right")) - 1
+        size0 = int(ms[row0]) * int(ns[int(full.col_ind[0])])
+        holed = BlockCSR(full.rbs, full.cbs, np.maximum(rp - 1, 0), np.asarray(full.col_ind)[1:],
+                         np.asarray(full.data)[size0:])
+        MC = b.Matrix.from_blocks(holed)
+        before = MC.to_host().data.copy()
+        with pytest.raises(b.BsmmError) as e:
+            b.bsmm_multiply_noalloc(1.0, MA.handle, MB.handle, 1.0, MC.handle)
+        assert e.value.status == b.BSMM_EINDEX
+        assert np.array_equal(MC.to_host().data, before)
+        MC.close()
+    finally:
+        MA.close()
+        MB.close()
