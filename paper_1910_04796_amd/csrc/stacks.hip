@@ -14,7 +14,8 @@
 //
 // Phases (all on the GPU, one workgroup per C block row where a row is the
 // unit):
-//   1. count    products per C block, through an LDS map column -> slot;
+//   1. count    products per C block, through an LDS map column -> slot
+//               (for C wider than the map, in windows of block columns);
 //   2. classify counting sort of the C blocks that receive products by
 //               class, stable in CSR order (per-tile histograms, a scan,
 //               wave-level ranking with ballots);
